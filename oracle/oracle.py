@@ -1,0 +1,178 @@
+"""Python front end of the CPU oracle for Motifs-k.  TEST INFRASTRUCTURE ONLY.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this module.  It loads ``liboracle.so`` (plain C,
+built from ``oracle.c`` with gcc) and adds a second, pure-Python brute-force
+checker for tiny graphs.  Nothing here is shared with the HIP library.
+
+Conventions (Section 3.2 of the paper: the isomorphism key is the adjacency
+matrix of the k-vertex subgraph):
+
+* code of an ordered vertex tuple (s_0..s_{k-1}): bit i(k-1) + j - [j > i]
+  is set iff the arc s_i -> s_j exists;
+* canonical code of a class: the minimum code over all k! relabelings;
+* class id (k <= 5 here): rank of the canonical code among the canonical
+  codes of weakly connected k-vertex digraphs.  The paper numbers classes
+  1..|P_k| without fixing an order; ranking by canonical code is our choice.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import functools
+import itertools
+import os
+import subprocess
+from typing import Dict
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+
+def build(force: bool = True) -> str:
+    """Compile liboracle.so with gcc (plain C, -O2)."""
+    if force or not os.path.exists(_LIB):
+        subprocess.check_call(["gcc", "-O2", "-std=c99", "-Wall", "-shared", "-fPIC",
+                               _SRC, "-o", _LIB])
+    return _LIB
+
+
+@functools.lru_cache(maxsize=None)
+def _lib():
+    if not os.path.exists(_LIB):
+        build()
+    lib = ctypes.CDLL(_LIB)
+    lib.oracle_connected.restype = ctypes.c_int
+    lib.oracle_connected.argtypes = [ctypes.c_int, ctypes.c_uint32]
+    lib.oracle_canon.restype = ctypes.c_uint32
+    lib.oracle_canon.argtypes = [ctypes.c_int, ctypes.c_uint32]
+    lib.oracle_canon_table.restype = ctypes.c_int
+    lib.oracle_canon_table.argtypes = [ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]
+    lib.oracle_count.restype = ctypes.c_int64
+    lib.oracle_count.argtypes = [ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
+                                 ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
+                                 ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]
+    return lib
+
+
+class OracleError(RuntimeError):
+    def __init__(self, code: int):
+        super().__init__("oracle error %d" % code)
+        self.code = code
+
+
+def bit_of(k: int, i: int, j: int) -> int:
+    return i * (k - 1) + j - (1 if j > i else 0)
+
+
+def connected(k: int, code: int) -> bool:
+    return bool(_lib().oracle_connected(k, code))
+
+
+def canon(k: int, code: int) -> int:
+    return int(_lib().oracle_canon(k, code))
+
+
+@functools.lru_cache(maxsize=None)
+def canon_table(k: int):
+    """(canon, conn): canonical code and connectivity of every code, k <= 5."""
+    n = 1 << (k * (k - 1))
+    c = np.empty(n, dtype=np.uint32)
+    ok = np.empty(n, dtype=np.uint8)
+    rc = _lib().oracle_canon_table(k, c.ctypes.data, ok.ctypes.data)
+    if rc != 0:
+        raise OracleError(rc)
+    c.setflags(write=False)
+    ok.setflags(write=False)
+    return c, ok
+
+
+@functools.lru_cache(maxsize=None)
+def class_codes(k: int) -> np.ndarray:
+    """Canonical codes of the weakly connected classes, ascending (k <= 5)."""
+    c, ok = canon_table(k)
+    out = np.unique(c[ok.astype(bool)])
+    out.setflags(write=False)
+    return out
+
+
+def count(row_ptr, col, k: int) -> Dict[int, int]:
+    """H_k as {canonical code: count} (zero classes omitted)."""
+    row_ptr = np.ascontiguousarray(row_ptr, dtype=np.int32)
+    col = np.ascontiguousarray(col, dtype=np.int32)
+    n = len(row_ptr) - 1
+    table = None
+    tptr = None
+    if 3 <= k <= 5:
+        table = canon_table(k)[0]
+        tptr = table.ctypes.data
+    cap = 1 << 16
+    while True:
+        codes = np.zeros(cap, dtype=np.uint32)
+        counts = np.zeros(cap, dtype=np.uint64)
+        total = ctypes.c_uint64(0)
+        rc = _lib().oracle_count(n, row_ptr.ctypes.data, col.ctypes.data if len(col) else None,
+                                 k, tptr, codes.ctypes.data, counts.ctypes.data, cap,
+                                 ctypes.byref(total))
+        if rc == -5:
+            cap *= 4
+            continue
+        if rc < 0:
+            raise OracleError(int(rc))
+        return {int(c): int(v) for c, v in zip(codes[:rc], counts[:rc])}
+
+
+def dense_hist(row_ptr, col, k: int) -> np.ndarray:
+    """H_k as a dense uint64 vector indexed by class id (k <= 5)."""
+    cc = class_codes(k)
+    h = np.zeros(len(cc), dtype=np.uint64)
+    for code, v in count(row_ptr, col, k).items():
+        i = int(np.searchsorted(cc, code))
+        assert i < len(cc) and cc[i] == code
+        h[i] = v
+    return h
+
+
+# --------------------------------------------------------------------------
+# second, independent brute force (tiny graphs only)
+# --------------------------------------------------------------------------
+
+def _py_canon(k: int, a) -> int:
+    best = None
+    for p in itertools.permutations(range(k)):
+        c = 0
+        for i in range(k):
+            for j in range(k):
+                if i != j and a[i][j]:
+                    c |= 1 << bit_of(k, p[i], p[j])
+        if best is None or c < best:
+            best = c
+    return best
+
+
+def brute_force_count(row_ptr, col, k: int) -> Dict[int, int]:
+    """H_k by the definition: every k-subset, kept if weakly connected."""
+    row_ptr = np.asarray(row_ptr)
+    n = len(row_ptr) - 1
+    arcs = set()
+    for u in range(n):
+        for t in range(row_ptr[u], row_ptr[u + 1]):
+            arcs.add((u, int(col[t])))
+    out: Dict[int, int] = {}
+    for sub in itertools.combinations(range(n), k):
+        a = [[(sub[i], sub[j]) in arcs for j in range(k)] for i in range(k)]
+        seen, stack = {0}, [0]
+        while stack:
+            u = stack.pop()
+            for w in range(k):
+                if w not in seen and (a[u][w] or a[w][u]):
+                    seen.add(w)
+                    stack.append(w)
+        if len(seen) != k:
+            continue
+        c = _py_canon(k, a)
+        out[c] = out.get(c, 0) + 1
+    return out
