@@ -1,0 +1,266 @@
+/*
+ * motifs.h -- C ABI of the MI355X Motifs-k library (libmotifs.so).
+ *
+ * Problem Motifs-k (arXiv 1804.09741, Section 1): given a directed graph G
+ * and k, count the connected induced k-vertex subgraphs of G grouped by
+ * isomorphism class; the result is the histogram H_k(G).  This library
+ * solves it for k = 3..6 on one AMD Instinct MI355X (gfx950):
+ *
+ *   - mk_table_*   the code -> class table of Section 3.2 (isomorphism in
+ *                  O(1) by precomputing the class of every adjacency matrix);
+ *   - mk_count*,
+ *     mk_batch_*   enumeration of every connected induced k-set exactly once,
+ *                  its adjacency code, the table lookup and the histogram;
+ *   - mk_server_*  a continuous-batching request server over the same path.
+ *
+ * Conventions used throughout:
+ *
+ *   Graph input.  A simple digraph as out-adjacency CSR: vertices 0..n-1,
+ *   row_ptr[n+1] (row_ptr[0] = 0, non-decreasing), col[row_ptr[n]] with the
+ *   heads of the arcs leaving each vertex, in any order.  m = row_ptr[n]
+ *   counts directed arcs, so a bidirected edge (u,v),(v,u) of Section 2
+ *   counts twice.  Self-loops and repeated arcs are rejected (an adjacency
+ *   code cannot represent them).
+ *
+ *   Connectivity.  Weak: delta(v) = A(v) u B(v) u C(v) ignores direction
+ *   (Section 2).  This is the reading that gives the paper's class counts.
+ *
+ *   Adjacency code.  For an ordered k-tuple (s_0..s_{k-1}) the code has bit
+ *   i*(k-1) + j - [j > i] set iff arc s_i -> s_j exists (row-major adjacency
+ *   matrix without its diagonal; k(k-1) bits).
+ *
+ *   Class id.  0-based rank of the class's canonical code (the minimum code
+ *   over all k! relabelings) among the weakly connected classes.  Id 0 is
+ *   the out-star (code 2^(k-1) - 1), the last id the complete digraph.
+ *   Number of classes: 13, 199, 9364, 1530843 for k = 3..6.  (Section 1
+ *   prints 1,530,842 for k = 6; Burnside's lemma and the paper's own k = 7
+ *   figure fix it at 1,530,843, which is what the table holds.)
+ *   Codes of disconnected digraphs map to MK_INVALID_CLASS.
+ *
+ *   Histogram.  Dense uint64 vector of num_classes counts indexed by class
+ *   id, zeros included.  Counts are exact; results do not depend on thread
+ *   timing.
+ *
+ * Ownership.  Handles are opaque and owned by the library.  Graphs and
+ * batches are freed by their *_free call; class tables belong to the
+ * context that built them and live until mk_table_release or mk_destroy.
+ * Caller arrays are only read during the call that receives them.
+ *
+ * Errors.  Every int-returning call returns MK_OK (0) or a negative MK_E*
+ * status; mk_last_error() then describes the failure (per thread).
+ * Calls on one context are serialised internally (thread-safe, not
+ * concurrent).
+ */
+#ifndef MOTIFS_H
+#define MOTIFS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MK_OK 0
+#define MK_EINVAL (-1)    /* bad argument: NULL pointer, negative size, wrong table */
+#define MK_ERANGE (-2)    /* k outside 3..6, id/code out of range, graph too large */
+#define MK_EGRAPH (-3)    /* input is not a simple digraph CSR */
+#define MK_ENOMEM (-4)    /* device or host allocation failed */
+#define MK_EDEVICE (-5)   /* HIP runtime error or a failed device-side check */
+#define MK_EBUSY (-6)     /* request can never fit the server budget / server stopped */
+#define MK_ETIMEDOUT (-7) /* mk_wait timed out; the request stays pending */
+#define MK_ENOTFOUND (-8) /* unknown or already collected ticket */
+
+#define MK_INVALID_CLASS 0xFFFFFFFFu
+
+/* Largest graph the enumeration accepts: n <= MK_MAX_VERTICES and undirected
+   degree (|delta(v)|) <= MK_MAX_DEGREE.  The paper's graphs have n <= 6175. */
+#define MK_MAX_VERTICES 8192
+#define MK_MAX_DEGREE 4096
+
+typedef struct mk_ctx mk_ctx;
+typedef struct mk_graph mk_graph;
+typedef struct mk_table mk_table;
+typedef struct mk_batch mk_batch;
+typedef struct mk_server mk_server;
+
+/* ---------------------------------------------------------------- context */
+
+/* Open a context on HIP device `device`.  *out receives the handle. */
+int mk_init(int device, mk_ctx **out);
+
+/* Free the context, its class tables and its stream.  Graphs, batches and
+   servers made from it must be freed first. */
+void mk_destroy(mk_ctx *ctx);
+
+/* Number of compute units of the context's device (for reports). */
+int mk_device_info(const mk_ctx *ctx, int32_t *compute_units, int64_t *hbm_bytes);
+
+/* ------------------------------------------------------------------ graph */
+
+/* Validate the simple digraph (n, row_ptr, col) (see "Graph input" above)
+   and copy it to device memory.  The caller keeps its arrays.  Errors:
+   MK_EINVAL for NULL arrays or n < 0, MK_EGRAPH for a non-monotone row_ptr,
+   ids outside [0,n), self-loops or repeated arcs, MK_ERANGE for
+   n > MK_MAX_VERTICES or a vertex whose undirected degree exceeds
+   MK_MAX_DEGREE. */
+int mk_graph_load_csr(mk_ctx *ctx, int32_t n, const int32_t *row_ptr,
+                      const int32_t *col, mk_graph **out);
+
+/* n, m (directed arcs) and the largest undirected degree of a loaded graph;
+   any output pointer may be NULL. */
+int mk_graph_info(const mk_graph *g, int32_t *n, int64_t *m, int32_t *max_degree);
+
+/* Device bytes one count of this graph needs beyond the graph itself
+   (workspace, work units, histogram) for subgraph size k. */
+int mk_graph_footprint(const mk_graph *g, int k, uint64_t *bytes);
+
+void mk_graph_free(mk_graph *g);
+
+/* ------------------------------------------------------------ class table */
+
+/* The code -> class table for k (Section 3.2): 2^(k(k-1)) uint32 entries in
+   device memory (k = 6: 2^30 entries, 4 GiB), built on the GPU by taking
+   the minimum code over all k! vertex relabelings of every code.  Built
+   once per context and k, then cached; later calls return the same handle.
+   MK_ERANGE for k outside 3..6. */
+int mk_table_build(mk_ctx *ctx, int k, mk_table **out);
+
+/* Drop the cached table for k (frees its device memory).  Handles obtained
+   earlier become invalid. */
+int mk_table_release(mk_ctx *ctx, int k);
+
+/* k, number of classes, number of entries (2^(k(k-1))) and the GPU build
+   time in milliseconds; any output pointer may be NULL. */
+int mk_table_info(const mk_table *t, int32_t *k, uint32_t *num_classes,
+                  uint64_t *num_entries, double *build_ms);
+
+/* Canonical code of class `id` (MK_ERANGE if id >= num_classes). */
+int mk_table_class_code(const mk_table *t, uint32_t id, uint32_t *canon_code);
+
+/* All canonical codes in id order (ascending) into codes[capacity];
+   MK_ERANGE if capacity < num_classes. */
+int mk_table_class_codes(const mk_table *t, uint32_t *codes, uint32_t capacity);
+
+/* Class id of one code (MK_INVALID_CLASS if the digraph is disconnected);
+   MK_ERANGE if code >= 2^(k(k-1)). */
+int mk_table_lookup(const mk_table *t, uint32_t code, uint32_t *id);
+
+/* Copy entries [first, first+count) of the table to host memory out[]. */
+int mk_table_read(const mk_table *t, uint64_t first, uint64_t count, uint32_t *out);
+
+/* ------------------------------------------------------------------ count */
+
+/* H_k(G) for one graph (k = the table's k).  hist: host array of
+   num_classes uint64 written densely; *total (may be NULL) receives the
+   number of connected induced k-subgraphs (the sum of hist).  A graph with
+   n < k gives all zeros.  Blocks until done. */
+int mk_count(mk_ctx *ctx, const mk_graph *g, const mk_table *t, uint64_t *hist,
+             uint64_t *total);
+
+/* H_k of ng graphs in one persistent launch.  hist: host array of
+   ng * num_classes uint64, graph i at hist + i*num_classes; totals (may be
+   NULL): ng uint64.  Equal, graph by graph, to mk_count.  Blocks. */
+int mk_count_batch(mk_ctx *ctx, const mk_graph *const *gs, int32_t ng,
+                   const mk_table *t, uint64_t *hist, uint64_t *totals);
+
+/* ----------------------------------------------------------- prepared batch */
+
+/* Tuning knobs of a batch.  Zero fields take the library defaults. */
+typedef struct mk_batch_opts {
+    uint64_t split_threshold; /* estimated subgraphs per work unit before a
+                                 (root, first neighbour) pair is split */
+    int32_t waves_per_cu;     /* resident enumeration waves per compute unit */
+    int32_t use_graph;        /* 1: replay a captured hipGraph (default),
+                                 -1: plain stream launches */
+} mk_batch_opts;
+
+/* Prepare a batch: device workspace for the typed adjacency, the work
+   units and the histograms of ng graphs (counted with table t), sized by
+   running the planner once.  The graphs and the table must outlive it. */
+int mk_batch_create(mk_ctx *ctx, const mk_graph *const *gs, int32_t ng,
+                    const mk_table *t, const mk_batch_opts *opts, mk_batch **out);
+
+/* Enqueue one full pass of the path on `stream` (a hipStream_t; NULL = the
+   context's stream): typed adjacency, work-unit plan, enumeration, codes,
+   lookups and histograms.  Asynchronous.  d_hist: device array of
+   ng * num_classes uint64 that receives the histograms (overwritten), or
+   NULL to use the batch's own buffer.  The first run on a given d_hist
+   captures the sequence as a hipGraph; later runs replay it. */
+int mk_batch_run(mk_batch *b, uint64_t *d_hist, void *stream);
+
+/* Wait for the batch's last run, check its device-side status and copy the
+   histograms (ng * num_classes) and per-graph totals to host memory (either
+   pointer may be NULL). */
+int mk_batch_read(mk_batch *b, uint64_t *hist, uint64_t *totals);
+
+/* Statistics of the last plan: number of work units, of split pairs, the
+   enumeration grid (workgroups of one 64-lane wave) and its LDS bytes per
+   workgroup. */
+typedef struct mk_batch_stats {
+    uint64_t units;
+    uint64_t split_pairs;
+    int32_t grid;
+    int32_t lds_bytes;
+    int32_t k;
+    int32_t ng;
+} mk_batch_stats;
+int mk_batch_stats_get(const mk_batch *b, mk_batch_stats *out);
+
+/* GPU time of the batch's last run, from HIP events recorded on the run's
+   stream: the whole pass and the enumeration kernel alone (milliseconds).
+   Waits for the run to finish. */
+int mk_batch_timing(mk_batch *b, double *pass_ms, double *enum_ms);
+
+void mk_batch_free(mk_batch *b);
+
+/* ----------------------------------------------------------------- server */
+
+/* Continuous-batching server.  Requests (graph, k) are admitted while their
+   device footprint fits `hbm_budget_bytes` and fewer than `max_slots` are
+   in flight; admitted requests are planned into work units and run in
+   bounded slices ("ticks") of at most `tick_units` units, so requests that
+   arrive while others run join the next tick and share the device with
+   them.  Each request's histogram is identical to mk_count's. */
+typedef struct mk_server_opts {
+    uint64_t hbm_budget_bytes; /* 0: 8 GiB */
+    int32_t max_slots;         /* 0: 64 */
+    int32_t tick_units;        /* 0: library default */
+} mk_server_opts;
+
+/* Per-request timing, microseconds since the server started. */
+typedef struct mk_request_times {
+    double submit_us;
+    double admit_us;
+    double done_us;
+} mk_request_times;
+
+/* Start the server (a host thread and its own stream).  Class tables for
+   the ks it will see are built on first use (or earlier by the caller). */
+int mk_server_start(mk_ctx *ctx, const mk_server_opts *opts, mk_server **out);
+
+/* Queue a request.  The graph must stay loaded until the request is
+   collected by mk_wait.  MK_EBUSY if its footprint can never fit the
+   budget or the server is stopping; MK_ERANGE for k outside 3..6. */
+int mk_submit(mk_server *s, const mk_graph *g, int k, uint64_t *ticket);
+
+/* Wait up to timeout_ms (negative: forever) for request `ticket`, then copy
+   its histogram (capacity must be >= its num_classes) and timings (may be
+   NULL) and forget the request.  MK_ETIMEDOUT leaves it pending. */
+int mk_wait(mk_server *s, uint64_t ticket, uint64_t *hist, uint32_t capacity,
+            int32_t timeout_ms, mk_request_times *times);
+
+/* Stop accepting requests, finish the admitted and queued ones, join the
+   thread and free the server.  Uncollected results are discarded. */
+int mk_server_stop(mk_server *s);
+
+/* ----------------------------------------------------------------- errors */
+
+const char *mk_status_str(int status);
+const char *mk_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MOTIFS_H */

@@ -1,0 +1,444 @@
+// Context, prepared batches and the count calls.
+//
+// A batch holds the device workspace of ng graphs counted with one class
+// table, and runs the whole path as one stream sequence:
+//   reset counters and histograms (fill kernels) -> typed adjacency (Section
+//   2's A/B/C lists) -> work-unit plan -> persistent enumeration kernel
+// with no host synchronisation in between.  The ten small preparation
+// kernels are captured once as a hipGraph and replayed; the enumeration
+// kernel follows as one launch between two HIP events (its timing).  Every
+// graph of the batch shares one queue and one launch; histograms are
+// [ng][num_classes] uint64.
+#include <algorithm>
+#include <cstring>
+
+#include "internal.h"
+
+using namespace mk;
+
+struct mk_batch {
+    mk_ctx *ctx = nullptr;
+    const mk_table *table = nullptr;
+    int k = 0;
+    int ng = 0;
+    std::vector<const mk_graph *> graphs;
+    mk_batch_opts opts{};
+
+    DevGraph *d_graphs = nullptr;
+    uint32_t *d_ws = nullptr;  // bits, urow, uadj
+    uint64_t bits_words = 0;
+    uint32_t *d_slot_cnt = nullptr;
+    uint32_t *d_slot_off = nullptr;
+    uint32_t *d_scan_tmp = nullptr;
+    uint32_t total_slots = 0;
+    int4 *d_units = nullptr;
+    uint32_t unit_cap = 0;
+    uint32_t *d_counters = nullptr;
+    unsigned long long *d_hist_own = nullptr;
+    unsigned long long *hist_last = nullptr;
+
+    int max_n = 0, max_words = 0, seg_cap = 0;
+    int64_t max_nnz = 0;
+    int grid = 0, lds_bytes = 0;
+    uint64_t units = 0, split_pairs = 0;
+
+    hipEvent_t ev[3] = {};  // pass start, enumeration start, enumeration end
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    unsigned long long *exec_hist = nullptr;
+    hipStream_t last_stream = nullptr;
+};
+
+static constexpr uint64_t kDefaultSplit[7] = {0, 0, 1u << 30, 1u << 14, 1u << 15, 1u << 16, 1u << 16};
+
+// ----------------------------------------------------------------- context
+
+extern "C" int mk_init(int device, mk_ctx **out)
+{
+    if (!out) return fail(MK_EINVAL, "mk_init: NULL out");
+    *out = nullptr;
+    int count = 0;
+    MK_HIP(hipGetDeviceCount(&count));
+    if (device < 0 || device >= count)
+        return fail(MK_ERANGE, "device %d not present (%d devices)", device, count);
+    MK_HIP(hipSetDevice(device));
+    hipDeviceProp_t prop;
+    MK_HIP(hipGetDeviceProperties(&prop, device));
+    mk_ctx *c = new mk_ctx();
+    c->device = device;
+    c->num_cus = prop.multiProcessorCount;
+    c->hbm_bytes = (int64_t)prop.totalGlobalMem;
+    c->max_lds = prop.sharedMemPerBlock;
+    hipError_t e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        delete c;
+        return fail(MK_EDEVICE, "hipStreamCreate: %s", hipGetErrorString(e));
+    }
+    *out = c;
+    return MK_OK;
+}
+
+extern "C" void mk_destroy(mk_ctx *ctx)
+{
+    if (!ctx) return;
+    (void)hipSetDevice(ctx->device);
+    (void)hipStreamSynchronize(ctx->stream);
+    for (int k = 0; k < 7; ++k) free_table(ctx->tables[k]);
+    (void)hipStreamDestroy(ctx->stream);
+    delete ctx;
+}
+
+extern "C" int mk_device_info(const mk_ctx *ctx, int32_t *compute_units, int64_t *hbm_bytes)
+{
+    if (!ctx) return fail(MK_EINVAL, "mk_device_info: NULL context");
+    if (compute_units) *compute_units = ctx->num_cus;
+    if (hbm_bytes) *hbm_bytes = ctx->hbm_bytes;
+    return MK_OK;
+}
+
+static uint32_t classes_for_k(int k)
+{
+    static const uint32_t n[7] = {0, 0, 0, 13, 199, 9364, 1530843};
+    return (k >= 3 && k <= 6) ? n[k] : 0;
+}
+
+extern "C" int mk_graph_footprint(const mk_graph *g, int k, uint64_t *bytes)
+{
+    if (!g || !bytes) return fail(MK_EINVAL, "mk_graph_footprint: NULL argument");
+    if (k < 3 || k > 6) return fail(MK_ERANGE, "k=%d outside 3..6", k);
+    const uint64_t n = (uint64_t)g->n, w = (n + 31) / 32;
+    const uint64_t ws = 4 * (2 * n * w + (n + 1) + (uint64_t)g->nnz_u);
+    const uint64_t slots = 8 * (uint64_t)g->nnz_u + 4 * ((uint64_t)g->nnz_u / 4096 + 2);
+    const uint64_t units = 16 * (uint64_t)g->nnz_u * 4;  // planning estimate
+    const uint64_t hist = 8ull * classes_for_k(k);
+    *bytes = ws + slots + units + hist + sizeof(DevGraph) + 4 * kNumCounters;
+    return MK_OK;
+}
+
+// ------------------------------------------------------------------ batch
+
+static void batch_release(mk_batch *b)
+{
+    for (hipEvent_t e : b->ev)
+        if (e) (void)hipEventDestroy(e);
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    void *bufs[] = {b->d_graphs, b->d_ws, b->d_slot_cnt, b->d_slot_off, b->d_scan_tmp,
+                    b->d_units, b->d_counters, b->d_hist_own};
+    for (void *p : bufs)
+        if (p) (void)hipFree(p);
+}
+
+// enqueue the preparation part of one pass on stream: counters and
+// histograms cleared, typed adjacency, work-unit plan (captured as a hipGraph)
+static int batch_enqueue_prep(mk_batch *b, unsigned long long *hist, hipStream_t stream)
+{
+    int rc = fill_u32(b->d_counters, 0, kNumCounters, stream);
+    if (rc) return rc;
+    rc = fill_u32(hist, 0, (size_t)b->ng * b->table->num_classes * 2, stream);
+    if (rc) return rc;
+    rc = launch_typed_csr(b->d_graphs, b->ng, b->max_n, b->max_words, b->bits_words, b->d_ws,
+                          b->d_counters, stream);
+    if (rc) return rc;
+    return launch_plan(b->k, b->d_graphs, b->ng, b->max_nnz, b->total_slots, b->d_slot_cnt,
+                       b->d_slot_off, b->d_scan_tmp, b->d_units, b->unit_cap,
+                       b->opts.split_threshold, b->d_counters, stream);
+}
+
+// the enumeration kernel between two timing events
+static int batch_enqueue_enum(mk_batch *b, unsigned long long *hist, hipStream_t stream)
+{
+    MK_HIP(hipEventRecord(b->ev[1], stream));
+    int rc = launch_enum(b->k, b->d_graphs, b->d_units, b->unit_cap, kAllUnits, b->d_counters,
+                         b->table->d_table, b->table->num_classes, hist, b->max_n, b->seg_cap,
+                         b->grid, b->lds_bytes, stream);
+    if (rc) return rc;
+    MK_HIP(hipEventRecord(b->ev[2], stream));
+    return MK_OK;
+}
+
+extern "C" int mk_batch_create(mk_ctx *ctx, const mk_graph *const *gs, int32_t ng,
+                               const mk_table *t, const mk_batch_opts *opts, mk_batch **out)
+{
+    if (!ctx || !t || !out || (ng > 0 && !gs)) return fail(MK_EINVAL, "mk_batch_create: NULL argument");
+    if (ng < 0) return fail(MK_EINVAL, "mk_batch_create: ng=%d < 0", ng);
+    if (t->ctx != ctx || !t->d_table) return fail(MK_EINVAL, "mk_batch_create: table of another context");
+    *out = nullptr;
+    for (int i = 0; i < ng; ++i)
+        if (!gs[i] || gs[i]->ctx != ctx)
+            return fail(MK_EINVAL, "mk_batch_create: graph %d missing or of another context", i);
+    std::lock_guard<std::recursive_mutex> lock(ctx->mu);
+    MK_HIP(hipSetDevice(ctx->device));
+
+    mk_batch *b = new mk_batch();
+    b->ctx = ctx;
+    b->table = t;
+    b->k = t->k;
+    b->ng = ng;
+    b->graphs.assign(gs, gs + ng);
+    if (opts) b->opts = *opts;
+    if (b->opts.split_threshold == 0) b->opts.split_threshold = kDefaultSplit[b->k];
+    if (b->opts.use_graph == 0) b->opts.use_graph = 1;
+
+    // workspace layout: [bits of every graph][urow of every graph][uadj ...]
+    std::vector<DevGraph> hg(ng);
+    uint64_t bits = 0, rows = 0, adj = 0, slots = 0;
+    for (int i = 0; i < ng; ++i) {
+        const mk_graph *g = gs[i];
+        const uint64_t w = ((uint64_t)g->n + 31) / 32;
+        bits += 2 * (uint64_t)g->n * w;
+        rows += (uint64_t)g->n + 1;
+        adj += (uint64_t)g->nnz_u;
+        b->max_n = std::max(b->max_n, g->n);
+        b->max_words = std::max<int>(b->max_words, (int)w);
+        b->seg_cap = std::max(b->seg_cap, g->max_udeg);
+        b->max_nnz = std::max<int64_t>(b->max_nnz, g->nnz_u);
+        slots += (uint64_t)g->nnz_u;
+    }
+    if (slots >= 0xFFFFFFFFull) {
+        delete b;
+        return fail(MK_ERANGE, "batch too large: %llu adjacency entries", (unsigned long long)slots);
+    }
+    b->bits_words = bits;
+    b->total_slots = (uint32_t)slots;
+    b->seg_cap = std::max(b->seg_cap, 1);
+    b->lds_bytes = enum_lds_bytes(b->k, std::max(b->max_n, 1), b->seg_cap);
+    if ((size_t)b->lds_bytes > ctx->max_lds) {
+        delete b;
+        return fail(MK_ERANGE, "graphs need %d bytes of LDS per wave (limit %zu)", b->lds_bytes,
+                    ctx->max_lds);
+    }
+    int rc = MK_OK;
+    auto bail = [&](int status) {
+        batch_release(b);
+        delete b;
+        return status;
+    };
+#define BAIL_HIP(x)                                                                            \
+    do {                                                                                       \
+        hipError_t e_ = (x);                                                                   \
+        if (e_ != hipSuccess)                                                                  \
+            return bail(fail(e_ == hipErrorOutOfMemory ? MK_ENOMEM : MK_EDEVICE, "%s: %s", #x, \
+                             hipGetErrorString(e_)));                                          \
+    } while (0)
+
+    BAIL_HIP(hipMalloc(&b->d_ws, sizeof(uint32_t) * std::max<uint64_t>(bits + rows + adj, 1)));
+    {
+        uint64_t ob = 0, orow = bits, oadj = bits + rows, oslot = 0;
+        for (int i = 0; i < ng; ++i) {
+            const mk_graph *g = gs[i];
+            DevGraph d;
+            std::memset(&d, 0, sizeof(d));
+            d.n = g->n;
+            d.words = (g->n + 31) / 32;
+            d.out_row = g->d_row;
+            d.out_col = g->d_col;
+            d.bits_out = b->d_ws + ob;
+            d.bits_in = b->d_ws + ob + (uint64_t)g->n * d.words;
+            d.urow = reinterpret_cast<int32_t *>(b->d_ws + orow);
+            d.uadj = b->d_ws + oadj;
+            d.slot_base = (uint32_t)oslot;
+            d.nnz_cap = (uint32_t)g->nnz_u;
+            ob += 2 * (uint64_t)g->n * d.words;
+            orow += (uint64_t)g->n + 1;
+            oadj += (uint64_t)g->nnz_u;
+            oslot += (uint64_t)g->nnz_u;
+            hg[i] = d;
+        }
+    }
+    BAIL_HIP(hipMalloc(&b->d_graphs, sizeof(DevGraph) * std::max(ng, 1)));
+    if (ng > 0)
+        BAIL_HIP(hipMemcpyAsync(b->d_graphs, hg.data(), sizeof(DevGraph) * ng,
+                                hipMemcpyHostToDevice, ctx->stream));
+    BAIL_HIP(hipMalloc(&b->d_slot_cnt, sizeof(uint32_t) * std::max<uint64_t>(slots, 1)));
+    BAIL_HIP(hipMalloc(&b->d_slot_off, sizeof(uint32_t) * std::max<uint64_t>(slots, 1)));
+    BAIL_HIP(hipMalloc(&b->d_scan_tmp, sizeof(uint32_t) * scan_tmp_words(slots)));
+    BAIL_HIP(hipMalloc(&b->d_counters, sizeof(uint32_t) * kNumCounters));
+    for (hipEvent_t &e : b->ev) BAIL_HIP(hipEventCreate(&e));
+
+    // sizing pass: typed adjacency + unit counts only
+    rc = fill_u32(b->d_counters, 0, kNumCounters, ctx->stream);
+    if (!rc)
+        rc = launch_typed_csr(b->d_graphs, ng, b->max_n, b->max_words, bits, b->d_ws,
+                              b->d_counters, ctx->stream);
+    if (!rc)
+        rc = launch_plan(b->k, b->d_graphs, ng, b->max_nnz, b->total_slots, b->d_slot_cnt,
+                         b->d_slot_off, b->d_scan_tmp, nullptr, 0, b->opts.split_threshold,
+                         b->d_counters, ctx->stream);
+    if (rc) return bail(rc);
+    uint32_t cnt[kNumCounters];
+    BAIL_HIP(hipMemcpyAsync(cnt, b->d_counters, sizeof(cnt), hipMemcpyDeviceToHost, ctx->stream));
+    BAIL_HIP(hipStreamSynchronize(ctx->stream));
+    if (cnt[kAdjOverflow] != 0)
+        return bail(fail(MK_EDEVICE, "typed adjacency exceeds its reserved size"));
+    b->units = cnt[kNumUnits];
+    b->split_pairs = cnt[kSplitPairs];
+    b->unit_cap = std::max<uint32_t>(cnt[kNumUnits], 1);
+    BAIL_HIP(hipMalloc(&b->d_units, sizeof(int4) * b->unit_cap));
+
+    int per_cu = 0;
+    rc = enum_max_blocks_per_cu(b->k, b->lds_bytes, &per_cu);
+    if (rc) return bail(rc);
+    if (b->opts.waves_per_cu > 0) per_cu = std::min(per_cu, b->opts.waves_per_cu);
+    per_cu = std::max(per_cu, 1);
+    b->grid = (int)std::min<uint64_t>((uint64_t)per_cu * ctx->num_cus, std::max<uint64_t>(b->units, 1));
+#undef BAIL_HIP
+    *out = b;
+    return MK_OK;
+}
+
+extern "C" int mk_batch_run(mk_batch *b, uint64_t *d_hist, void *stream)
+{
+    if (!b) return fail(MK_EINVAL, "mk_batch_run: NULL batch");
+    mk_ctx *ctx = b->ctx;
+    std::lock_guard<std::recursive_mutex> lock(ctx->mu);
+    MK_HIP(hipSetDevice(ctx->device));
+    unsigned long long *hist = reinterpret_cast<unsigned long long *>(d_hist);
+    if (!hist) {
+        if (!b->d_hist_own) {
+            hipError_t e = hipMalloc(&b->d_hist_own, sizeof(unsigned long long) *
+                                                         std::max<size_t>((size_t)b->ng * b->table->num_classes, 1));
+            if (e != hipSuccess) return fail(MK_ENOMEM, "mk_batch_run: histogram allocation failed");
+        }
+        hist = b->d_hist_own;
+    }
+    hipStream_t s = stream ? reinterpret_cast<hipStream_t>(stream) : ctx->stream;
+    if (b->ng == 0) {
+        b->hist_last = hist;
+        b->last_stream = s;
+        return MK_OK;
+    }
+    if (b->opts.use_graph > 0) {
+        if (!b->exec || b->exec_hist != hist) {
+            if (b->exec) (void)hipGraphExecDestroy(b->exec);
+            if (b->graph) (void)hipGraphDestroy(b->graph);
+            b->exec = nullptr;
+            b->graph = nullptr;
+            MK_HIP(hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
+            int rc = batch_enqueue_prep(b, hist, ctx->stream);
+            hipGraph_t g = nullptr;
+            hipError_t e = hipStreamEndCapture(ctx->stream, &g);
+            if (rc) {
+                if (g) (void)hipGraphDestroy(g);
+                return rc;
+            }
+            if (e != hipSuccess) return fail(MK_EDEVICE, "hipStreamEndCapture: %s", hipGetErrorString(e));
+            b->graph = g;
+            MK_HIP(hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0));
+            b->exec_hist = hist;
+        }
+        MK_HIP(hipEventRecord(b->ev[0], s));
+        MK_HIP(hipGraphLaunch(b->exec, s));
+    } else {
+        MK_HIP(hipEventRecord(b->ev[0], s));
+        int rc = batch_enqueue_prep(b, hist, s);
+        if (rc) return rc;
+    }
+    int rc = batch_enqueue_enum(b, hist, s);
+    if (rc) return rc;
+    b->hist_last = hist;
+    b->last_stream = s;
+    return MK_OK;
+}
+
+extern "C" int mk_batch_read(mk_batch *b, uint64_t *hist, uint64_t *totals)
+{
+    if (!b) return fail(MK_EINVAL, "mk_batch_read: NULL batch");
+    if (!b->hist_last) return fail(MK_EINVAL, "mk_batch_read: batch has not run");
+    mk_ctx *ctx = b->ctx;
+    std::lock_guard<std::recursive_mutex> lock(ctx->mu);
+    MK_HIP(hipSetDevice(ctx->device));
+    MK_HIP(hipStreamSynchronize(b->last_stream));
+    const size_t nc = b->table->num_classes;
+    if (b->ng == 0) return MK_OK;
+    uint32_t cnt[kNumCounters];
+    MK_HIP(hipMemcpy(cnt, b->d_counters, sizeof(cnt), hipMemcpyDeviceToHost));
+    if (cnt[kErrors] != 0 || cnt[kAdjOverflow] != 0)
+        return fail(MK_EDEVICE,
+                    "device-side check failed (%u lookup/plan errors, %u adjacency overflows)",
+                    cnt[kErrors], cnt[kAdjOverflow]);
+    if (cnt[kNumUnits] > b->unit_cap)
+        return fail(MK_EDEVICE, "plan produced %u units, capacity %u", cnt[kNumUnits], b->unit_cap);
+    b->units = cnt[kNumUnits];
+    b->split_pairs = cnt[kSplitPairs];
+    std::vector<uint64_t> tmp;
+    uint64_t *dst = hist;
+    if (!dst && totals) {
+        tmp.resize((size_t)b->ng * nc);
+        dst = tmp.data();
+    }
+    if (dst) {
+        MK_HIP(hipMemcpy(dst, b->hist_last, sizeof(uint64_t) * (size_t)b->ng * nc,
+                         hipMemcpyDeviceToHost));
+        if (totals)
+            for (int i = 0; i < b->ng; ++i) {
+                uint64_t s = 0;
+                for (size_t c = 0; c < nc; ++c) s += dst[(size_t)i * nc + c];
+                totals[i] = s;
+            }
+    }
+    return MK_OK;
+}
+
+extern "C" int mk_batch_stats_get(const mk_batch *b, mk_batch_stats *out)
+{
+    if (!b || !out) return fail(MK_EINVAL, "mk_batch_stats_get: NULL argument");
+    out->units = b->units;
+    out->split_pairs = b->split_pairs;
+    out->grid = b->grid;
+    out->lds_bytes = b->lds_bytes;
+    out->k = b->k;
+    out->ng = b->ng;
+    return MK_OK;
+}
+
+extern "C" int mk_batch_timing(mk_batch *b, double *pass_ms, double *enum_ms)
+{
+    if (!b) return fail(MK_EINVAL, "mk_batch_timing: NULL batch");
+    if (!b->hist_last || b->ng == 0) return fail(MK_EINVAL, "mk_batch_timing: batch has not run");
+    std::lock_guard<std::recursive_mutex> lock(b->ctx->mu);
+    MK_HIP(hipSetDevice(b->ctx->device));
+    MK_HIP(hipEventSynchronize(b->ev[2]));
+    float a = 0.f, e = 0.f;
+    MK_HIP(hipEventElapsedTime(&a, b->ev[0], b->ev[2]));
+    MK_HIP(hipEventElapsedTime(&e, b->ev[1], b->ev[2]));
+    if (pass_ms) *pass_ms = a;
+    if (enum_ms) *enum_ms = e;
+    return MK_OK;
+}
+
+extern "C" void mk_batch_free(mk_batch *b)
+{
+    if (!b) return;
+    std::lock_guard<std::recursive_mutex> lock(b->ctx->mu);
+    (void)hipSetDevice(b->ctx->device);
+    if (b->last_stream) (void)hipStreamSynchronize(b->last_stream);
+    (void)hipStreamSynchronize(b->ctx->stream);
+    batch_release(b);
+    delete b;
+}
+
+// ------------------------------------------------------------------ count
+
+extern "C" int mk_count_batch(mk_ctx *ctx, const mk_graph *const *gs, int32_t ng,
+                              const mk_table *t, uint64_t *hist, uint64_t *totals)
+{
+    if (!ctx || !t || (ng > 0 && (!gs || !hist)))
+        return fail(MK_EINVAL, "mk_count_batch: NULL argument");
+    mk_batch_opts o{};
+    o.use_graph = -1;
+    mk_batch *b = nullptr;
+    int rc = mk_batch_create(ctx, gs, ng, t, &o, &b);
+    if (rc) return rc;
+    rc = mk_batch_run(b, nullptr, nullptr);
+    if (!rc) rc = mk_batch_read(b, hist, totals);
+    mk_batch_free(b);
+    return rc;
+}
+
+extern "C" int mk_count(mk_ctx *ctx, const mk_graph *g, const mk_table *t, uint64_t *hist,
+                        uint64_t *total)
+{
+    if (!g) return fail(MK_EINVAL, "mk_count: NULL graph");
+    return mk_count_batch(ctx, &g, 1, t, hist, total);
+}

@@ -1,0 +1,369 @@
+// Enumeration of connected induced k-subgraphs, their adjacency codes, the
+// O(1) class lookup (Section 3.2) and the histogram H_k (Problem Motifs-k).
+//
+// One 64-lane wavefront is one workgroup.  Waves are persistent: each takes
+// work units from a global queue (one atomic per unit) until it is empty.
+// A unit is a first-level ESU node (root v, first extension vertex w_i),
+// possibly restricted to a range of that node's children (hub splitting).
+//
+// Per wave, LDS holds
+//   mark[n]        for every vertex x, its relation to the current members
+//                  s_0..s_d of the growing subgraph: "in" bit d(k-1) set iff
+//                  arc s_d -> x, "out" bit OUTB+d set iff arc x -> s_d.  The
+//                  in bits are already spread at stride k-1, so the code
+//                  bits that a vertex adds when it joins at position p are
+//                      (out << p(k-1)) | (in << (p-1))
+//                  -- exactly bits b(i,p) = i(k-1)+p-1 and b(p,i) = p(k-1)+i
+//                  of the adjacency code.  mark[x] == 0 also says "x is
+//                  neither a member nor a neighbour of one" (the exclusive
+//                  neighbourhood test of ESU).
+//   seg[l][.]      the vertices that joined the extension list when member
+//                  s_l was added (s_0's are the root's larger neighbours).
+// A node's extension list is the concatenation of the unconsumed tails of
+// seg[0..d]; it is never copied.
+//
+// Adding a member scans its typed adjacency list (Section 2's A/B/C types)
+// with all 64 lanes: each lane reads the mark of one neighbour, a ballot and
+// a lane-prefix count compact the new extension vertices into seg[d], and the
+// lane ORs the member's two bits into the neighbour's mark.  Removing it
+// clears those bits again, so marks are all zero between units.
+//
+// At the last level every extension vertex u closes one k-subgraph: lanes
+// take one u each, read mark[u] and form the code with two shifts and an OR
+// -- this replaces the pair tests of Algorithms 2-5 (Section 3.1): the edges
+// of G[S] are known from the marks the members left.  Lanes holding equal
+// codes are merged with ballots (all lanes of a node share k-1 members, so
+// few distinct codes occur), then each distinct code is looked up in the
+// code -> class table once and added to the graph's histogram with one
+// 64-bit atomic.
+#include <climits>
+
+#include "internal.h"
+
+namespace mk {
+
+constexpr int kAggRounds = 16;
+
+template <int K>
+struct EnumState {
+    static constexpr int OUTB = (K - 2) * (K - 1) + 1;
+    static constexpr uint32_t INMASK = (1u << OUTB) - 1u;
+    uint32_t *mark;
+    uint32_t *seg;
+    int seg_cap;
+    int root;
+    const int32_t *urow;
+    const uint32_t *uadj;
+    unsigned long long *hist;
+    const uint32_t *table;
+    uint32_t num_classes;
+    uint32_t *errors;
+    int len[K - 1];
+};
+
+__device__ __forceinline__ int lane_id() { return (int)threadIdx.x; }
+
+__device__ __forceinline__ int uniform(int x) { return __builtin_amdgcn_readfirstlane(x); }
+
+__device__ __forceinline__ uint32_t lanes_below(unsigned long long mask)
+{
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                     __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+// both mark bits of member position d for a neighbour of type t
+template <int K>
+__device__ __forceinline__ uint32_t mark_bits(int d, uint32_t t)
+{
+    return ((t & 1u) << (d * (K - 1))) | (((t >> 1) & 1u) << (EnumState<K>::OUTB + d));
+}
+
+// code bits contributed by a vertex with mark m joining at position p >= 1
+template <int K>
+__device__ __forceinline__ uint32_t code_bits(uint32_t m, int p)
+{
+    return ((m >> EnumState<K>::OUTB) << (p * (K - 1))) | ((m & EnumState<K>::INMASK) << (p - 1));
+}
+
+// s_D := x.  Builds seg[D] (new exclusive extension vertices, ascending) and
+// ORs position D's bits into the marks of x's neighbours.
+template <int K, int D>
+__device__ __forceinline__ void push(EnumState<K> &s, int x)
+{
+    const int lane = lane_id();
+    const int r0 = uniform(s.urow[x]);
+    const int r1 = uniform(s.urow[x + 1]);
+    uint32_t *seg = s.seg + D * s.seg_cap;
+    int cnt = 0;
+    for (int base = r0; base < r1; base += kWave) {
+        const int e = base + lane;
+        const bool valid = e < r1;
+        const uint32_t ent = valid ? s.uadj[e] : 0u;
+        const int y = (int)(ent >> 2);
+        const uint32_t m = valid ? s.mark[y] : 1u;
+        const bool fresh = valid && y > s.root && m == 0u;
+        const unsigned long long bal = __ballot(fresh);
+        if (fresh) seg[cnt + (int)lanes_below(bal)] = (uint32_t)y;
+        cnt += __popcll(bal);
+        if (valid) s.mark[y] = m | mark_bits<K>(D, ent & 3u);
+    }
+    s.len[D] = cnt;
+    __syncthreads();
+}
+
+// undo push<D>(x)
+template <int K, int D>
+__device__ __forceinline__ void pop(EnumState<K> &s, int x)
+{
+    const int lane = lane_id();
+    const int r0 = uniform(s.urow[x]);
+    const int r1 = uniform(s.urow[x + 1]);
+    const uint32_t keep = ~mark_bits<K>(D, 3u);
+    for (int base = r0; base < r1; base += kWave) {
+        const int e = base + lane;
+        if (e < r1) {
+            const int y = (int)(s.uadj[e] >> 2);
+            s.mark[y] &= keep;
+        }
+    }
+    __syncthreads();
+}
+
+// count one code per valid lane
+template <int K>
+__device__ __forceinline__ void count_codes(EnumState<K> &s, bool valid, uint32_t code)
+{
+    const int lane = lane_id();
+    unsigned long long act = __ballot(valid);
+    uint32_t n = 0;
+    bool lead = false;
+#pragma unroll 1
+    for (int r = 0; r < kAggRounds && act; ++r) {
+        const int l = __builtin_ctzll(act);
+        const uint32_t c0 = (uint32_t)__builtin_amdgcn_readlane((int)code, l);
+        const unsigned long long eq = __ballot(code == c0) & act;
+        if (lane == l) {
+            lead = true;
+            n = (uint32_t)__popcll(eq);
+        }
+        act &= ~eq;
+    }
+    if ((act >> lane) & 1ull) {
+        lead = true;
+        n = 1;
+    }
+    if (lead) {
+        const uint32_t id = s.table[code];
+        if (id < s.num_classes) atomicAdd(&s.hist[id], (unsigned long long)n);
+        else atomicAdd(s.errors, 1u);
+    }
+}
+
+// last level: members s_0..s_{K-2}; every extension vertex closes a k-set
+template <int K>
+__device__ __forceinline__ void leaf(EnumState<K> &s, const int (&st)[K - 1], uint32_t code)
+{
+    const int lane = lane_id();
+    int rem[K - 1];
+    int total = 0;
+#pragma unroll
+    for (int q = 0; q < K - 1; ++q) {
+        rem[q] = s.len[q] - st[q];
+        total += rem[q];
+    }
+    for (int base = 0; base < total; base += kWave) {
+        int a = base + lane;
+        const bool valid = a < total;
+        int addr = 0;
+        bool found = false;
+#pragma unroll
+        for (int q = 0; q < K - 1; ++q) {
+            if (!found) {
+                if (a < rem[q]) {
+                    addr = q * s.seg_cap + st[q] + a;
+                    found = true;
+                } else {
+                    a -= rem[q];
+                }
+            }
+        }
+        uint32_t c = 0;
+        if (valid) {
+            const uint32_t u = s.seg[addr];
+            c = code | code_bits<K>(s.mark[u], K - 1);
+        }
+        count_codes<K>(s, valid, c);
+    }
+}
+
+// node with members s_0..s_D: visit children jlo..jhi-1 of its extension
+// list (the tails seg[q][st[q]:] for q <= D, in order)
+template <int K, int D>
+__device__ void visit(EnumState<K> &s, const int (&st)[K - 1], uint32_t code, int jlo, int jhi)
+{
+    if constexpr (D == K - 2) {
+        leaf<K>(s, st, code);
+    } else {
+        int rem[D + 1];
+        int total = 0;
+#pragma unroll
+        for (int q = 0; q <= D; ++q) {
+            rem[q] = s.len[q] - st[q];
+            total += rem[q];
+        }
+        const int hi = total < jhi ? total : jhi;
+        for (int j = jlo; j < hi; ++j) {
+            int a = j, L = 0, o = 0;
+            bool found = false;
+#pragma unroll
+            for (int q = 0; q <= D; ++q) {
+                if (!found) {
+                    if (a < rem[q]) {
+                        L = q;
+                        o = st[q] + a;
+                        found = true;
+                    } else {
+                        a -= rem[q];
+                    }
+                }
+            }
+            const int x = uniform((int)s.seg[L * s.seg_cap + o]);
+            const uint32_t mx = (uint32_t)uniform((int)s.mark[x]);
+            const uint32_t ccode = code | code_bits<K>(mx, D + 1);
+            push<K, D + 1>(s, x);
+            int cst[K - 1];
+#pragma unroll
+            for (int q = 0; q < K - 1; ++q)
+                cst[q] = q < L ? s.len[q] : (q == L ? o + 1 : (q <= D ? st[q] : 0));
+            visit<K, D + 1>(s, cst, ccode, 0, INT_MAX);
+            pop<K, D + 1>(s, x);
+        }
+    }
+}
+
+template <int K>
+__device__ void run_unit(EnumState<K> &s, int v, int i, uint32_t range)
+{
+    s.root = v;
+    push<K, 0>(s, v);
+    if (i < s.len[0]) {
+        const int x = uniform((int)s.seg[i]);
+        const uint32_t code = code_bits<K>((uint32_t)uniform((int)s.mark[x]), 1);
+        push<K, 1>(s, x);
+        int st[K - 1];
+#pragma unroll
+        for (int q = 0; q < K - 1; ++q) st[q] = 0;
+        st[0] = i + 1;
+        if (range == kFullChild)
+            visit<K, 1>(s, st, code, 0, INT_MAX);
+        else
+            visit<K, 1>(s, st, code, (int)(range & 0xFFFFu), (int)(range >> 16));
+        pop<K, 1>(s, x);
+    } else if (lane_id() == 0) {
+        atomicAdd(s.errors, 1u);
+    }
+    pop<K, 0>(s, v);
+}
+
+template <int K>
+__global__ __launch_bounds__(kWave) void enum_kernel(const DevGraph *graphs, const int4 *units,
+                                                     uint32_t unit_cap, uint32_t unit_end,
+                                                     uint32_t *counters,
+                                                     const uint32_t *table, uint32_t num_classes,
+                                                     unsigned long long *hist_base, int max_n,
+                                                     int seg_cap)
+{
+    extern __shared__ uint32_t lds[];
+    EnumState<K> s;
+    s.mark = lds;
+    s.seg = lds + max_n;
+    s.seg_cap = seg_cap;
+    s.table = table;
+    s.num_classes = num_classes;
+    s.errors = &counters[kErrors];
+    s.root = 0;
+    s.urow = nullptr;
+    s.uadj = nullptr;
+    s.hist = nullptr;
+    for (int i = lane_id(); i < max_n; i += kWave) lds[i] = 0u;
+    __syncthreads();
+    const uint32_t navail = counters[kNumUnits];
+    const uint32_t cap = unit_cap < unit_end ? unit_cap : unit_end;
+    const uint32_t total = navail < cap ? navail : cap;
+    int cur = -1;
+    for (;;) {
+        uint32_t idx = 0;
+        if (lane_id() == 0) idx = atomicAdd(&counters[kQueueHead], 1u);
+        idx = (uint32_t)uniform((int)idx);
+        if (idx >= total) break;
+        const int4 u = units[idx];
+        const int gi = uniform(u.x);
+        if (gi != cur) {
+            s.urow = graphs[gi].urow;
+            s.uadj = graphs[gi].uadj;
+            s.hist = hist_base + (size_t)gi * num_classes;
+            cur = gi;
+        }
+        run_unit<K>(s, uniform(u.y), uniform(u.z), (uint32_t)uniform(u.w));
+    }
+}
+
+int enum_lds_bytes(int k, int max_n, int seg_cap)
+{
+    return (int)sizeof(uint32_t) * (max_n + (k - 1) * seg_cap);
+}
+
+template <int K>
+static const void *enum_fn()
+{
+    return reinterpret_cast<const void *>(&enum_kernel<K>);
+}
+
+int enum_max_blocks_per_cu(int k, int lds_bytes, int *blocks)
+{
+    const void *fn = nullptr;
+    switch (k) {
+    case 3: fn = enum_fn<3>(); break;
+    case 4: fn = enum_fn<4>(); break;
+    case 5: fn = enum_fn<5>(); break;
+    case 6: fn = enum_fn<6>(); break;
+    default: return fail(MK_ERANGE, "k=%d outside 3..6", k);
+    }
+    MK_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, fn, kWave, (size_t)lds_bytes));
+    return MK_OK;
+}
+
+int launch_enum(int k, const DevGraph *d_graphs, const int4 *units, uint32_t unit_cap,
+                uint32_t unit_end, uint32_t *counters, const uint32_t *table, uint32_t num_classes,
+                unsigned long long *hist_base, int max_n, int seg_cap, int grid, int lds_bytes,
+                hipStream_t stream)
+{
+    if (grid <= 0) return MK_OK;
+    switch (k) {
+    case 3:
+        hipLaunchKernelGGL(enum_kernel<3>, dim3(grid), dim3(kWave), lds_bytes, stream, d_graphs,
+                           units, unit_cap, unit_end, counters, table, num_classes, hist_base, max_n,
+                           seg_cap);
+        break;
+    case 4:
+        hipLaunchKernelGGL(enum_kernel<4>, dim3(grid), dim3(kWave), lds_bytes, stream, d_graphs,
+                           units, unit_cap, unit_end, counters, table, num_classes, hist_base, max_n,
+                           seg_cap);
+        break;
+    case 5:
+        hipLaunchKernelGGL(enum_kernel<5>, dim3(grid), dim3(kWave), lds_bytes, stream, d_graphs,
+                           units, unit_cap, unit_end, counters, table, num_classes, hist_base, max_n,
+                           seg_cap);
+        break;
+    case 6:
+        hipLaunchKernelGGL(enum_kernel<6>, dim3(grid), dim3(kWave), lds_bytes, stream, d_graphs,
+                           units, unit_cap, unit_end, counters, table, num_classes, hist_base, max_n,
+                           seg_cap);
+        break;
+    default: return fail(MK_ERANGE, "k=%d outside 3..6", k);
+    }
+    MK_HIP(hipGetLastError());
+    return MK_OK;
+}
+
+}  // namespace mk

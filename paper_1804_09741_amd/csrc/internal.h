@@ -1,0 +1,146 @@
+// Internal declarations of libmotifs (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdint>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "motifs.h"
+
+namespace mk {
+
+// ------------------------------------------------------------------ errors
+
+int fail(int status, const char *fmt, ...);  // records the message, returns status
+
+#define MK_HIP(call)                                                            \
+    do {                                                                        \
+        hipError_t mk_e_ = (call);                                              \
+        if (mk_e_ != hipSuccess)                                                \
+            return ::mk::fail(MK_EDEVICE, "%s: %s (%s:%d)", #call,              \
+                              hipGetErrorString(mk_e_), __FILE__, __LINE__);    \
+    } while (0)
+
+// ---------------------------------------------------------- device limits
+
+constexpr int kWave = 64;
+
+// ------------------------------------------------------------ table object
+
+struct Table {
+    mk_ctx *ctx = nullptr;
+    int k = 0;
+    uint64_t entries = 0;          // 2^(k(k-1))
+    uint32_t num_classes = 0;
+    uint32_t *d_table = nullptr;   // entries x uint32: code -> class id
+    uint32_t *d_classes = nullptr; // num_classes canonical codes, ascending
+    std::vector<uint32_t> classes; // host copy of d_classes
+    double build_ms = 0.0;
+};
+
+// ----------------------------------------------------------- graph object
+
+struct Graph {
+    mk_ctx *ctx = nullptr;
+    int32_t n = 0;
+    int64_t m = 0;
+    int64_t nnz_u = 0;        // sum of undirected degrees |delta(v)|
+    int32_t max_udeg = 0;
+    int32_t *d_row = nullptr; // n+1, out-adjacency CSR as given
+    int32_t *d_col = nullptr; // m
+};
+
+// Descriptor of one graph inside a batch, read by every kernel of the path.
+struct DevGraph {
+    int32_t n;
+    int32_t words;            // 32-bit words per bit-matrix row: ceil(n/32)
+    const int32_t *out_row;   // n+1
+    const int32_t *out_col;   // m
+    uint32_t *bits_out;       // n x words, row u bit v: arc u -> v
+    uint32_t *bits_in;        // n x words, row v bit u: arc u -> v
+    int32_t *urow;            // n+1 offsets of delta(v) in uadj
+    uint32_t *uadj;           // (u << 2) | type; type bit0: v -> u, bit1: u -> v
+    uint32_t slot_base;       // first planner slot of this graph
+    uint32_t nnz_cap;         // entries reserved for uadj (host-computed sum of |delta(v)|)
+};
+
+// Work unit of the enumeration queue.
+//   x: graph index in the batch, y: root vertex v,
+//   z: index i of the first extension vertex in v's extension list,
+//   w: kFullChild -> the whole subtree below (v, w_i);
+//      else j0 | j1 << 16 -> children j0..j1-1 of the node (v, w_i).
+constexpr uint32_t kFullChild = 0xFFFFFFFFu;
+
+// counters[] slots shared by planner and enumeration kernels
+enum Counter : int {
+    kQueueHead = 0,   // next unit to hand out
+    kNumUnits = 1,    // units written by the planner
+    kErrors = 2,      // device-side consistency failures (must stay 0)
+    kSplitPairs = 3,  // (root, first neighbour) pairs split at the second level
+    kAdjOverflow = 4, // typed adjacency larger than reserved (must stay 0)
+    kNumCounters = 8,
+};
+
+// --------------------------------------------------------------- context
+
+struct Ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    int num_cus = 0;
+    int64_t hbm_bytes = 0;
+    size_t max_lds = 0;
+    Table *tables[7] = {};
+    std::recursive_mutex mu;
+};
+
+// ------------------------------------------------------- kernel launchers
+
+// Exclusive prefix sum of n uint32 values (or of their popcounts when
+// popcount != 0) into out; the grand total goes to *d_total.  tmp must hold
+// scan_tmp_words(n) words.  Everything is on `stream`, asynchronous.
+size_t scan_tmp_words(size_t n);
+int scan_u32(const uint32_t *in, uint32_t *out, size_t n, int popcount, uint32_t *d_total,
+             uint32_t *tmp, hipStream_t stream);
+
+// Fill n 32-bit words with value (a kernel, so it can live in a captured
+// hipGraph).
+int fill_u32(void *dst, uint32_t value, size_t n, hipStream_t stream);
+
+// Class table build for k (3..6).  Allocates and fills t->d_table,
+// t->d_classes, t->num_classes.  Synchronous.
+int build_table(Table *t, hipStream_t stream);
+
+// Typed symmetric adjacency of every graph of a batch (bit matrices
+// zeroed, arcs set, degrees counted and scanned, lists written).
+int launch_typed_csr(const DevGraph *d_graphs, int ng, int max_n, int max_words,
+                     uint64_t bits_words_total, uint32_t *bits_base, uint32_t *counters,
+                     hipStream_t stream);
+
+// Work-unit planner: counts per slot, scan, emit.  Writes counters[kNumUnits].
+int launch_plan(int k, const DevGraph *d_graphs, int ng, int64_t max_nnz, uint32_t total_slots,
+                uint32_t *slot_cnt, uint32_t *slot_off, uint32_t *scan_tmp, int4 *units,
+                uint32_t unit_cap, uint64_t split_threshold, uint32_t *counters,
+                hipStream_t stream);
+
+// Enumeration + code + lookup + histogram over the queued units.
+int enum_lds_bytes(int k, int max_n, int seg_cap);
+int enum_max_blocks_per_cu(int k, int lds_bytes, int *blocks);
+constexpr uint32_t kAllUnits = 0xFFFFFFFFu;
+// Units are taken from counters[kQueueHead] up to min(counters[kNumUnits],
+// unit_cap, unit_end).
+int launch_enum(int k, const DevGraph *d_graphs, const int4 *units, uint32_t unit_cap,
+                uint32_t unit_end, uint32_t *counters, const uint32_t *table, uint32_t num_classes,
+                unsigned long long *hist_base, int max_n, int seg_cap, int grid, int lds_bytes,
+                hipStream_t stream);
+
+void free_table(Table *t);
+
+}  // namespace mk
+
+struct mk_ctx : mk::Ctx {};
+struct mk_graph : mk::Graph {};
+struct mk_table : mk::Table {};

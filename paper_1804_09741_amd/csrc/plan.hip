@@ -1,0 +1,172 @@
+// Work-unit planner for the enumeration queue.
+//
+// The enumeration lists every connected k-set once from its smallest vertex
+// v (the root) by ESU: the root's extension list is E_v = {u in delta(v) :
+// u > v}; choosing its i-th vertex w_i gives the node (v, w_i), whose own
+// extension list is E_v[i+1:] followed by the neighbours of w_i that exceed v
+// and are not in delta(v).  A work unit is one such first-level node; the
+// subtree below it holds roughly C(L2, k-2) subgraphs when its extension list
+// has L2 vertices.  Nodes estimated above the split threshold (hubs of the
+// celebrity graphs of Section 3.1) are cut into ranges of their own children
+// instead, weighted C(L2-j-1, k-3) + 1 for child j, so that many wavefronts
+// share one hub.
+//
+// Slots are the entries of the typed adjacency lists (one per (v, u) with
+// u in delta(v)); a slot with u > v is a first-level node.  Pass one counts
+// the units of every slot, a scan gives offsets, pass two writes the units.
+// The order is graph by graph, root by root.
+#include "internal.h"
+
+namespace mk {
+
+constexpr int kPlanThreads = 256;
+
+__device__ __forceinline__ uint64_t choose_small(int64_t n, int r)
+{
+    if (n < r) return 0;
+    const uint64_t x = (uint64_t)n;
+    switch (r) {
+    case 0: return 1;
+    case 1: return x;
+    case 2: return x * (x - 1) / 2;
+    case 3: return x * (x - 1) * (x - 2) / 6;
+    default: return x * (x - 1) * (x - 2) / 6 * (x - 3) / 4;
+    }
+}
+
+// vertex v with urow[v] <= e < urow[v+1]
+__device__ __forceinline__ int owner_of(const int32_t *urow, int n, int e)
+{
+    int lo = 0, hi = n;  // answer in [lo, hi)
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (urow[mid] <= e) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// first position in [r0, r1) whose vertex exceeds v (lists are sorted)
+__device__ __forceinline__ int first_above(const uint32_t *uadj, int r0, int r1, int v)
+{
+    int lo = r0, hi = r1;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if ((int)(uadj[mid] >> 2) > v) hi = mid;
+        else lo = mid + 1;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ bool adjacent(const DevGraph &g, int v, int x)
+{
+    const size_t w = (size_t)v * g.words + (x >> 5);
+    return ((g.bits_out[w] | g.bits_in[w]) >> (x & 31)) & 1u;
+}
+
+template <int K, bool EMIT>
+__global__ __launch_bounds__(kPlanThreads) void plan_kernel(const DevGraph *graphs,
+                                                            uint32_t *slot_cnt,
+                                                            const uint32_t *slot_off, int4 *units,
+                                                            uint32_t unit_cap, uint64_t threshold,
+                                                            uint32_t *counters)
+{
+    const int gi = blockIdx.y;
+    const DevGraph &g = graphs[gi];
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g.n == 0 || e >= min(g.urow[g.n], (int)g.nnz_cap)) return;
+    const uint32_t slot = g.slot_base + (uint32_t)e;
+    const int v = owner_of(g.urow, g.n, e);
+    const int y = (int)(g.uadj[e] >> 2);
+    if (y <= v) {
+        if (!EMIT) slot_cnt[slot] = 0;
+        return;
+    }
+    const int r1 = g.urow[v + 1];
+    const int first = first_above(g.uadj, g.urow[v], r1, v);
+    const int i = e - first;
+    const int ext_v = r1 - first;
+    int fresh = 0;
+    for (int t = g.urow[y]; t < g.urow[y + 1]; ++t) {
+        const int x = (int)(g.uadj[t] >> 2);
+        if (x > v && !adjacent(g, v, x)) ++fresh;
+    }
+    const int L2 = ext_v - i - 1 + fresh;
+    uint32_t base = 0;
+    if (EMIT) base = slot_off[slot];
+    auto put = [&](uint32_t r, uint32_t w) {
+        const uint32_t idx = base + r;
+        if (idx < unit_cap) units[idx] = make_int4(gi, v, i, (int)w);
+        else atomicOr(&counters[kErrors], 1u);
+    };
+    uint32_t cnt = 0;
+    if (K == 3 || choose_small(L2, K - 2) <= threshold) {
+        if (EMIT) put(0, kFullChild);
+        cnt = 1;
+    } else {
+        int j0 = 0;
+        uint64_t acc = 0;
+        for (int j = 0; j < L2; ++j) {
+            const uint64_t wj = choose_small(L2 - j - 1, K - 3) + 1;
+            if (j > j0 && acc + wj > threshold) {
+                if (EMIT) put(cnt, (uint32_t)j0 | ((uint32_t)j << 16));
+                ++cnt;
+                j0 = j;
+                acc = 0;
+            }
+            acc += wj;
+        }
+        if (L2 > j0) {
+            if (EMIT) put(cnt, (uint32_t)j0 | ((uint32_t)L2 << 16));
+            ++cnt;
+        }
+        if (!EMIT) atomicAdd(&counters[kSplitPairs], 1u);
+    }
+    if (!EMIT) slot_cnt[slot] = cnt;
+}
+
+template <int K>
+static int plan_k(const DevGraph *d_graphs, int ng, int64_t max_nnz, uint32_t total_slots,
+                  uint32_t *slot_cnt, uint32_t *slot_off, uint32_t *scan_tmp, int4 *units,
+                  uint32_t unit_cap, uint64_t threshold, uint32_t *counters, hipStream_t stream)
+{
+    const dim3 grid((unsigned)((max_nnz + kPlanThreads - 1) / kPlanThreads > 0
+                                   ? (max_nnz + kPlanThreads - 1) / kPlanThreads
+                                   : 1),
+                    (unsigned)ng);
+    hipLaunchKernelGGL((plan_kernel<K, false>), grid, dim3(kPlanThreads), 0, stream, d_graphs,
+                       slot_cnt, slot_off, units, unit_cap, threshold, counters);
+    MK_HIP(hipGetLastError());
+    int rc = scan_u32(slot_cnt, slot_off, total_slots, 0, &counters[kNumUnits], scan_tmp, stream);
+    if (rc != MK_OK) return rc;
+    if (!units) return MK_OK;  // sizing pass
+    hipLaunchKernelGGL((plan_kernel<K, true>), grid, dim3(kPlanThreads), 0, stream, d_graphs,
+                       slot_cnt, slot_off, units, unit_cap, threshold, counters);
+    MK_HIP(hipGetLastError());
+    return MK_OK;
+}
+
+int launch_plan(int k, const DevGraph *d_graphs, int ng, int64_t max_nnz, uint32_t total_slots,
+                uint32_t *slot_cnt, uint32_t *slot_off, uint32_t *scan_tmp, int4 *units,
+                uint32_t unit_cap, uint64_t split_threshold, uint32_t *counters,
+                hipStream_t stream)
+{
+    if (ng <= 0) return MK_OK;
+    switch (k) {
+    case 3:
+        return plan_k<3>(d_graphs, ng, max_nnz, total_slots, slot_cnt, slot_off, scan_tmp, units,
+                         unit_cap, split_threshold, counters, stream);
+    case 4:
+        return plan_k<4>(d_graphs, ng, max_nnz, total_slots, slot_cnt, slot_off, scan_tmp, units,
+                         unit_cap, split_threshold, counters, stream);
+    case 5:
+        return plan_k<5>(d_graphs, ng, max_nnz, total_slots, slot_cnt, slot_off, scan_tmp, units,
+                         unit_cap, split_threshold, counters, stream);
+    case 6:
+        return plan_k<6>(d_graphs, ng, max_nnz, total_slots, slot_cnt, slot_off, scan_tmp, units,
+                         unit_cap, split_threshold, counters, stream);
+    default: return fail(MK_ERANGE, "k=%d outside 3..6", k);
+    }
+}
+
+}  // namespace mk

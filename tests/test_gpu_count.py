@@ -1,0 +1,172 @@
+"""GPU enumeration + lookup + histogram against the CPU oracle.
+
+Small cases compare every class bit-exactly; closed-form graphs check the
+known counts; batched, split and replayed runs must equal the plain run.
+"""
+
+import math
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1804_09741_amd import inputs as I
+from paper_1804_09741_amd import motifs as M
+
+from gpu_helpers import as_code_dict, assert_hist_equals_oracle
+
+pytestmark = pytest.mark.gpu
+
+
+def _count(ctx, g, k, **opts):
+    gr = ctx.load_graph(*g)
+    t = ctx.table(k)
+    try:
+        if opts:
+            b = ctx.batch([gr], t, **opts)
+            try:
+                b.run()
+                hist, totals = b.read()
+                return hist[0], int(totals[0])
+            finally:
+                b.free()
+        return ctx.count(gr, t)
+    finally:
+        gr.free()
+
+
+@pytest.mark.parametrize("k", [3, 4, 5, 6])
+@pytest.mark.parametrize("seed", range(3))
+def test_random_small_graphs(ctx, k, seed):
+    rng = np.random.default_rng([1000, k, seed])
+    n = int(rng.integers(20, 80))
+    m = int(rng.integers(n, 4 * n))
+    g = I.chung_lu_digraph(n, m, float(rng.uniform(2.0, 2.6)), 25, 0.2, rng)
+    hist, total = _count(ctx, g, k)
+    cc = ctx.table(k).class_codes()
+    assert total == int(hist.sum())
+    assert_hist_equals_oracle(hist, cc, *g, k)
+
+
+@pytest.mark.parametrize("k", [3, 4, 5, 6])
+def test_brute_force_tiny(ctx, k):
+    rng = np.random.default_rng([2000, k])
+    cc = ctx.table(k).class_codes()
+    for _ in range(4):
+        g = I.er_digraph(9, int(rng.integers(9, 30)), rng)
+        hist, _ = _count(ctx, g, k)
+        assert as_code_dict(hist, cc) == O.brute_force_count(*g, k)
+
+
+@pytest.mark.parametrize("k", [3, 4, 5, 6])
+def test_closed_forms(ctx, k):
+    t = ctx.table(k)
+    full = (1 << (k * (k - 1))) - 1
+    star = (1 << (k - 1)) - 1
+    hist, total = _count(ctx, I.complete_digraph(9), k)
+    assert total == math.comb(9, k) and hist[t.lookup(full)] == total
+    hist, total = _count(ctx, I.out_star(40), k)
+    assert total == math.comb(40, k - 1) and hist[0] == total and t.class_code(0) == star
+    hist, total = _count(ctx, I.in_star(40), k)
+    assert total == math.comb(40, k - 1) and np.count_nonzero(hist) == 1
+    hist, total = _count(ctx, I.directed_cycle(30), k)
+    assert total == 30 and np.count_nonzero(hist) == 1
+    hist, total = _count(ctx, I.directed_path(30), k)
+    assert total == 30 - k + 1 and np.count_nonzero(hist) == 1
+    hist, total = _count(ctx, I.bidirected_cycle(30), k)
+    assert total == 30 and np.count_nonzero(hist) == 1
+
+
+@pytest.mark.parametrize("k", [3, 4, 5, 6])
+def test_hub_star_splits(ctx, k):
+    """A hub of degree 300 (k=6: 60) forces second-level work splitting."""
+    leaves = 300 if k < 6 else 60
+    rng = np.random.default_rng([3000, k])
+    s = [0] * leaves + rng.integers(1, leaves + 1, size=leaves // 3).tolist()
+    d = list(range(1, leaves + 1)) + rng.integers(1, leaves + 1, size=leaves // 3).tolist()
+    keep = [(a, b) for a, b in dict.fromkeys(zip(s, d)) if a != b]
+    g = I.csr_from_arcs(leaves + 1, [a for a, _ in keep], [b for _, b in keep])
+    cc = ctx.table(k).class_codes()
+    h1, t1 = _count(ctx, g, k)
+    h2, t2 = _count(ctx, g, k, split_threshold=1)
+    h3, t3 = _count(ctx, g, k, split_threshold=1 << 40, waves_per_cu=1)
+    assert np.array_equal(h1, h2) and np.array_equal(h1, h3)
+    if k <= 5 or leaves <= 60:
+        assert_hist_equals_oracle(h1, cc, *g, k)
+
+
+def test_edge_cases(ctx):
+    for k in (3, 4, 5, 6):
+        t = ctx.table(k)
+        for g in (I.empty_graph(0), I.empty_graph(5), I.complete_digraph(k - 1),
+                  I.directed_path(k - 1), I.empty_graph(1)):
+            hist, total = _count(ctx, g, k)
+            assert total == 0 and hist.shape == (t.num_classes,) and not hist.any()
+        hist, total = _count(ctx, I.complete_digraph(k), k)
+        assert total == 1
+
+
+def test_bad_graphs_rejected(ctx):
+    cases = [
+        ([0, 1, 1], [0], M.MK_EGRAPH),            # loop
+        ([0, 2, 2], [1, 1], M.MK_EGRAPH),         # repeated arc
+        ([0, 1, 1], [5], M.MK_EGRAPH),            # head out of range
+        ([0, 2, 1], [1, 0], M.MK_EGRAPH),         # row_ptr decreases
+        ([1, 1, 1], [], M.MK_EGRAPH),             # row_ptr[0] != 0
+    ]
+    for rp, cl, status in cases:
+        with pytest.raises(M.MotifsError) as e:
+            ctx.load_graph(np.array(rp, np.int32), np.array(cl + [0], np.int32))
+        assert e.value.status == status
+    n = M.MK_MAX_VERTICES + 1
+    with pytest.raises(M.MotifsError) as e:
+        ctx.load_graph(np.zeros(n + 1, np.int32), np.zeros(1, np.int32))
+    assert e.value.status == M.MK_ERANGE
+
+
+def test_batch_equals_plain_and_replays(ctx):
+    k = 4
+    rng = np.random.default_rng(77)
+    graphs = [I.chung_lu_digraph(int(rng.integers(30, 300)), int(rng.integers(100, 900)), 2.2,
+                                 40, 0.2, rng) for _ in range(9)]
+    graphs.append(I.empty_graph(3))
+    t = ctx.table(k)
+    loaded = [ctx.load_graph(*g) for g in graphs]
+    try:
+        plain = [ctx.count(g, t)[0] for g in loaded]
+        hb, tb = ctx.count_batch(loaded, t)
+        for i in range(len(graphs)):
+            assert np.array_equal(hb[i], plain[i])
+            assert int(tb[i]) == int(plain[i].sum())
+        b = ctx.batch(loaded, t)
+        try:
+            for rep in range(3):
+                b.run()
+                h, _ = b.read()
+                assert np.array_equal(h, hb), rep
+                _ = ctx.count(loaded[0], t)   # eager work between replays
+        finally:
+            b.free()
+    finally:
+        for g in loaded:
+            g.free()
+
+
+def test_torch_buffer_and_stream(ctx):
+    torch = pytest.importorskip("torch")
+    k = 3
+    g = I.er_digraph(100, 400, np.random.default_rng(5))
+    gr = ctx.load_graph(*g)
+    t = ctx.table(k)
+    try:
+        b = ctx.batch([gr], t)
+        out = torch.zeros((1, t.num_classes), dtype=torch.int64, device="cuda:0")
+        s = torch.cuda.Stream()
+        b.run(out, stream=s)
+        s.synchronize()
+        h = out.cpu().numpy().astype(np.uint64)
+        ref, _ = ctx.count(gr, t)
+        assert np.array_equal(h[0], ref)
+        b.free()
+    finally:
+        gr.free()
