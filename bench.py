@@ -46,7 +46,10 @@ def _parse():
     p.add_argument("--no-plain", action="store_true", help="skip the plain comparator")
     p.add_argument("--cpu-graphs", type=int, default=10,
                    help="graphs of the batch the CPU oracle counts (bounded sample)")
-    p.add_argument("--split", type=int, default=0, help="split threshold (0: library default)")
+    p.add_argument("--split", type=int, default=0,
+                   help="k=6 split threshold (0: library default)")
+    p.add_argument("--k5-split", type=int, default=0,
+                   help="k=5 split threshold (0: library default)")
     p.add_argument("--waves-per-cu", type=int, default=0)
     return p.parse_args()
 
@@ -184,11 +187,13 @@ def main():
         w5 = I.workload_k5_batch()
         t5 = ctx.table(5)
         g5 = [ctx.load_graph(*g) for g in w5.graphs]
-        r5 = _timed_batch(ctx, M, g5, t5, max(2, args.steps // 3), 1, torch)
+        o5 = {"split_threshold": args.k5_split} if args.k5_split else {}
+        r5 = _timed_batch(ctx, M, g5, t5, max(2, args.steps // 3), 1, torch, **o5)
         s5 = int(r5["totals"].sum())
         k5 = {"workload": w5.name, "value": s5 / (r5["wall_s"] / max(2, args.steps // 3)),
               "subgraphs_per_step": s5, "kernel_ms": float(np.mean(r5["enum_ms"])),
-              "pass_ms": float(np.mean(r5["pass_ms"])), "table_build_ms": t5.build_ms}
+              "pass_ms": float(np.mean(r5["pass_ms"])), "table_build_ms": t5.build_ms,
+              "batch_stats": r5["stats"]}
         if not args.no_plain:
             p5 = _plain(ctx, g5, t5, 1, torch)
             k5["plain_value"] = s5 / p5

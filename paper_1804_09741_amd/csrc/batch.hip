@@ -49,7 +49,7 @@ struct mk_batch {
     hipStream_t last_stream = nullptr;
 };
 
-static constexpr uint64_t kDefaultSplit[7] = {0, 0, 1u << 30, 1u << 14, 1u << 15, 1u << 16, 1u << 16};
+static constexpr uint64_t kDefaultSplit[7] = {0, 0, 0, 1u << 30, 1u << 13, 1u << 14, 1u << 12};
 
 // ----------------------------------------------------------------- context
 
@@ -391,6 +391,55 @@ extern "C" int mk_batch_stats_get(const mk_batch *b, mk_batch_stats *out)
     out->ng = b->ng;
     return MK_OK;
 }
+
+// ------------------------------------------------- hooks for the server
+
+namespace mk {
+
+uint64_t batch_units(const mk_batch *b) { return b->units; }
+
+uint64_t batch_device_bytes(const mk_batch *b)
+{
+    uint64_t words = 0;
+    for (const mk_graph *g : b->graphs) {
+        const uint64_t n = (uint64_t)g->n, w = (n + 31) / 32;
+        words += 2 * n * w + n + 1 + (uint64_t)g->nnz_u;
+    }
+    return 4 * words + 8ull * b->total_slots + 4 * scan_tmp_words(b->total_slots) +
+           16ull * b->unit_cap + 8ull * b->ng * b->table->num_classes +
+           sizeof(DevGraph) * b->graphs.size() + 4 * kNumCounters;
+}
+
+// typed adjacency + plan into the batch's own histogram buffer
+int batch_prepare(mk_batch *b, hipStream_t stream)
+{
+    MK_HIP(hipSetDevice(b->ctx->device));
+    if (!b->d_hist_own) {
+        hipError_t e = hipMalloc(&b->d_hist_own, sizeof(unsigned long long) *
+                                                     std::max<size_t>((size_t)b->ng * b->table->num_classes, 1));
+        if (e != hipSuccess) return fail(MK_ENOMEM, "histogram allocation failed");
+    }
+    b->hist_last = b->d_hist_own;
+    b->last_stream = stream;
+    if (b->ng == 0) return MK_OK;
+    return batch_enqueue_prep(b, b->d_hist_own, stream);
+}
+
+// enumeration of units [begin, end) of a prepared batch
+int batch_enum_slice(mk_batch *b, uint32_t begin, uint32_t end, hipStream_t stream)
+{
+    if (b->ng == 0 || end <= begin) return MK_OK;
+    int rc = fill_u32(b->d_counters + kQueueHeads, 0, kQueues * kHeadStride, stream);
+    if (rc) return rc;
+    rc = fill_u32(b->d_counters + kSliceBegin, begin, 1, stream);
+    if (rc) return rc;
+    const int grid = (int)std::min<uint64_t>((uint64_t)b->grid, end - begin);
+    return launch_enum(b->k, b->d_graphs, b->d_units, b->unit_cap, end, b->d_counters,
+                       b->table->d_table, b->table->num_classes, b->d_hist_own, b->max_n,
+                       b->seg_cap, grid, b->lds_bytes, stream);
+}
+
+}  // namespace mk
 
 extern "C" int mk_batch_timing(mk_batch *b, double *pass_ms, double *enum_ms)
 {

@@ -2,7 +2,12 @@
 // O(1) class lookup (Section 3.2) and the histogram H_k (Problem Motifs-k).
 //
 // One 64-lane wavefront is one workgroup.  Waves are persistent: each takes
-// work units from a global queue (one atomic per unit) until it is empty.
+// work units from global queues until they are empty.  The unit list is cut
+// into eight ranges with a head each (one per XCD, on separate cache lines);
+// a wave starts on the range of its own XCD (workgroups are dealt to the
+// XCDs round-robin, so consecutive units of one graph stay in one L2) and
+// then helps the others.  Units are grabbed a few at a time, so the head
+// atomics stay far below their throughput limit.
 // A unit is a first-level ESU node (root v, first extension vertex w_i),
 // possibly restricted to a range of that node's children (hub splitting).
 //
@@ -44,6 +49,12 @@ namespace mk {
 
 constexpr int kAggRounds = 16;
 
+// members whose extension segment is kept: positions 0..k-3 (k >= 4; the
+// last two levels are flat), positions 0..1 for k = 3
+template <int K>
+constexpr int kSegments = K == 3 ? 2 : K - 2;
+constexpr int kScratchWords = 3 * kWave;
+
 template <int K>
 struct EnumState {
     static constexpr int OUTB = (K - 2) * (K - 1) + 1;
@@ -54,6 +65,10 @@ struct EnumState {
     int root;
     const int32_t *urow;
     const uint32_t *uadj;
+    const uint32_t *bits_out;   // row w bit u: arc w -> u
+    const uint32_t *bits_in;    // row w bit u: arc u -> w
+    int words;
+    uint32_t *scratch;          // 3 x 64 words of LDS per wave
     unsigned long long *hist;
     const uint32_t *table;
     uint32_t num_classes;
@@ -196,13 +211,155 @@ __device__ __forceinline__ void leaf(EnumState<K> &s, const int (&st)[K - 1], ui
     }
 }
 
+
+// Position in seg storage of element a of an extension list made of the
+// tails seg[q][st[q]:] (rem[q] elements each), q < NQ.
+template <int K, int NQ>
+__device__ __forceinline__ int ext_addr(const EnumState<K> &s, const int (&st)[K - 1],
+                                        const int (&rem)[NQ], int a)
+{
+    int addr = 0;
+    bool found = false;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        if (!found) {
+            if (a < rem[q]) {
+                addr = q * s.seg_cap + st[q] + a;
+                found = true;
+            } else {
+                a -= rem[q];
+            }
+        }
+    }
+    return addr;
+}
+
+// two-bit relation of w to u: bit0 arc w -> u, bit1 arc u -> w
+template <int K>
+__device__ __forceinline__ uint32_t pair_type(const EnumState<K> &s, uint32_t w, uint32_t u)
+{
+    const size_t word = (size_t)w * s.words + (u >> 5);
+    const uint32_t sh = u & 31u;
+    return ((s.bits_out[word] >> sh) & 1u) | (((s.bits_in[word] >> sh) & 1u) << 1);
+}
+
+// The last two ESU levels of a node X with k-2 members s_0..s_{k-3} and
+// extension list E, done flat across the wavefront without adding members.
+// Child w = E[i] (i in [jlo, jhi)) closes the k-sets X + {w, u} for
+//   (A) u = E[j], j > i: w's and u's relations to X come from their marks,
+//       the relation between w and u from the adjacency bit matrices (the
+//       pair test of Algorithm 2, Section 3.1);
+//   (B) u an exclusive neighbour of w (u > root, mark[u] == 0): u has no arc
+//       to X, its relation to w is the type of the entry in w's list (the
+//       neighbour-list scan of Algorithm 3).
+// (A) and (B) together are exactly ESU's extension list of the child w.
+template <int K>
+__device__ void last_two(EnumState<K> &s, const int (&st)[K - 1], uint32_t code, int jlo, int jhi)
+{
+    constexpr int NQ = K - 2;
+    constexpr int P1 = K - 2, P2 = K - 1;
+    constexpr int B_WU = (K - 2) * (K - 1) + (K - 2);  // bit of arc s_{k-2} -> s_{k-1}
+    constexpr int B_UW = (K - 1) * (K - 1) + (K - 2);  // bit of arc s_{k-1} -> s_{k-2}
+    const int lane = lane_id();
+    int rem[NQ];
+    int e = 0;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        rem[q] = s.len[q] - st[q];
+        e += rem[q];
+    }
+    const int hi = e < jhi ? e : jhi;
+    if (jlo >= hi) return;
+
+    // (A) pairs: row r = i - jlo holds A - r pairs, A = e - 1 - jlo
+    const int64_t A = e - 1 - jlo;
+    const int rows = hi - jlo;
+    const int64_t npairs = (int64_t)rows * A - (int64_t)rows * (rows - 1) / 2;
+    const float tA = 2.0f * (float)A + 1.0f;
+    for (int64_t base = 0; base < npairs; base += kWave) {
+        const int64_t p = base + lane;
+        const bool valid = p < npairs;
+        uint32_t c = 0;
+        if (valid) {
+            float disc = tA * tA - 8.0f * (float)p;
+            disc = disc > 0.f ? disc : 0.f;
+            int r = (int)((tA - sqrtf(disc)) * 0.5f);
+            r = r < 0 ? 0 : (r > rows - 1 ? rows - 1 : r);
+            while (r + 1 < rows && (int64_t)(r + 1) * A - (int64_t)(r + 1) * r / 2 <= p) ++r;
+            while (r > 0 && (int64_t)r * A - (int64_t)r * (r - 1) / 2 > p) --r;
+            const int64_t off = (int64_t)r * A - (int64_t)r * (r - 1) / 2;
+            const int i = jlo + r;
+            const int j = i + 1 + (int)(p - off);
+            if (j < e) {
+                const uint32_t w = s.seg[ext_addr<K, NQ>(s, st, rem, i)];
+                const uint32_t u = s.seg[ext_addr<K, NQ>(s, st, rem, j)];
+                const uint32_t t = pair_type<K>(s, w, u);
+                c = code | code_bits<K>(s.mark[w], P1) | code_bits<K>(s.mark[u], P2) |
+                    ((t & 1u) << B_WU) | ((t >> 1) << B_UW);
+            } else {
+                atomicAdd(s.errors, 1u);  // unreachable: row search keeps j < e
+            }
+        }
+        count_codes<K>(s, valid && c != 0, c);
+    }
+
+    // (B) exclusive neighbours, 64 children at a time: a lane-prefix sum of
+    // their degrees maps a flat index to (child, list position)
+    uint32_t *pre = s.scratch, *start = s.scratch + kWave, *cw = s.scratch + 2 * kWave;
+    for (int ib = jlo; ib < hi; ib += kWave) {
+        const int i = ib + lane;
+        int deg = 0, row = 0;
+        uint32_t wcode = 0;
+        if (i < hi) {
+            const uint32_t w = s.seg[ext_addr<K, NQ>(s, st, rem, i)];
+            row = s.urow[w];
+            deg = s.urow[w + 1] - row;
+            wcode = code_bits<K>(s.mark[w], P1);
+        }
+        int incl = deg;
+#pragma unroll
+        for (int d = 1; d < kWave; d <<= 1) {
+            const int o = __shfl_up(incl, d, kWave);
+            if (lane >= d) incl += o;
+        }
+        const int tot = uniform(__shfl(incl, kWave - 1, kWave));
+        pre[lane] = (uint32_t)incl;
+        start[lane] = (uint32_t)row;
+        cw[lane] = wcode;
+        __syncthreads();
+        for (int fb = 0; fb < tot; fb += kWave) {
+            const int f = fb + lane;
+            bool valid = f < tot;
+            uint32_t c = 0;
+            if (valid) {
+                int lo = 0, up = kWave - 1;
+                while (lo < up) {
+                    const int mid = (lo + up) >> 1;
+                    if ((int)pre[mid] > f) up = mid;
+                    else lo = mid + 1;
+                }
+                const int before = lo ? (int)pre[lo - 1] : 0;
+                const uint32_t ent = s.uadj[start[lo] + (uint32_t)(f - before)];
+                const int u = (int)(ent >> 2);
+                const uint32_t t = ent & 3u;
+                valid = u > s.root && s.mark[u] == 0u;
+                c = code | cw[lo] | ((t & 1u) << B_WU) | ((t >> 1) << B_UW);
+            }
+            count_codes<K>(s, valid, c);
+        }
+        __syncthreads();
+    }
+}
+
 // node with members s_0..s_D: visit children jlo..jhi-1 of its extension
 // list (the tails seg[q][st[q]:] for q <= D, in order)
 template <int K, int D>
 __device__ void visit(EnumState<K> &s, const int (&st)[K - 1], uint32_t code, int jlo, int jhi)
 {
-    if constexpr (D == K - 2) {
+    if constexpr (K == 3 && D == 1) {
         leaf<K>(s, st, code);
+    } else if constexpr (K >= 4 && D == K - 3) {
+        last_two<K>(s, st, code, jlo, jhi);
     } else {
         int rem[D + 1];
         int total = 0;
@@ -278,6 +435,10 @@ __global__ __launch_bounds__(kWave) void enum_kernel(const DevGraph *graphs, con
     s.mark = lds;
     s.seg = lds + max_n;
     s.seg_cap = seg_cap;
+    s.scratch = lds + max_n + kSegments<K> * seg_cap;
+    s.bits_out = nullptr;
+    s.bits_in = nullptr;
+    s.words = 0;
     s.table = table;
     s.num_classes = num_classes;
     s.errors = &counters[kErrors];
@@ -289,28 +450,46 @@ __global__ __launch_bounds__(kWave) void enum_kernel(const DevGraph *graphs, con
     __syncthreads();
     const uint32_t navail = counters[kNumUnits];
     const uint32_t cap = unit_cap < unit_end ? unit_cap : unit_end;
-    const uint32_t total = navail < cap ? navail : cap;
+    const uint32_t end = navail < cap ? navail : cap;
+    const uint32_t begin = counters[kSliceBegin];
+    const uint32_t span = end > begin ? end - begin : 0u;
+    // units per grab: about 1/16 of a wave's share, 1..16
+    uint32_t chunk = span / (gridDim.x * 16u);
+    chunk = chunk < 1u ? 1u : (chunk > 16u ? 16u : chunk);
     int cur = -1;
-    for (;;) {
-        uint32_t idx = 0;
-        if (lane_id() == 0) idx = atomicAdd(&counters[kQueueHead], 1u);
-        idx = (uint32_t)uniform((int)idx);
-        if (idx >= total) break;
-        const int4 u = units[idx];
-        const int gi = uniform(u.x);
-        if (gi != cur) {
-            s.urow = graphs[gi].urow;
-            s.uadj = graphs[gi].uadj;
-            s.hist = hist_base + (size_t)gi * num_classes;
-            cur = gi;
+    const int home = (int)(blockIdx.x % kQueues);
+    for (int q = 0; q < kQueues; ++q) {
+        const int x = (home + q) % kQueues;
+        const uint32_t lo = begin + (uint32_t)((uint64_t)span * x / kQueues);
+        const uint32_t hi = begin + (uint32_t)((uint64_t)span * (x + 1) / kQueues);
+        for (;;) {
+            uint32_t idx = 0;
+            if (lane_id() == 0) idx = atomicAdd(&counters[kQueueHeads + x * kHeadStride], chunk);
+            idx = lo + (uint32_t)uniform((int)idx);
+            if (idx >= hi) break;
+            const uint32_t stop = idx + chunk < hi ? idx + chunk : hi;
+            for (; idx < stop; ++idx) {
+                const int4 u = units[idx];
+                const int gi = uniform(u.x);
+                if (gi != cur) {
+                    s.urow = graphs[gi].urow;
+                    s.uadj = graphs[gi].uadj;
+                    s.bits_out = graphs[gi].bits_out;
+                    s.bits_in = graphs[gi].bits_in;
+                    s.words = graphs[gi].words;
+                    s.hist = hist_base + (size_t)gi * num_classes;
+                    cur = gi;
+                }
+                run_unit<K>(s, uniform(u.y), uniform(u.z), (uint32_t)uniform(u.w));
+            }
         }
-        run_unit<K>(s, uniform(u.y), uniform(u.z), (uint32_t)uniform(u.w));
     }
 }
 
 int enum_lds_bytes(int k, int max_n, int seg_cap)
 {
-    return (int)sizeof(uint32_t) * (max_n + (k - 1) * seg_cap);
+    const int segs = k == 3 ? 2 : k - 2;
+    return (int)sizeof(uint32_t) * (max_n + segs * seg_cap + kScratchWords);
 }
 
 template <int K>

@@ -77,13 +77,16 @@ constexpr uint32_t kFullChild = 0xFFFFFFFFu;
 
 // counters[] slots shared by planner and enumeration kernels
 enum Counter : int {
-    kQueueHead = 0,   // next unit to hand out
+    kSliceBegin = 0,  // first unit of the current launch (server slices; else 0)
     kNumUnits = 1,    // units written by the planner
     kErrors = 2,      // device-side consistency failures (must stay 0)
     kSplitPairs = 3,  // (root, first neighbour) pairs split at the second level
     kAdjOverflow = 4, // typed adjacency larger than reserved (must stay 0)
-    kNumCounters = 8,
+    kQueueHeads = 16, // kQueues heads, one per XCD, kHeadStride words apart
+    kNumCounters = 16 + 8 * 16,
 };
+constexpr int kQueues = 8;       // one queue per XCD of the MI355X
+constexpr int kHeadStride = 16;  // 64 bytes: one cache line per head
 
 // --------------------------------------------------------------- context
 
@@ -130,14 +133,22 @@ int launch_plan(int k, const DevGraph *d_graphs, int ng, int64_t max_nnz, uint32
 int enum_lds_bytes(int k, int max_n, int seg_cap);
 int enum_max_blocks_per_cu(int k, int lds_bytes, int *blocks);
 constexpr uint32_t kAllUnits = 0xFFFFFFFFu;
-// Units are taken from counters[kQueueHead] up to min(counters[kNumUnits],
-// unit_cap, unit_end).
+// The units [counters[kSliceBegin], min(counters[kNumUnits], unit_cap,
+// unit_end)) are cut into kQueues equal ranges; wave w starts on range
+// w % kQueues (the XCD the wave runs on) and then helps the others.  Heads
+// must be zero at launch.
 int launch_enum(int k, const DevGraph *d_graphs, const int4 *units, uint32_t unit_cap,
                 uint32_t unit_end, uint32_t *counters, const uint32_t *table, uint32_t num_classes,
                 unsigned long long *hist_base, int max_n, int seg_cap, int grid, int lds_bytes,
                 hipStream_t stream);
 
 void free_table(Table *t);
+
+// Prepared-batch hooks used by the request server.
+uint64_t batch_units(const mk_batch *b);
+uint64_t batch_device_bytes(const mk_batch *b);
+int batch_prepare(mk_batch *b, hipStream_t stream);
+int batch_enum_slice(mk_batch *b, uint32_t begin, uint32_t end, hipStream_t stream);
 
 }  // namespace mk
 

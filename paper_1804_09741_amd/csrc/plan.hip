@@ -3,13 +3,14 @@
 // The enumeration lists every connected k-set once from its smallest vertex
 // v (the root) by ESU: the root's extension list is E_v = {u in delta(v) :
 // u > v}; choosing its i-th vertex w_i gives the node (v, w_i), whose own
-// extension list is E_v[i+1:] followed by the neighbours of w_i that exceed v
-// and are not in delta(v).  A work unit is one such first-level node; the
-// subtree below it holds roughly C(L2, k-2) subgraphs when its extension list
-// has L2 vertices.  Nodes estimated above the split threshold (hubs of the
-// celebrity graphs of Section 3.1) are cut into ranges of their own children
-// instead, weighted C(L2-j-1, k-3) + 1 for child j, so that many wavefronts
-// share one hub.
+// extension list E2 is E_v[i+1:] followed by the neighbours of w_i that
+// exceed v and are not in delta(v) (L2 vertices).  A work unit is a range of
+// the children of such a node.  Child j (vertex x) of the node roots a
+// subtree of roughly C(L2 - j - 1 + d(x) - 1, k - 3) subgraphs: its own
+// extension list is the rest of E2 plus at most d(x) - 1 new neighbours.
+// Children are packed greedily into ranges whose estimated sum stays under
+// the split threshold, so hubs (the celebrity vertices of Section 3.1) are
+// shared by many wavefronts while sparse parts stay one unit per node.
 //
 // Slots are the entries of the typed adjacency lists (one per (v, u) with
 // u in delta(v)); a slot with u > v is a first-level node.  Pass one counts
@@ -100,27 +101,36 @@ __global__ __launch_bounds__(kPlanThreads) void plan_kernel(const DevGraph *grap
         else atomicOr(&counters[kErrors], 1u);
     };
     uint32_t cnt = 0;
-    if (K == 3 || choose_small(L2, K - 2) <= threshold) {
+    if (K == 3) {
         if (EMIT) put(0, kFullChild);
         cnt = 1;
     } else {
-        int j0 = 0;
+        // children j of (v, w_i) in extension order: E_v[i+1:] then the
+        // exclusive neighbours of w_i; greedy ranges of estimated cost
+        int j = 0, j0 = 0;
         uint64_t acc = 0;
-        for (int j = 0; j < L2; ++j) {
-            const uint64_t wj = choose_small(L2 - j - 1, K - 3) + 1;
-            if (j > j0 && acc + wj > threshold) {
+        auto child = [&](int x) {
+            const int dx = g.urow[x + 1] - g.urow[x];
+            const uint64_t cj = choose_small(L2 - j - 1 + dx - 1, K - 3) + 1;
+            if (j > j0 && acc + cj > threshold) {
                 if (EMIT) put(cnt, (uint32_t)j0 | ((uint32_t)j << 16));
                 ++cnt;
                 j0 = j;
                 acc = 0;
             }
-            acc += wj;
+            acc += cj;
+            ++j;
+        };
+        for (int t = first + i + 1; t < r1; ++t) child((int)(g.uadj[t] >> 2));
+        for (int t = g.urow[y]; t < g.urow[y + 1]; ++t) {
+            const int x = (int)(g.uadj[t] >> 2);
+            if (x > v && !adjacent(g, v, x)) child(x);
         }
         if (L2 > j0) {
             if (EMIT) put(cnt, (uint32_t)j0 | ((uint32_t)L2 << 16));
             ++cnt;
         }
-        if (!EMIT) atomicAdd(&counters[kSplitPairs], 1u);
+        if (!EMIT && cnt > 1) atomicAdd(&counters[kSplitPairs], 1u);
     }
     if (!EMIT) slot_cnt[slot] = cnt;
 }

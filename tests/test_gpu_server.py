@@ -1,0 +1,101 @@
+"""Continuous-batching server: every request's histogram equals the same
+request solved alone (tolerance 0), including requests submitted while
+others run; admission by footprint; timeouts and bad tickets."""
+
+import time
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1804_09741_amd import inputs as I
+from paper_1804_09741_amd import motifs as M
+
+from gpu_helpers import assert_hist_equals_oracle
+
+pytestmark = pytest.mark.gpu
+
+
+def _requests(seed, count, n_max=400):
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(count):
+        k = int(rng.integers(3, 7))
+        n = int(rng.integers(30, n_max))
+        m = int(round(n * rng.uniform(2.0, 4.0)))
+        cap = 40 if k <= 5 else 15
+        out.append((k, I.chung_lu_digraph(n, m, float(rng.uniform(2.0, 2.6)), cap, 0.1, rng)))
+    return out
+
+
+def test_served_equals_alone(ctx):
+    reqs = _requests(1, 24)
+    graphs = [ctx.load_graph(*g) for _, g in reqs]
+    alone = [ctx.count(g, ctx.table(k))[0] for (k, _), g in zip(reqs, graphs)]
+    srv = ctx.server(tick_units=64)
+    try:
+        # first half at once, second half while the first half runs
+        tickets = [srv.submit(g, k) for (k, _), g in zip(reqs[:12], graphs[:12])]
+        first = srv.wait(tickets[0], reqs[0][0])
+        tickets += [srv.submit(g, k) for (k, _), g in zip(reqs[12:], graphs[12:])]
+        results = [first] + [srv.wait(t, k) for t, (k, _) in zip(tickets[1:], reqs[1:])]
+    finally:
+        srv.stop()
+    for (hist, times), ref, (k, g) in zip(results, alone, reqs):
+        assert np.array_equal(hist, ref)
+        assert times["submit_us"] <= times["admit_us"] <= times["done_us"]
+    for (hist, _), (k, g) in list(zip(results, reqs))[:6]:
+        assert_hist_equals_oracle(hist, ctx.table(k).class_codes(), *g, k)
+    for g in graphs:
+        g.free()
+
+
+def test_admission_by_footprint(ctx):
+    reqs = _requests(2, 6)
+    graphs = [ctx.load_graph(*g) for _, g in reqs]
+    biggest = max(g.footprint(k) for (k, _), g in zip(reqs, graphs))
+    # budget for about one request at a time: all still complete, in order
+    srv = ctx.server(hbm_budget_bytes=biggest + 1024, max_slots=2, tick_units=16)
+    try:
+        tickets = [srv.submit(g, k) for (k, _), g in zip(reqs, graphs)]
+        res = [srv.wait(t, k) for t, (k, _) in zip(tickets, reqs)]
+        for (hist, _), (k, _), g in zip(res, reqs, graphs):
+            assert np.array_equal(hist, ctx.count(g, ctx.table(k))[0])
+        with pytest.raises(M.MotifsError) as e:
+            tiny = ctx.server(hbm_budget_bytes=1024)
+            try:
+                tiny.submit(graphs[0], reqs[0][0])
+            finally:
+                tiny.stop()
+        assert e.value.status == M.MK_EBUSY
+    finally:
+        srv.stop()
+        for g in graphs:
+            g.free()
+
+
+def test_timeout_and_unknown_ticket(ctx):
+    big = ctx.load_graph(*I.k5_batch_graph(0))
+    small = ctx.load_graph(*I.er_digraph(50, 150, np.random.default_rng(3)))
+    ctx.table(5)
+    srv = ctx.server(max_slots=1)
+    try:
+        t1 = srv.submit(big, 5)
+        t2 = srv.submit(small, 3)
+        # one slot: the second request stays queued behind the first
+        with pytest.raises(M.MotifsError) as e:
+            srv.wait(t2, 3, timeout_ms=0)
+        assert e.value.status == M.MK_ETIMEDOUT
+        h1, _ = srv.wait(t1, 5)
+        h2, _ = srv.wait(t2, 3)
+        assert h1.sum() > 0 and h2.sum() > 0
+        with pytest.raises(M.MotifsError) as e:
+            srv.wait(t2, 3, timeout_ms=0)
+        assert e.value.status == M.MK_ENOTFOUND
+        with pytest.raises(M.MotifsError) as e:
+            srv.submit(small, 7)
+        assert e.value.status == M.MK_ERANGE
+    finally:
+        srv.stop()
+        big.free()
+        small.free()
