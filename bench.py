@@ -51,6 +51,10 @@ def _parse():
     p.add_argument("--k5-split", type=int, default=0,
                    help="k=5 split threshold (0: library default)")
     p.add_argument("--waves-per-cu", type=int, default=0)
+    p.add_argument("--serve", type=int, default=0, metavar="R",
+                   help="also run the serving workload with R requests (0: skip)")
+    p.add_argument("--serve-load", type=float, default=0.7,
+                   help="open-loop arrival rate as a fraction of the measured capacity")
     return p.parse_args()
 
 
@@ -98,6 +102,76 @@ def _plain(ctx, graphs, table, steps, torch):
     finally:
         for b in bs:
             b.free()
+
+
+def _serving(ctx, M, I, R, load, torch):
+    """Serving workload: R (graph, k) requests, graphs resident on the device.
+
+    1. plain: one request per launch, first come first served (mk_count);
+    2. served, closed loop: all requests submitted at once -> capacity;
+    3. served, open loop: Poisson arrivals at `load` x capacity -> p50/p99 of
+       (completion - submission) as timed by the server.
+    Every served histogram must equal the plain one.
+    """
+    import threading
+
+    import numpy as np
+
+    reqs = I.serving_requests(count=R)
+    _log("serving: %d requests generated" % R)
+    for k in (3, 4, 5, 6):
+        ctx.table(k)
+    graphs = [ctx.load_graph(*r.graph) for r in reqs]
+    tables = {k: ctx.table(k) for k in (3, 4, 5, 6)}
+    t0 = time.perf_counter()
+    plain = [ctx.count(g, tables[r.k])[0] for g, r in zip(graphs, reqs)]
+    plain_s = time.perf_counter() - t0
+    total = int(sum(int(h.sum()) for h in plain))
+    _log("serving: plain FIFO %.2f s, %d subgraphs" % (plain_s, total))
+
+    srv = ctx.server()
+    try:
+        t0 = time.perf_counter()
+        tickets = [srv.submit(g, r.k) for g, r in zip(graphs, reqs)]
+        burst = [srv.wait(t, r.k) for t, r in zip(tickets, reqs)]
+        burst_s = time.perf_counter() - t0
+        same = all(np.array_equal(h, p) for (h, _), p in zip(burst, plain))
+        _log("serving: closed loop %.2f s" % burst_s)
+        rate = load * R / burst_s
+        gaps = np.random.default_rng(55).exponential(1.0 / rate, size=R)
+        arrivals = np.cumsum(gaps) - gaps[0]
+        tickets = [None] * R
+
+        def submitter():
+            start = time.perf_counter()
+            for i in range(R):
+                delay = arrivals[i] - (time.perf_counter() - start)
+                if delay > 0:
+                    time.sleep(delay)
+                tickets[i] = srv.submit(graphs[i], reqs[i].k)
+
+        th = threading.Thread(target=submitter)
+        t0 = time.perf_counter()
+        th.start()
+        lat = []
+        for i in range(R):
+            while tickets[i] is None:
+                time.sleep(0.0005)
+            h, tm = srv.wait(tickets[i], reqs[i].k)
+            same &= bool(np.array_equal(h, plain[i]))
+            lat.append((tm["done_us"] - tm["submit_us"]) / 1000.0)
+        th.join()
+        open_s = time.perf_counter() - t0
+    finally:
+        srv.stop()
+    for g in graphs:
+        g.free()
+    return {"requests": R, "subgraphs": total, "value": total / burst_s,
+            "plain_value": total / plain_s, "speedup_vs_plain": plain_s / burst_s,
+            "capacity_req_per_s": R / burst_s, "open_loop_rate_req_per_s": rate,
+            "open_loop_throughput": total / open_s,
+            "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+            "served_equals_alone": bool(same)}
 
 
 def main():
@@ -201,6 +275,8 @@ def main():
         _log("k=5 batch: %.3f ms/step" % k5["pass_ms"])
         for g in g5:
             g.free()
+    if args.serve:
+        out["serving"] = _serving(ctx, M, I, args.serve, args.serve_load, torch)
     ctx.close()
     print(json.dumps(out))
 

@@ -39,7 +39,7 @@ struct mk_batch {
 
     int max_n = 0, max_words = 0, seg_cap = 0;
     int64_t max_nnz = 0;
-    int grid = 0, lds_bytes = 0;
+    int grid = 0, max_grid = 0, lds_bytes = 0;
     uint64_t units = 0, split_pairs = 0;
 
     hipEvent_t ev[3] = {};  // pass start, enumeration start, enumeration end
@@ -49,7 +49,7 @@ struct mk_batch {
     hipStream_t last_stream = nullptr;
 };
 
-static constexpr uint64_t kDefaultSplit[7] = {0, 0, 0, 1u << 30, 1u << 13, 1u << 14, 1u << 12};
+static constexpr uint64_t kDefaultSplit[7] = {0, 0, 0, 1u << 30, 1u << 12, 1u << 12, 1u << 12};
 
 // ----------------------------------------------------------------- context
 
@@ -142,7 +142,7 @@ static int batch_enqueue_prep(mk_batch *b, unsigned long long *hist, hipStream_t
     if (rc) return rc;
     return launch_plan(b->k, b->d_graphs, b->ng, b->max_nnz, b->total_slots, b->d_slot_cnt,
                        b->d_slot_off, b->d_scan_tmp, b->d_units, b->unit_cap,
-                       b->opts.split_threshold, b->d_counters, stream);
+                       b->opts.split_threshold, (uint32_t)b->max_grid, b->d_counters, stream);
 }
 
 // the enumeration kernel between two timing events
@@ -256,6 +256,13 @@ extern "C" int mk_batch_create(mk_ctx *ctx, const mk_graph *const *gs, int32_t n
     BAIL_HIP(hipMalloc(&b->d_counters, sizeof(uint32_t) * kNumCounters));
     for (hipEvent_t &e : b->ev) BAIL_HIP(hipEventCreate(&e));
 
+    int per_cu = 0;
+    rc = enum_max_blocks_per_cu(b->k, b->lds_bytes, &per_cu);
+    if (rc) return bail(rc);
+    if (b->opts.waves_per_cu > 0) per_cu = std::min(per_cu, b->opts.waves_per_cu);
+    per_cu = std::max(per_cu, 1);
+    b->max_grid = per_cu * ctx->num_cus;
+
     // sizing pass: typed adjacency + unit counts only
     rc = fill_u32(b->d_counters, 0, kNumCounters, ctx->stream);
     if (!rc)
@@ -264,7 +271,7 @@ extern "C" int mk_batch_create(mk_ctx *ctx, const mk_graph *const *gs, int32_t n
     if (!rc)
         rc = launch_plan(b->k, b->d_graphs, ng, b->max_nnz, b->total_slots, b->d_slot_cnt,
                          b->d_slot_off, b->d_scan_tmp, nullptr, 0, b->opts.split_threshold,
-                         b->d_counters, ctx->stream);
+                         (uint32_t)b->max_grid, b->d_counters, ctx->stream);
     if (rc) return bail(rc);
     uint32_t cnt[kNumCounters];
     BAIL_HIP(hipMemcpyAsync(cnt, b->d_counters, sizeof(cnt), hipMemcpyDeviceToHost, ctx->stream));
@@ -276,12 +283,7 @@ extern "C" int mk_batch_create(mk_ctx *ctx, const mk_graph *const *gs, int32_t n
     b->unit_cap = std::max<uint32_t>(cnt[kNumUnits], 1);
     BAIL_HIP(hipMalloc(&b->d_units, sizeof(int4) * b->unit_cap));
 
-    int per_cu = 0;
-    rc = enum_max_blocks_per_cu(b->k, b->lds_bytes, &per_cu);
-    if (rc) return bail(rc);
-    if (b->opts.waves_per_cu > 0) per_cu = std::min(per_cu, b->opts.waves_per_cu);
-    per_cu = std::max(per_cu, 1);
-    b->grid = (int)std::min<uint64_t>((uint64_t)per_cu * ctx->num_cus, std::max<uint64_t>(b->units, 1));
+    b->grid = (int)std::min<uint64_t>((uint64_t)b->max_grid, std::max<uint64_t>(b->units, 1));
 #undef BAIL_HIP
     *out = b;
     return MK_OK;

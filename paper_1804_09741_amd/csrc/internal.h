@@ -82,6 +82,7 @@ enum Counter : int {
     kErrors = 2,      // device-side consistency failures (must stay 0)
     kSplitPairs = 3,  // (root, first neighbour) pairs split at the second level
     kAdjOverflow = 4, // typed adjacency larger than reserved (must stay 0)
+    kEstTotal = 6,    // words 6-7: u64 estimated total cost (planner)
     kQueueHeads = 16, // kQueues heads, one per XCD, kHeadStride words apart
     kNumCounters = 16 + 8 * 16,
 };
@@ -123,10 +124,12 @@ int launch_typed_csr(const DevGraph *d_graphs, int ng, int max_n, int max_words,
                      uint64_t bits_words_total, uint32_t *bits_base, uint32_t *counters,
                      hipStream_t stream);
 
-// Work-unit planner: counts per slot, scan, emit.  Writes counters[kNumUnits].
+// Work-unit planner: cost estimate, counts per slot, scan, emit (units ==
+// nullptr: sizing only).  Writes counters[kNumUnits].  The split threshold
+// is max(split_threshold, estimated total / (waves * 16)).
 int launch_plan(int k, const DevGraph *d_graphs, int ng, int64_t max_nnz, uint32_t total_slots,
                 uint32_t *slot_cnt, uint32_t *slot_off, uint32_t *scan_tmp, int4 *units,
-                uint32_t unit_cap, uint64_t split_threshold, uint32_t *counters,
+                uint32_t unit_cap, uint64_t split_threshold, uint32_t waves, uint32_t *counters,
                 hipStream_t stream);
 
 // Enumeration + code + lookup + histogram over the queued units.

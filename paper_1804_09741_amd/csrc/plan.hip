@@ -65,116 +65,160 @@ __device__ __forceinline__ bool adjacent(const DevGraph &g, int v, int x)
     return ((g.bits_out[w] | g.bits_in[w]) >> (x & 31)) & 1u;
 }
 
-template <int K, bool EMIT>
+// Pass kinds of the planner kernel.
+enum PlanPass : int { kEstimate = 0, kCount = 1, kEmit = 2 };
+
+// Split threshold of the count and emit passes: the floor, raised so that
+// the estimated total work makes about kUnitsPerWave units per enumeration
+// wave (large batches need little splitting, single graphs need more).
+constexpr uint64_t kUnitsPerWave = 16;
+
+__device__ __forceinline__ uint64_t effective_threshold(const uint32_t *counters, uint64_t floor_t,
+                                                        uint32_t waves)
+{
+    const uint64_t total = *reinterpret_cast<const unsigned long long *>(counters + kEstTotal);
+    const uint64_t adaptive = total / ((uint64_t)waves * kUnitsPerWave + 1);
+    return adaptive > floor_t ? adaptive : floor_t;
+}
+
+template <int K, int PASS>
 __global__ __launch_bounds__(kPlanThreads) void plan_kernel(const DevGraph *graphs,
                                                             uint32_t *slot_cnt,
                                                             const uint32_t *slot_off, int4 *units,
-                                                            uint32_t unit_cap, uint64_t threshold,
-                                                            uint32_t *counters)
+                                                            uint32_t unit_cap, uint64_t floor_t,
+                                                            uint32_t waves, uint32_t *counters)
 {
     const int gi = blockIdx.y;
     const DevGraph &g = graphs[gi];
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (g.n == 0 || e >= min(g.urow[g.n], (int)g.nnz_cap)) return;
-    const uint32_t slot = g.slot_base + (uint32_t)e;
-    const int v = owner_of(g.urow, g.n, e);
-    const int y = (int)(g.uadj[e] >> 2);
-    if (y <= v) {
-        if (!EMIT) slot_cnt[slot] = 0;
-        return;
-    }
-    const int r1 = g.urow[v + 1];
-    const int first = first_above(g.uadj, g.urow[v], r1, v);
-    const int i = e - first;
-    const int ext_v = r1 - first;
-    int fresh = 0;
-    for (int t = g.urow[y]; t < g.urow[y + 1]; ++t) {
-        const int x = (int)(g.uadj[t] >> 2);
-        if (x > v && !adjacent(g, v, x)) ++fresh;
-    }
-    const int L2 = ext_v - i - 1 + fresh;
-    uint32_t base = 0;
-    if (EMIT) base = slot_off[slot];
-    auto put = [&](uint32_t r, uint32_t w) {
-        const uint32_t idx = base + r;
-        if (idx < unit_cap) units[idx] = make_int4(gi, v, i, (int)w);
-        else atomicOr(&counters[kErrors], 1u);
-    };
-    uint32_t cnt = 0;
-    if (K == 3) {
-        if (EMIT) put(0, kFullChild);
-        cnt = 1;
-    } else {
-        // children j of (v, w_i) in extension order: E_v[i+1:] then the
-        // exclusive neighbours of w_i; greedy ranges of estimated cost
-        int j = 0, j0 = 0;
-        uint64_t acc = 0;
-        auto child = [&](int x) {
-            const int dx = g.urow[x + 1] - g.urow[x];
-            const uint64_t cj = choose_small(L2 - j - 1 + dx - 1, K - 3) + 1;
-            if (j > j0 && acc + cj > threshold) {
-                if (EMIT) put(cnt, (uint32_t)j0 | ((uint32_t)j << 16));
-                ++cnt;
-                j0 = j;
-                acc = 0;
+    uint64_t est = 0;  // kEstimate: this slot's estimated cost
+    const bool live = g.n > 0 && e < min(g.urow[g.n], (int)g.nnz_cap);
+    const uint64_t threshold = PASS == kEstimate ? ~0ull : effective_threshold(counters, floor_t, waves);
+    if (live) {
+        const uint32_t slot = g.slot_base + (uint32_t)e;
+        const int v = owner_of(g.urow, g.n, e);
+        const int y = (int)(g.uadj[e] >> 2);
+        uint32_t cnt = 0;
+        if (y > v) {
+            const int r1 = g.urow[v + 1];
+            const int first = first_above(g.uadj, g.urow[v], r1, v);
+            const int i = e - first;
+            const int ext_v = r1 - first;
+            int fresh = 0;
+            for (int t = g.urow[y]; t < g.urow[y + 1]; ++t) {
+                const int x = (int)(g.uadj[t] >> 2);
+                if (x > v && !adjacent(g, v, x)) ++fresh;
             }
-            acc += cj;
-            ++j;
-        };
-        for (int t = first + i + 1; t < r1; ++t) child((int)(g.uadj[t] >> 2));
-        for (int t = g.urow[y]; t < g.urow[y + 1]; ++t) {
-            const int x = (int)(g.uadj[t] >> 2);
-            if (x > v && !adjacent(g, v, x)) child(x);
+            const int L2 = ext_v - i - 1 + fresh;
+            uint32_t base = 0;
+            if (PASS == kEmit) base = slot_off[slot];
+            auto put = [&](uint32_t r, uint32_t w) {
+                const uint32_t idx = base + r;
+                if (idx < unit_cap) units[idx] = make_int4(gi, v, i, (int)w);
+                else atomicOr(&counters[kErrors], 1u);
+            };
+            if (K == 3) {
+                if (PASS == kEmit) put(0, kFullChild);
+                cnt = 1;
+                est = (uint64_t)L2 + 1;
+            } else {
+                // children j of (v, w_i) in extension order: E_v[i+1:] then
+                // the exclusive neighbours of w_i; greedy ranges of estimated
+                // cost
+                int j = 0, j0 = 0;
+                uint64_t acc = 0;
+                auto child = [&](int x) {
+                    const int dx = g.urow[x + 1] - g.urow[x];
+                    const uint64_t cj = choose_small(L2 - j - 1 + dx - 1, K - 3) + 1;
+                    est += cj;
+                    if (j > j0 && acc + cj > threshold) {
+                        if (PASS == kEmit) put(cnt, (uint32_t)j0 | ((uint32_t)j << 16));
+                        ++cnt;
+                        j0 = j;
+                        acc = 0;
+                    }
+                    acc += cj;
+                    ++j;
+                };
+                for (int t = first + i + 1; t < r1; ++t) child((int)(g.uadj[t] >> 2));
+                for (int t = g.urow[y]; t < g.urow[y + 1]; ++t) {
+                    const int x = (int)(g.uadj[t] >> 2);
+                    if (x > v && !adjacent(g, v, x)) child(x);
+                }
+                if (L2 > j0) {
+                    if (PASS == kEmit) put(cnt, (uint32_t)j0 | ((uint32_t)L2 << 16));
+                    ++cnt;
+                }
+                if (PASS == kCount && cnt > 1) atomicAdd(&counters[kSplitPairs], 1u);
+            }
         }
-        if (L2 > j0) {
-            if (EMIT) put(cnt, (uint32_t)j0 | ((uint32_t)L2 << 16));
-            ++cnt;
-        }
-        if (!EMIT && cnt > 1) atomicAdd(&counters[kSplitPairs], 1u);
+        if (PASS == kCount) slot_cnt[slot] = cnt;
     }
-    if (!EMIT) slot_cnt[slot] = cnt;
+    if (PASS == kEstimate) {
+        // workgroup sum, one 64-bit atomic per workgroup
+        __shared__ unsigned long long part[kPlanThreads / kWave];
+        unsigned long long x = est;
+#pragma unroll
+        for (int d = kWave / 2; d > 0; d >>= 1) x += __shfl_down(x, d, kWave);
+        if (threadIdx.x % kWave == 0) part[threadIdx.x / kWave] = x;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            unsigned long long sum = 0;
+            for (int w = 0; w < kPlanThreads / kWave; ++w) sum += part[w];
+            if (sum) atomicAdd(reinterpret_cast<unsigned long long *>(counters + kEstTotal), sum);
+        }
+    }
 }
 
 template <int K>
 static int plan_k(const DevGraph *d_graphs, int ng, int64_t max_nnz, uint32_t total_slots,
                   uint32_t *slot_cnt, uint32_t *slot_off, uint32_t *scan_tmp, int4 *units,
-                  uint32_t unit_cap, uint64_t threshold, uint32_t *counters, hipStream_t stream)
+                  uint32_t unit_cap, uint64_t threshold, uint32_t waves, uint32_t *counters,
+                  hipStream_t stream)
 {
     const dim3 grid((unsigned)((max_nnz + kPlanThreads - 1) / kPlanThreads > 0
                                    ? (max_nnz + kPlanThreads - 1) / kPlanThreads
                                    : 1),
                     (unsigned)ng);
-    hipLaunchKernelGGL((plan_kernel<K, false>), grid, dim3(kPlanThreads), 0, stream, d_graphs,
-                       slot_cnt, slot_off, units, unit_cap, threshold, counters);
+    int rc = fill_u32(counters + kEstTotal, 0, 2, stream);
+    if (rc != MK_OK) return rc;
+    if (K > 3) {
+        hipLaunchKernelGGL((plan_kernel<K, kEstimate>), grid, dim3(kPlanThreads), 0, stream,
+                           d_graphs, slot_cnt, slot_off, units, unit_cap, threshold, waves,
+                           counters);
+        MK_HIP(hipGetLastError());
+    }
+    hipLaunchKernelGGL((plan_kernel<K, kCount>), grid, dim3(kPlanThreads), 0, stream, d_graphs,
+                       slot_cnt, slot_off, units, unit_cap, threshold, waves, counters);
     MK_HIP(hipGetLastError());
-    int rc = scan_u32(slot_cnt, slot_off, total_slots, 0, &counters[kNumUnits], scan_tmp, stream);
+    rc = scan_u32(slot_cnt, slot_off, total_slots, 0, &counters[kNumUnits], scan_tmp, stream);
     if (rc != MK_OK) return rc;
     if (!units) return MK_OK;  // sizing pass
-    hipLaunchKernelGGL((plan_kernel<K, true>), grid, dim3(kPlanThreads), 0, stream, d_graphs,
-                       slot_cnt, slot_off, units, unit_cap, threshold, counters);
+    hipLaunchKernelGGL((plan_kernel<K, kEmit>), grid, dim3(kPlanThreads), 0, stream, d_graphs,
+                       slot_cnt, slot_off, units, unit_cap, threshold, waves, counters);
     MK_HIP(hipGetLastError());
     return MK_OK;
 }
 
 int launch_plan(int k, const DevGraph *d_graphs, int ng, int64_t max_nnz, uint32_t total_slots,
                 uint32_t *slot_cnt, uint32_t *slot_off, uint32_t *scan_tmp, int4 *units,
-                uint32_t unit_cap, uint64_t split_threshold, uint32_t *counters,
+                uint32_t unit_cap, uint64_t split_threshold, uint32_t waves, uint32_t *counters,
                 hipStream_t stream)
 {
     if (ng <= 0) return MK_OK;
     switch (k) {
     case 3:
         return plan_k<3>(d_graphs, ng, max_nnz, total_slots, slot_cnt, slot_off, scan_tmp, units,
-                         unit_cap, split_threshold, counters, stream);
+                         unit_cap, split_threshold, waves, counters, stream);
     case 4:
         return plan_k<4>(d_graphs, ng, max_nnz, total_slots, slot_cnt, slot_off, scan_tmp, units,
-                         unit_cap, split_threshold, counters, stream);
+                         unit_cap, split_threshold, waves, counters, stream);
     case 5:
         return plan_k<5>(d_graphs, ng, max_nnz, total_slots, slot_cnt, slot_off, scan_tmp, units,
-                         unit_cap, split_threshold, counters, stream);
+                         unit_cap, split_threshold, waves, counters, stream);
     case 6:
         return plan_k<6>(d_graphs, ng, max_nnz, total_slots, slot_cnt, slot_off, scan_tmp, units,
-                         unit_cap, split_threshold, counters, stream);
+                         unit_cap, split_threshold, waves, counters, stream);
     default: return fail(MK_ERANGE, "k=%d outside 3..6", k);
     }
 }
