@@ -51,6 +51,9 @@ def _parse():
     p.add_argument("--k5-split", type=int, default=0,
                    help="k=5 split threshold (0: library default)")
     p.add_argument("--waves-per-cu", type=int, default=0)
+    p.add_argument("--copy-mib", type=int, default=0,
+                   help="also run one device-to-device copy of this many MiB (a kernel of "
+                        "known traffic, to scale hardware byte counters)")
     p.add_argument("--serve", type=int, default=0, metavar="R",
                    help="also run the serving workload with R requests (0: skip)")
     p.add_argument("--serve-load", type=float, default=0.7,
@@ -187,6 +190,13 @@ def main():
     from paper_1804_09741_amd import motifs as M
 
     ctx = M.Context(0)
+    if args.copy_mib:
+        n = args.copy_mib * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     w = I.workload_k6_batch()
     _log("k=6 batch generated; building the k=6 table")
     t6 = ctx.table(6)

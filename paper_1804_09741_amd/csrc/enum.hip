@@ -36,11 +36,12 @@
 // At the last level every extension vertex u closes one k-subgraph: lanes
 // take one u each, read mark[u] and form the code with two shifts and an OR
 // -- this replaces the pair tests of Algorithms 2-5 (Section 3.1): the edges
-// of G[S] are known from the marks the members left.  Lanes holding equal
-// codes are merged with ballots (all lanes of a node share k-1 members, so
-// few distinct codes occur), then each distinct code is looked up in the
-// code -> class table once and added to the graph's histogram with one
-// 64-bit atomic.
+// of G[S] are known from the marks the members left.  Codes go into a small
+// per-wave LDS hash of pending counts (one ballot round first merges the
+// lanes that share the first lane's code): the same few shapes recur across
+// nodes, so the hash absorbs most of them, and only its flush looks codes up
+// in the code -> class table and adds to the graph's histogram with 64-bit
+// atomics.
 #include <climits>
 
 #include "internal.h"
@@ -54,6 +55,12 @@ constexpr int kAggRounds = 16;
 template <int K>
 constexpr int kSegments = K == 3 ? 2 : K - 2;
 constexpr int kScratchWords = 3 * kWave;
+// Per-wave hash of pending (code, count) pairs; flushed to the histogram when
+// half full, at the end of a unit once a quarter full, on a graph switch and
+// at exit.
+constexpr int kHashSlots = 256;
+constexpr int kHashProbes = 8;
+constexpr uint32_t kEmpty = 0xFFFFFFFFu;
 
 template <int K>
 struct EnumState {
@@ -69,6 +76,9 @@ struct EnumState {
     const uint32_t *bits_in;    // row w bit u: arc u -> w
     int words;
     uint32_t *scratch;          // 3 x 64 words of LDS per wave
+    uint32_t *hkey;             // per-wave LDS hash: code (kEmpty = free)
+    uint32_t *hcnt;             //   and its pending count
+    int hused;                  // keys in the hash (wave-uniform)
     unsigned long long *hist;
     const uint32_t *table;
     uint32_t num_classes;
@@ -144,34 +154,74 @@ __device__ __forceinline__ void pop(EnumState<K> &s, int x)
     __syncthreads();
 }
 
-// count one code per valid lane
+// add n to the histogram bin of code (table lookup + global 64-bit atomic)
+template <int K>
+__device__ __forceinline__ void add_global(EnumState<K> &s, uint32_t code, uint32_t n)
+{
+    const uint32_t id = s.table[code];
+    if (id < s.num_classes) atomicAdd(&s.hist[id], (unsigned long long)n);
+    else atomicAdd(s.errors, 1u);
+}
+
+// move the wave's pending counts to the histogram and empty the hash
+template <int K>
+__device__ __forceinline__ void flush_hash(EnumState<K> &s)
+{
+    __syncthreads();
+    for (int i = lane_id(); i < kHashSlots; i += kWave) {
+        const uint32_t key = s.hkey[i];
+        if (key != kEmpty) {
+            add_global<K>(s, key, s.hcnt[i]);
+            s.hkey[i] = kEmpty;
+            s.hcnt[i] = 0u;
+        }
+    }
+    s.hused = 0;
+    __syncthreads();
+}
+
+// count one code per valid lane.  One ballot round merges the lanes that
+// share the first lane's code; every remaining code goes into the wave's
+// LDS hash (linear probing; a lane that finds no slot within kHashProbes
+// goes straight to the histogram).
 template <int K>
 __device__ __forceinline__ void count_codes(EnumState<K> &s, bool valid, uint32_t code)
 {
     const int lane = lane_id();
-    unsigned long long act = __ballot(valid);
-    uint32_t n = 0;
-    bool lead = false;
-#pragma unroll 1
-    for (int r = 0; r < kAggRounds && act; ++r) {
-        const int l = __builtin_ctzll(act);
-        const uint32_t c0 = (uint32_t)__builtin_amdgcn_readlane((int)code, l);
-        const unsigned long long eq = __ballot(code == c0) & act;
-        if (lane == l) {
-            lead = true;
-            n = (uint32_t)__popcll(eq);
+    const unsigned long long act = __ballot(valid);
+    if (!act) return;
+    const int l = __builtin_ctzll(act);
+    const uint32_t c0 = (uint32_t)__builtin_amdgcn_readlane((int)code, l);
+    const unsigned long long eq = __ballot(code == c0) & act;
+    bool mine = valid && !((eq >> lane) & 1ull);
+    uint32_t n = 1;
+    if (lane == l) {
+        mine = true;
+        n = (uint32_t)__popcll(eq);
+    }
+    bool fresh = false;
+    if (mine) {
+        uint32_t h = (code * 2654435761u) >> (32 - 8);
+        bool done = false;
+        for (int p = 0; p < kHashProbes && !done; ++p) {
+            uint32_t k = s.hkey[h];
+            if (k == kEmpty) {
+                k = atomicCAS(&s.hkey[h], kEmpty, code);
+                if (k == kEmpty) {
+                    fresh = true;
+                    k = code;
+                }
+            }
+            if (k == code) {
+                atomicAdd(&s.hcnt[h], n);
+                done = true;
+            }
+            h = (h + 1) & (kHashSlots - 1);
         }
-        act &= ~eq;
+        if (!done) add_global<K>(s, code, n);
     }
-    if ((act >> lane) & 1ull) {
-        lead = true;
-        n = 1;
-    }
-    if (lead) {
-        const uint32_t id = s.table[code];
-        if (id < s.num_classes) atomicAdd(&s.hist[id], (unsigned long long)n);
-        else atomicAdd(s.errors, 1u);
-    }
+    s.hused += __popcll(__ballot(fresh));
+    if (s.hused > kHashSlots / 2) flush_hash<K>(s);
 }
 
 // last level: members s_0..s_{K-2}; every extension vertex closes a k-set
@@ -436,6 +486,13 @@ __global__ __launch_bounds__(kWave) void enum_kernel(const DevGraph *graphs, con
     s.seg = lds + max_n;
     s.seg_cap = seg_cap;
     s.scratch = lds + max_n + kSegments<K> * seg_cap;
+    s.hkey = s.scratch + kScratchWords;
+    s.hcnt = s.hkey + kHashSlots;
+    s.hused = 0;
+    for (int i = lane_id(); i < kHashSlots; i += kWave) {
+        s.hkey[i] = kEmpty;
+        s.hcnt[i] = 0u;
+    }
     s.bits_out = nullptr;
     s.bits_in = nullptr;
     s.words = 0;
@@ -472,6 +529,7 @@ __global__ __launch_bounds__(kWave) void enum_kernel(const DevGraph *graphs, con
                 const int4 u = units[idx];
                 const int gi = uniform(u.x);
                 if (gi != cur) {
+                    if (s.hused) flush_hash<K>(s);
                     s.urow = graphs[gi].urow;
                     s.uadj = graphs[gi].uadj;
                     s.bits_out = graphs[gi].bits_out;
@@ -481,15 +539,17 @@ __global__ __launch_bounds__(kWave) void enum_kernel(const DevGraph *graphs, con
                     cur = gi;
                 }
                 run_unit<K>(s, uniform(u.y), uniform(u.z), (uint32_t)uniform(u.w));
+                if (s.hused > kHashSlots / 4) flush_hash<K>(s);
             }
         }
     }
+    if (s.hused) flush_hash<K>(s);
 }
 
 int enum_lds_bytes(int k, int max_n, int seg_cap)
 {
     const int segs = k == 3 ? 2 : k - 2;
-    return (int)sizeof(uint32_t) * (max_n + segs * seg_cap + kScratchWords);
+    return (int)sizeof(uint32_t) * (max_n + segs * seg_cap + kScratchWords + 2 * kHashSlots);
 }
 
 template <int K>
