@@ -30,6 +30,28 @@ import time
 
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_SUBGRAPH = 4 + 8 + 8
+ROOT = os.path.dirname(os.path.abspath(__file__))
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "enum_kernel_hbm_traffic.json")
+KERNEL_SOURCES = ("paper_1804_09741_amd/csrc/enum.hip", "paper_1804_09741_amd/csrc/internal.h")
+
+
+def _measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter runs
+    (FETCH_SIZE + WRITE_SIZE, scaled by a copy of known size), or None when
+    the kernel source changed since they were taken."""
+    import hashlib
+    try:
+        with open(TRAFFIC_FILE) as f:
+            rec = json.load(f)
+        h = hashlib.sha256()
+        for name in KERNEL_SOURCES:
+            with open(os.path.join(ROOT, name), "rb") as f:
+                h.update(f.read())
+        if h.hexdigest()[:16] != rec["source_sha256_16"]:
+            return None
+        return rec["kernels"][kernel]["traffic_bytes"]
+    except (OSError, KeyError, ValueError):
+        return None
 
 
 def _log(msg):
@@ -230,7 +252,8 @@ def main():
         "config": {"workload": w.name, "k": 6, "graphs": len(w.graphs), "n": 700, "m": 1500,
                    "subgraphs_per_step": subgraphs},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": _measured_traffic("enum_kernel<6>"),
                      "kernel": "enum_kernel<6>", "kernel_ms": enum_ms,
                      "bytes_per_subgraph": BYTES_PER_SUBGRAPH},
         "pass_ms": float(np.mean(r["pass_ms"])),
