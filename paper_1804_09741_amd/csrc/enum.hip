@@ -48,19 +48,36 @@
 
 namespace mk {
 
-constexpr int kAggRounds = 16;
 
 // members whose extension segment is kept: positions 0..k-3 (k >= 4; the
 // last two levels are flat), positions 0..1 for k = 3
 template <int K>
 constexpr int kSegments = K == 3 ? 2 : K - 2;
 constexpr int kScratchWords = 3 * kWave;
+// Compile-time tuning knobs (build flags may override them).
+#ifndef MK_HASH_BITS
+#define MK_HASH_BITS 8   // log2 of the per-wave hash slots
+#endif
+#ifndef MK_MERGE_ROUNDS
+#define MK_MERGE_ROUNDS 1  // ballot rounds merging equal codes before the hash
+#endif
+#ifndef MK_ROW_MIN
+#define MK_ROW_MIN 32    // see kRowMin
+#endif
+
 // Per-wave hash of pending (code, count) pairs; flushed to the histogram when
 // half full, at the end of a unit once a quarter full, on a graph switch and
 // at exit.
-constexpr int kHashSlots = 256;
+constexpr int kHashBits = MK_HASH_BITS;
+constexpr int kHashSlots = 1 << kHashBits;
 constexpr int kHashProbes = 8;
 constexpr uint32_t kEmpty = 0xFFFFFFFFu;
+// A flush is forced once this many subgraphs are pending, so no 32-bit slot
+// count can overflow (every insert adds less than 2^31 on top).
+constexpr uint32_t kPendingMax = 1u << 30;
+// Rows of the last-level pair triangle, and children's lists, at least this
+// long are processed one at a time with their first vertex wave-uniform.
+constexpr int kRowMin = MK_ROW_MIN;
 
 template <int K>
 struct EnumState {
@@ -79,6 +96,7 @@ struct EnumState {
     uint32_t *hkey;             // per-wave LDS hash: code (kEmpty = free)
     uint32_t *hcnt;             //   and its pending count
     int hused;                  // keys in the hash (wave-uniform)
+    uint32_t hpending;          // subgraphs pending in the hash (wave-uniform)
     unsigned long long *hist;
     const uint32_t *table;
     uint32_t num_classes;
@@ -177,31 +195,19 @@ __device__ __forceinline__ void flush_hash(EnumState<K> &s)
         }
     }
     s.hused = 0;
+    s.hpending = 0;
     __syncthreads();
 }
 
-// count one code per valid lane.  One ballot round merges the lanes that
-// share the first lane's code; every remaining code goes into the wave's
-// LDS hash (linear probing; a lane that finds no slot within kHashProbes
-// goes straight to the histogram).
+// Add n to the pending count of code for every lane with `mine` set: the
+// wave's LDS hash (linear probing); a lane that finds no slot within
+// kHashProbes goes straight to the histogram.  Flushes when half full.
 template <int K>
-__device__ __forceinline__ void count_codes(EnumState<K> &s, bool valid, uint32_t code)
+__device__ __forceinline__ void hash_insert(EnumState<K> &s, bool mine, uint32_t code, uint32_t n)
 {
-    const int lane = lane_id();
-    const unsigned long long act = __ballot(valid);
-    if (!act) return;
-    const int l = __builtin_ctzll(act);
-    const uint32_t c0 = (uint32_t)__builtin_amdgcn_readlane((int)code, l);
-    const unsigned long long eq = __ballot(code == c0) & act;
-    bool mine = valid && !((eq >> lane) & 1ull);
-    uint32_t n = 1;
-    if (lane == l) {
-        mine = true;
-        n = (uint32_t)__popcll(eq);
-    }
     bool fresh = false;
     if (mine) {
-        uint32_t h = (code * 2654435761u) >> (32 - 8);
+        uint32_t h = (code * 2654435761u) >> (32 - kHashBits);
         bool done = false;
         for (int p = 0; p < kHashProbes && !done; ++p) {
             uint32_t k = s.hkey[h];
@@ -221,7 +227,31 @@ __device__ __forceinline__ void count_codes(EnumState<K> &s, bool valid, uint32_
         if (!done) add_global<K>(s, code, n);
     }
     s.hused += __popcll(__ballot(fresh));
-    if (s.hused > kHashSlots / 2) flush_hash<K>(s);
+    if (s.hused > kHashSlots / 2 || s.hpending >= kPendingMax) flush_hash<K>(s);
+}
+
+// count one code per valid lane.  MK_MERGE_ROUNDS ballot rounds merge the
+// lanes that share the first remaining lane's code; every code left goes
+// into the hash.
+template <int K>
+__device__ __forceinline__ void count_codes(EnumState<K> &s, bool valid, uint32_t code)
+{
+    const int lane = lane_id();
+    unsigned long long act = __ballot(valid);
+    if (!act) return;
+    s.hpending += (uint32_t)__popcll(act);
+    uint32_t n = 1;
+#pragma unroll
+    for (int r = 0; r < MK_MERGE_ROUNDS; ++r) {
+        if (!act) break;
+        const int l = __builtin_ctzll(act);
+        const uint32_t c0 = (uint32_t)__builtin_amdgcn_readlane((int)code, l);
+        const unsigned long long eq = __ballot(code == c0) & act;
+        if (lane == l) n = (uint32_t)__popcll(eq);
+        else if ((eq >> lane) & 1ull) n = 0;
+        act &= ~eq;
+    }
+    hash_insert<K>(s, valid && n > 0, code, n);
 }
 
 // last level: members s_0..s_{K-2}; every extension vertex closes a k-set
@@ -321,13 +351,35 @@ __device__ void last_two(EnumState<K> &s, const int (&st)[K - 1], uint32_t code,
     const int hi = e < jhi ? e : jhi;
     if (jlo >= hi) return;
 
-    // (A) pairs: row r = i - jlo holds A - r pairs, A = e - 1 - jlo
-    const int64_t A = e - 1 - jlo;
-    const int rows = hi - jlo;
-    const int64_t npairs = (int64_t)rows * A - (int64_t)rows * (rows - 1) / 2;
+    // (A) pairs (E[i], E[j]), j > i.  Long rows run one at a time with the
+    // row's vertex w wave-uniform; the short rows left at the end run flat.
+    int i0 = jlo;
+    for (; i0 < hi && e - 1 - i0 >= kRowMin; ++i0) {
+        const uint32_t w = (uint32_t)uniform((int)s.seg[ext_addr<K, NQ>(s, st, rem, i0)]);
+        const uint32_t cw = code | code_bits<K>((uint32_t)uniform((int)s.mark[w]), P1);
+        const uint32_t *bo = s.bits_out + (size_t)w * s.words;
+        const uint32_t *bi = s.bits_in + (size_t)w * s.words;
+        for (int jb = i0 + 1; jb < e; jb += kWave) {
+            const int j = jb + lane;
+            const bool valid = j < e;
+            uint32_t c = 0;
+            if (valid) {
+                const uint32_t u = s.seg[ext_addr<K, NQ>(s, st, rem, j)];
+                const uint32_t sh = u & 31u;
+                const uint32_t t = ((bo[u >> 5] >> sh) & 1u) | (((bi[u >> 5] >> sh) & 1u) << 1);
+                c = cw | code_bits<K>(s.mark[u], P2) | ((t & 1u) << B_WU) | ((t >> 1) << B_UW);
+            }
+            count_codes<K>(s, valid, c);
+        }
+    }
+    // flat: row r = i - i0 holds A - r pairs, A = e - 1 - i0 (< kRowMin here
+    // unless the range ends early)
+    const int A = e - 1 - i0;
+    const int rows = hi - i0;
+    const int npairs = rows > 0 ? rows * A - rows * (rows - 1) / 2 : 0;
     const float tA = 2.0f * (float)A + 1.0f;
-    for (int64_t base = 0; base < npairs; base += kWave) {
-        const int64_t p = base + lane;
+    for (int base = 0; base < npairs; base += kWave) {
+        const int p = base + lane;
         const bool valid = p < npairs;
         uint32_t c = 0;
         if (valid) {
@@ -335,11 +387,10 @@ __device__ void last_two(EnumState<K> &s, const int (&st)[K - 1], uint32_t code,
             disc = disc > 0.f ? disc : 0.f;
             int r = (int)((tA - sqrtf(disc)) * 0.5f);
             r = r < 0 ? 0 : (r > rows - 1 ? rows - 1 : r);
-            while (r + 1 < rows && (int64_t)(r + 1) * A - (int64_t)(r + 1) * r / 2 <= p) ++r;
-            while (r > 0 && (int64_t)r * A - (int64_t)r * (r - 1) / 2 > p) --r;
-            const int64_t off = (int64_t)r * A - (int64_t)r * (r - 1) / 2;
-            const int i = jlo + r;
-            const int j = i + 1 + (int)(p - off);
+            while (r + 1 < rows && (r + 1) * A - (r + 1) * r / 2 <= p) ++r;
+            while (r > 0 && r * A - r * (r - 1) / 2 > p) --r;
+            const int i = i0 + r;
+            const int j = i + 1 + (p - (r * A - r * (r - 1) / 2));
             if (j < e) {
                 const uint32_t w = s.seg[ext_addr<K, NQ>(s, st, rem, i)];
                 const uint32_t u = s.seg[ext_addr<K, NQ>(s, st, rem, j)];
@@ -353,8 +404,11 @@ __device__ void last_two(EnumState<K> &s, const int (&st)[K - 1], uint32_t code,
         count_codes<K>(s, valid && c != 0, c);
     }
 
-    // (B) exclusive neighbours, 64 children at a time: a lane-prefix sum of
-    // their degrees maps a flat index to (child, list position)
+    // (B) exclusive neighbours, 64 children at a time.  A child of degree
+    // >= kRowMin is scanned alone: its new neighbours all have mark 0, so
+    // only the arc type varies and three scalar counts carry the result.
+    // The others run flat, a lane-prefix sum of their degrees mapping a flat
+    // index to (child, list position).
     uint32_t *pre = s.scratch, *start = s.scratch + kWave, *cw = s.scratch + 2 * kWave;
     for (int ib = jlo; ib < hi; ib += kWave) {
         const int i = ib + lane;
@@ -366,6 +420,32 @@ __device__ void last_two(EnumState<K> &s, const int (&st)[K - 1], uint32_t code,
             deg = s.urow[w + 1] - row;
             wcode = code_bits<K>(s.mark[w], P1);
         }
+        unsigned long long big = __ballot(deg >= kRowMin);
+        while (big) {
+            const int l = __builtin_ctzll(big);
+            big &= big - 1;
+            const int brow = __builtin_amdgcn_readlane(row, l);
+            const int bdeg = __builtin_amdgcn_readlane(deg, l);
+            const uint32_t bcode = code | (uint32_t)__builtin_amdgcn_readlane((int)wcode, l);
+            uint32_t n1 = 0, n2 = 0, n3 = 0;
+            for (int b = 0; b < bdeg; b += kWave) {
+                const int e2 = b + lane;
+                uint32_t t = 0;
+                if (e2 < bdeg) {
+                    const uint32_t ent = s.uadj[brow + e2];
+                    const int u = (int)(ent >> 2);
+                    if (u > s.root && s.mark[u] == 0u) t = ent & 3u;
+                }
+                n1 += (uint32_t)__popcll(__ballot(t == 1u));
+                n2 += (uint32_t)__popcll(__ballot(t == 2u));
+                n3 += (uint32_t)__popcll(__ballot(t == 3u));
+            }
+            const uint32_t tl = (uint32_t)lane + 1u;
+            const uint32_t nl = lane == 0 ? n1 : (lane == 1 ? n2 : n3);
+            s.hpending += n1 + n2 + n3;
+            hash_insert<K>(s, lane < 3 && nl > 0, bcode | ((tl & 1u) << B_WU) | ((tl >> 1) << B_UW), nl);
+        }
+        if (deg >= kRowMin) deg = 0;
         int incl = deg;
 #pragma unroll
         for (int d = 1; d < kWave; d <<= 1) {
@@ -489,6 +569,7 @@ __global__ __launch_bounds__(kWave) void enum_kernel(const DevGraph *graphs, con
     s.hkey = s.scratch + kScratchWords;
     s.hcnt = s.hkey + kHashSlots;
     s.hused = 0;
+    s.hpending = 0;
     for (int i = lane_id(); i < kHashSlots; i += kWave) {
         s.hkey[i] = kEmpty;
         s.hcnt[i] = 0u;
