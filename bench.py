@@ -73,6 +73,8 @@ def _parse():
     p.add_argument("--k5-split", type=int, default=0,
                    help="k=5 split threshold (0: library default)")
     p.add_argument("--waves-per-cu", type=int, default=0)
+    p.add_argument("--autotune", action="store_true",
+                   help="pick the k=6 batch options with the library's autotuner first")
     p.add_argument("--copy-mib", type=int, default=0,
                    help="also run one device-to-device copy of this many MiB (a kernel of "
                         "known traffic, to scale hardware byte counters)")
@@ -229,6 +231,11 @@ def main():
         opts["split_threshold"] = args.split
     if args.waves_per_cu:
         opts["waves_per_cu"] = args.waves_per_cu
+    tuned = None
+    if args.autotune:
+        tuned, tuned_ms = ctx.autotune(graphs, t6, trials=2)
+        opts = {kk: v for kk, v in tuned.items() if kk != "debug_flags" and v}
+        _log("autotune: %s (enum kernel %.3f ms)" % (opts, tuned_ms))
     r = _timed_batch(ctx, M, graphs, t6, args.steps, args.warmup, torch, **opts)
     subgraphs = int(r["totals"].sum())
     ms_per_step = 1000.0 * r["wall_s"] / args.steps
@@ -258,6 +265,7 @@ def main():
                      "bytes_per_subgraph": BYTES_PER_SUBGRAPH},
         "pass_ms": float(np.mean(r["pass_ms"])),
         "batch_stats": r["stats"],
+        "batch_opts": opts,
         "table_build_ms": {"6": t6.build_ms},
     }
     _log("batched k=6: %.3f ms/step, enum kernel %.3f ms" % (ms_per_step, enum_ms))

@@ -174,6 +174,11 @@ typedef struct mk_batch_opts {
     int32_t waves_per_cu;     /* resident enumeration waves per compute unit */
     int32_t use_graph;        /* 1: replay a captured hipGraph (default),
                                  -1: plain stream launches */
+    int32_t units_per_grab;   /* work units a wave takes per queue atomic
+                                 (0: about 1/16 of a wave's share, <= 16) */
+    int32_t debug_flags;      /* tests only: 1 = every code straight to the
+                                 histogram, 2 = flush the per-wave count hash
+                                 after every insert; results are the same */
 } mk_batch_opts;
 
 /* Prepare a batch: device workspace for the typed adjacency, the work
@@ -214,6 +219,16 @@ int mk_batch_stats_get(const mk_batch *b, mk_batch_stats *out);
 int mk_batch_timing(mk_batch *b, double *pass_ms, double *enum_ms);
 
 void mk_batch_free(mk_batch *b);
+
+/* Autotuner: time the batch path on these graphs (best of `trials` runs
+   each) under candidate settings -- split-threshold floor, units per queue
+   grab, waves per CU, tried one knob at a time from the library defaults --
+   and return the fastest in *best and its enumeration-kernel time in
+   *best_ms (may be NULL).  Every candidate's histograms must equal the
+   defaults' (MK_EDEVICE otherwise).  Allocates and frees its own batches;
+   takes as long as about a dozen runs of the batch. */
+int mk_autotune(mk_ctx *ctx, const mk_graph *const *gs, int32_t ng, const mk_table *t,
+                int32_t trials, mk_batch_opts *best, double *best_ms);
 
 /* ----------------------------------------------------------------- server */
 

@@ -40,11 +40,10 @@ def build(force: bool = True) -> str:
     return _LIB
 
 
-@functools.lru_cache(maxsize=None)
-def _lib():
-    if not os.path.exists(_LIB):
-        build()
-    lib = ctypes.CDLL(_LIB)
+def load_library(path: str):
+    """A ctypes handle on an oracle library built from oracle.c (or from a
+    deliberately broken copy of it, for the mutation tests)."""
+    lib = ctypes.CDLL(path)
     lib.oracle_connected.restype = ctypes.c_int
     lib.oracle_connected.argtypes = [ctypes.c_int, ctypes.c_uint32]
     lib.oracle_canon.restype = ctypes.c_uint32
@@ -56,6 +55,13 @@ def _lib():
                                  ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
                                  ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]
     return lib
+
+
+@functools.lru_cache(maxsize=None)
+def _lib():
+    if not os.path.exists(_LIB):
+        build()
+    return load_library(_LIB)
 
 
 class OracleError(RuntimeError):
@@ -76,18 +82,23 @@ def canon(k: int, code: int) -> int:
     return int(_lib().oracle_canon(k, code))
 
 
-@functools.lru_cache(maxsize=None)
-def canon_table(k: int):
-    """(canon, conn): canonical code and connectivity of every code, k <= 5."""
+def canon_table_with(lib, k: int):
+    """(canon, conn) from a given oracle library."""
     n = 1 << (k * (k - 1))
     c = np.empty(n, dtype=np.uint32)
     ok = np.empty(n, dtype=np.uint8)
-    rc = _lib().oracle_canon_table(k, c.ctypes.data, ok.ctypes.data)
+    rc = lib.oracle_canon_table(k, c.ctypes.data, ok.ctypes.data)
     if rc != 0:
         raise OracleError(rc)
     c.setflags(write=False)
     ok.setflags(write=False)
     return c, ok
+
+
+@functools.lru_cache(maxsize=None)
+def canon_table(k: int):
+    """(canon, conn): canonical code and connectivity of every code, k <= 5."""
+    return canon_table_with(_lib(), k)
 
 
 @functools.lru_cache(maxsize=None)
@@ -101,20 +112,23 @@ def class_codes(k: int) -> np.ndarray:
 
 def count(row_ptr, col, k: int) -> Dict[int, int]:
     """H_k as {canonical code: count} (zero classes omitted)."""
+    return count_with(_lib(), row_ptr, col, k, canon_table(k)[0] if 3 <= k <= 5 else None)
+
+
+def count_with(lib, row_ptr, col, k: int, table=None) -> Dict[int, int]:
+    """H_k from a given oracle library (table: its canon table for k <= 5)."""
     row_ptr = np.ascontiguousarray(row_ptr, dtype=np.int32)
     col = np.ascontiguousarray(col, dtype=np.int32)
     n = len(row_ptr) - 1
-    table = None
     tptr = None
     if 3 <= k <= 5:
-        table = canon_table(k)[0]
         tptr = table.ctypes.data
     cap = 1 << 16
     while True:
         codes = np.zeros(cap, dtype=np.uint32)
         counts = np.zeros(cap, dtype=np.uint64)
         total = ctypes.c_uint64(0)
-        rc = _lib().oracle_count(n, row_ptr.ctypes.data, col.ctypes.data if len(col) else None,
+        rc = lib.oracle_count(n, row_ptr.ctypes.data, col.ctypes.data if len(col) else None,
                                  k, tptr, codes.ctypes.data, counts.ctypes.data, cap,
                                  ctypes.byref(total))
         if rc == -5:

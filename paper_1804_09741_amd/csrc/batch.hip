@@ -129,6 +129,16 @@ static void batch_release(mk_batch *b)
         if (p) (void)hipFree(p);
 }
 
+static EnumConfig enum_config(const mk_batch *b)
+{
+    EnumConfig c;
+    c.max_n = b->max_n;
+    c.seg_cap = b->seg_cap;
+    c.flags = (uint32_t)b->opts.debug_flags;
+    c.chunk = (uint32_t)std::max(b->opts.units_per_grab, 0);
+    return c;
+}
+
 // enqueue the preparation part of one pass on stream: counters and
 // histograms cleared, typed adjacency, work-unit plan (captured as a hipGraph)
 static int batch_enqueue_prep(mk_batch *b, unsigned long long *hist, hipStream_t stream)
@@ -150,8 +160,8 @@ static int batch_enqueue_enum(mk_batch *b, unsigned long long *hist, hipStream_t
 {
     MK_HIP(hipEventRecord(b->ev[1], stream));
     int rc = launch_enum(b->k, b->d_graphs, b->d_units, b->unit_cap, kAllUnits, b->d_counters,
-                         b->table->d_table, b->table->num_classes, hist, b->max_n, b->seg_cap,
-                         b->grid, b->lds_bytes, stream);
+                         b->table->d_table, b->table->num_classes, hist, enum_config(b), b->grid,
+                         b->lds_bytes, stream);
     if (rc) return rc;
     MK_HIP(hipEventRecord(b->ev[2], stream));
     return MK_OK;
@@ -437,8 +447,8 @@ int batch_enum_slice(mk_batch *b, uint32_t begin, uint32_t end, hipStream_t stre
     if (rc) return rc;
     const int grid = (int)std::min<uint64_t>((uint64_t)b->grid, end - begin);
     return launch_enum(b->k, b->d_graphs, b->d_units, b->unit_cap, end, b->d_counters,
-                       b->table->d_table, b->table->num_classes, b->d_hist_own, b->max_n,
-                       b->seg_cap, grid, b->lds_bytes, stream);
+                       b->table->d_table, b->table->num_classes, b->d_hist_own, enum_config(b),
+                       grid, b->lds_bytes, stream);
 }
 
 }  // namespace mk
@@ -467,6 +477,86 @@ extern "C" void mk_batch_free(mk_batch *b)
     (void)hipStreamSynchronize(b->ctx->stream);
     batch_release(b);
     delete b;
+}
+
+// --------------------------------------------------------------- autotune
+
+// time one candidate: best enumeration-kernel time over `trials` runs; the
+// histograms go to host memory in *hist
+static int time_candidate(mk_ctx *ctx, const mk_graph *const *gs, int32_t ng, const mk_table *t,
+                          const mk_batch_opts &o, int trials, double *ms,
+                          std::vector<uint64_t> *hist, int *waves_per_cu = nullptr)
+{
+    mk_batch *b = nullptr;
+    int rc = mk_batch_create(ctx, gs, ng, t, &o, &b);
+    if (rc) return rc;
+    if (waves_per_cu) *waves_per_cu = b->max_grid / std::max(ctx->num_cus, 1);
+    double best = 1e30;
+    for (int i = 0; i < trials && rc == MK_OK; ++i) {
+        rc = mk_batch_run(b, nullptr, nullptr);
+        double pass = 0, e = 0;
+        if (!rc) rc = mk_batch_timing(b, &pass, &e);
+        if (!rc) best = std::min(best, e);
+    }
+    if (!rc) {
+        hist->resize((size_t)ng * t->num_classes);
+        rc = mk_batch_read(b, hist->data(), nullptr);
+    }
+    mk_batch_free(b);
+    *ms = best;
+    return rc;
+}
+
+extern "C" int mk_autotune(mk_ctx *ctx, const mk_graph *const *gs, int32_t ng, const mk_table *t,
+                           int32_t trials, mk_batch_opts *best, double *best_ms)
+{
+    if (!ctx || !t || !best || (ng > 0 && !gs)) return fail(MK_EINVAL, "mk_autotune: NULL argument");
+    if (ng <= 0) return fail(MK_EINVAL, "mk_autotune: no graphs");
+    trials = std::max(trials, 1);
+    mk_batch_opts cur{};
+    cur.use_graph = 1;
+    std::vector<uint64_t> ref, h;
+    double cur_ms = 0;
+    int per_cu = 0;
+    int rc = time_candidate(ctx, gs, ng, t, cur, trials, &cur_ms, &ref, &per_cu);
+    if (rc) return rc;
+    auto trial = [&](mk_batch_opts o) -> int {
+        double ms = 0;
+        int r = time_candidate(ctx, gs, ng, t, o, trials, &ms, &h);
+        if (r) return r;
+        if (h != ref) return fail(MK_EDEVICE, "mk_autotune: a candidate changed the histograms");
+        if (ms < cur_ms) {
+            cur_ms = ms;
+            cur = o;
+        }
+        return MK_OK;
+    };
+    // coordinate search: split floor, then units per grab, then waves per CU
+    static const uint64_t floors[] = {1u << 10, 1u << 14, 1u << 18, 1u << 22};
+    const mk_batch_opts base1 = cur;
+    for (uint64_t f : floors) {
+        mk_batch_opts o = base1;
+        o.split_threshold = f;
+        if ((rc = trial(o))) return rc;
+    }
+    static const int grabs[] = {1, 4, 16, 64};
+    const mk_batch_opts base2 = cur;
+    for (int g : grabs) {
+        mk_batch_opts o = base2;
+        o.units_per_grab = g;
+        if ((rc = trial(o))) return rc;
+    }
+    if (per_cu > 2) {
+        const mk_batch_opts base3 = cur;
+        for (int wpc : {per_cu / 2, (3 * per_cu) / 4}) {
+            mk_batch_opts o = base3;
+            o.waves_per_cu = wpc;
+            if ((rc = trial(o))) return rc;
+        }
+    }
+    *best = cur;
+    if (best_ms) *best_ms = cur_ms;
+    return MK_OK;
 }
 
 // ------------------------------------------------------------------ count

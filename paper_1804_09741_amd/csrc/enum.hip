@@ -97,6 +97,7 @@ struct EnumState {
     uint32_t *hcnt;             //   and its pending count
     int hused;                  // keys in the hash (wave-uniform)
     uint32_t hpending;          // subgraphs pending in the hash (wave-uniform)
+    uint32_t flags;             // kDebug* bits
     unsigned long long *hist;
     const uint32_t *table;
     uint32_t num_classes;
@@ -206,6 +207,10 @@ template <int K>
 __device__ __forceinline__ void hash_insert(EnumState<K> &s, bool mine, uint32_t code, uint32_t n)
 {
     bool fresh = false;
+    if (s.flags & kDebugNoHash) {
+        if (mine) add_global<K>(s, code, n);
+        return;
+    }
     if (mine) {
         uint32_t h = (code * 2654435761u) >> (32 - kHashBits);
         bool done = false;
@@ -227,7 +232,8 @@ __device__ __forceinline__ void hash_insert(EnumState<K> &s, bool mine, uint32_t
         if (!done) add_global<K>(s, code, n);
     }
     s.hused += __popcll(__ballot(fresh));
-    if (s.hused > kHashSlots / 2 || s.hpending >= kPendingMax) flush_hash<K>(s);
+    if (s.hused > kHashSlots / 2 || s.hpending >= kPendingMax || (s.flags & kDebugFlushAlways))
+        flush_hash<K>(s);
 }
 
 // count one code per valid lane.  MK_MERGE_ROUNDS ballot rounds merge the
@@ -557,15 +563,17 @@ __global__ __launch_bounds__(kWave) void enum_kernel(const DevGraph *graphs, con
                                                      uint32_t unit_cap, uint32_t unit_end,
                                                      uint32_t *counters,
                                                      const uint32_t *table, uint32_t num_classes,
-                                                     unsigned long long *hist_base, int max_n,
-                                                     int seg_cap)
+                                                     unsigned long long *hist_base,
+                                                     EnumConfig cfg)
 {
     extern __shared__ uint32_t lds[];
     EnumState<K> s;
     s.mark = lds;
+    const int max_n = cfg.max_n;
     s.seg = lds + max_n;
-    s.seg_cap = seg_cap;
-    s.scratch = lds + max_n + kSegments<K> * seg_cap;
+    s.seg_cap = cfg.seg_cap;
+    s.flags = cfg.flags;
+    s.scratch = lds + max_n + kSegments<K> * cfg.seg_cap;
     s.hkey = s.scratch + kScratchWords;
     s.hcnt = s.hkey + kHashSlots;
     s.hused = 0;
@@ -592,8 +600,9 @@ __global__ __launch_bounds__(kWave) void enum_kernel(const DevGraph *graphs, con
     const uint32_t begin = counters[kSliceBegin];
     const uint32_t span = end > begin ? end - begin : 0u;
     // units per grab: about 1/16 of a wave's share, 1..16
-    uint32_t chunk = span / (gridDim.x * 16u);
-    chunk = chunk < 1u ? 1u : (chunk > 16u ? 16u : chunk);
+    uint32_t chunk = cfg.chunk ? cfg.chunk : span / (gridDim.x * 16u);
+    chunk = chunk < 1u ? 1u : (chunk > 256u ? 256u : chunk);
+    if (!cfg.chunk && chunk > 16u) chunk = 16u;
     int cur = -1;
     const int home = (int)(blockIdx.x % kQueues);
     for (int q = 0; q < kQueues; ++q) {
@@ -655,30 +664,26 @@ int enum_max_blocks_per_cu(int k, int lds_bytes, int *blocks)
 
 int launch_enum(int k, const DevGraph *d_graphs, const int4 *units, uint32_t unit_cap,
                 uint32_t unit_end, uint32_t *counters, const uint32_t *table, uint32_t num_classes,
-                unsigned long long *hist_base, int max_n, int seg_cap, int grid, int lds_bytes,
+                unsigned long long *hist_base, const EnumConfig &cfg, int grid, int lds_bytes,
                 hipStream_t stream)
 {
     if (grid <= 0) return MK_OK;
     switch (k) {
     case 3:
         hipLaunchKernelGGL(enum_kernel<3>, dim3(grid), dim3(kWave), lds_bytes, stream, d_graphs,
-                           units, unit_cap, unit_end, counters, table, num_classes, hist_base, max_n,
-                           seg_cap);
+                           units, unit_cap, unit_end, counters, table, num_classes, hist_base, cfg);
         break;
     case 4:
         hipLaunchKernelGGL(enum_kernel<4>, dim3(grid), dim3(kWave), lds_bytes, stream, d_graphs,
-                           units, unit_cap, unit_end, counters, table, num_classes, hist_base, max_n,
-                           seg_cap);
+                           units, unit_cap, unit_end, counters, table, num_classes, hist_base, cfg);
         break;
     case 5:
         hipLaunchKernelGGL(enum_kernel<5>, dim3(grid), dim3(kWave), lds_bytes, stream, d_graphs,
-                           units, unit_cap, unit_end, counters, table, num_classes, hist_base, max_n,
-                           seg_cap);
+                           units, unit_cap, unit_end, counters, table, num_classes, hist_base, cfg);
         break;
     case 6:
         hipLaunchKernelGGL(enum_kernel<6>, dim3(grid), dim3(kWave), lds_bytes, stream, d_graphs,
-                           units, unit_cap, unit_end, counters, table, num_classes, hist_base, max_n,
-                           seg_cap);
+                           units, unit_cap, unit_end, counters, table, num_classes, hist_base, cfg);
         break;
     default: return fail(MK_ERANGE, "k=%d outside 3..6", k);
     }

@@ -136,13 +136,23 @@ int launch_plan(int k, const DevGraph *d_graphs, int ng, int64_t max_nnz, uint32
 int enum_lds_bytes(int k, int max_n, int seg_cap);
 int enum_max_blocks_per_cu(int k, int lds_bytes, int *blocks);
 constexpr uint32_t kAllUnits = 0xFFFFFFFFu;
+
+// Launch configuration of the enumeration kernel.
+struct EnumConfig {
+    int max_n;       // largest n of the batch (LDS marks)
+    int seg_cap;     // largest undirected degree (LDS extension segments)
+    uint32_t flags;  // kDebug* bits below (tests only; 0 in production)
+    uint32_t chunk;  // units per queue grab; 0 = about 1/16 of a wave's share
+};
+constexpr uint32_t kDebugNoHash = 1u;      // every code straight to the histogram
+constexpr uint32_t kDebugFlushAlways = 2u; // flush the hash after every insert
 // The units [counters[kSliceBegin], min(counters[kNumUnits], unit_cap,
 // unit_end)) are cut into kQueues equal ranges; wave w starts on range
 // w % kQueues (the XCD the wave runs on) and then helps the others.  Heads
 // must be zero at launch.
 int launch_enum(int k, const DevGraph *d_graphs, const int4 *units, uint32_t unit_cap,
                 uint32_t unit_end, uint32_t *counters, const uint32_t *table, uint32_t num_classes,
-                unsigned long long *hist_base, int max_n, int seg_cap, int grid, int lds_bytes,
+                unsigned long long *hist_base, const EnumConfig &cfg, int grid, int lds_bytes,
                 hipStream_t stream);
 
 void free_table(Table *t);

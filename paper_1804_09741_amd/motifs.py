@@ -46,7 +46,8 @@ class MotifsError(RuntimeError):
 
 class BatchOpts(ctypes.Structure):
     _fields_ = [("split_threshold", ctypes.c_uint64), ("waves_per_cu", ctypes.c_int32),
-                ("use_graph", ctypes.c_int32)]
+                ("use_graph", ctypes.c_int32), ("units_per_grab", ctypes.c_int32),
+                ("debug_flags", ctypes.c_int32)]
 
 
 class BatchStats(ctypes.Structure):
@@ -99,6 +100,8 @@ SIGNATURES = {
     "mk_batch_timing": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double),
                                        ctypes.POINTER(ctypes.c_double)]),
     "mk_batch_free": (None, [_P]),
+    "mk_autotune": (ctypes.c_int, [_P, _P, _I32, _P, _I32, ctypes.POINTER(BatchOpts),
+                                   ctypes.POINTER(ctypes.c_double)]),
     "mk_server_start": (ctypes.c_int, [_P, ctypes.POINTER(ServerOpts), ctypes.POINTER(_P)]),
     "mk_submit": (ctypes.c_int, [_P, _P, ctypes.c_int, ctypes.POINTER(_U64)]),
     "mk_wait": (ctypes.c_int, [_P, _U64, _P, _U32, _I32, ctypes.POINTER(RequestTimes)]),
@@ -276,8 +279,9 @@ def mk_count_batch(ctx: int, gs: Sequence[int], t: int) -> Tuple[np.ndarray, np.
 
 
 def mk_batch_create(ctx: int, gs: Sequence[int], t: int, split_threshold: int = 0,
-                    waves_per_cu: int = 0, use_graph: int = 0) -> int:
-    opts = BatchOpts(split_threshold, waves_per_cu, use_graph)
+                    waves_per_cu: int = 0, use_graph: int = 0, units_per_grab: int = 0,
+                    debug_flags: int = 0) -> int:
+    opts = BatchOpts(split_threshold, waves_per_cu, use_graph, units_per_grab, debug_flags)
     h = _P()
     _check(library().mk_batch_create(ctx, _handles(gs), len(gs), t, ctypes.byref(opts),
                                      ctypes.byref(h)))
@@ -313,6 +317,15 @@ def mk_batch_timing(b: int) -> Tuple[float, float]:
 
 def mk_batch_free(b: int) -> None:
     library().mk_batch_free(b)
+
+
+def mk_autotune(ctx: int, gs: Sequence[int], t: int, trials: int = 2) -> Tuple[dict, float]:
+    """(fastest batch options, its enumeration-kernel ms) for these graphs."""
+    o = BatchOpts()
+    ms = ctypes.c_double()
+    _check(library().mk_autotune(ctx, _handles(gs), len(gs), t, trials, ctypes.byref(o),
+                                 ctypes.byref(ms)))
+    return {f: getattr(o, f) for f, _ in BatchOpts._fields_}, ms.value
 
 
 # ------------------------------------------------------------------- server
@@ -458,6 +471,9 @@ class Context:
 
     def batch(self, graphs: Sequence[Graph], table: Table, **opts) -> Batch:
         return Batch(self, graphs, table, **opts)
+
+    def autotune(self, graphs: Sequence[Graph], table: Table, trials: int = 2):
+        return mk_autotune(self.handle, [g.handle for g in graphs], table.handle, trials)
 
     def server(self, **opts) -> Server:
         return Server(self, **opts)

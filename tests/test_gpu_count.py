@@ -170,3 +170,40 @@ def test_torch_buffer_and_stream(ctx):
         b.free()
     finally:
         gr.free()
+
+
+@pytest.mark.parametrize("k", [3, 4, 5, 6])
+def test_counting_paths_agree(ctx, k):
+    """The per-wave hash, its constant-flush and bypass paths, and different
+    queue grab sizes all give the same histogram (and the oracle's)."""
+    rng = np.random.default_rng([4000, k])
+    g = I.chung_lu_digraph(300, 1000, 2.1, 60 if k < 6 else 20, 0.15, rng)
+    ref, _ = _count(ctx, g, k)
+    for opts in ({"debug_flags": 1}, {"debug_flags": 2}, {"units_per_grab": 1},
+                 {"units_per_grab": 64}, {"split_threshold": 1, "units_per_grab": 3}):
+        h, _ = _count(ctx, g, k, **opts)
+        assert np.array_equal(h, ref), opts
+    if k <= 5:
+        assert_hist_equals_oracle(ref, ctx.table(k).class_codes(), *g, k)
+
+
+def test_autotune_keeps_results(ctx):
+    k = 5
+    rng = np.random.default_rng(4100)
+    graphs = [I.chung_lu_digraph(200, 700, 2.2, 50, 0.1, rng) for _ in range(4)]
+    t = ctx.table(k)
+    loaded = [ctx.load_graph(*g) for g in graphs]
+    try:
+        opts, ms = ctx.autotune(loaded, t, trials=1)
+        assert ms > 0
+        ref, _ = ctx.count_batch(loaded, t)
+        b = ctx.batch(loaded, t, **{kk: v for kk, v in opts.items() if kk != "debug_flags"})
+        try:
+            b.run()
+            h, _ = b.read()
+        finally:
+            b.free()
+        assert np.array_equal(h, ref)
+    finally:
+        for g in loaded:
+            g.free()

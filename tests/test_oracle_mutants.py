@@ -1,0 +1,118 @@
+"""Plausible mistakes planted in copies of the oracle (compiled with gcc on
+the CPU) must each fail at least one pin: the pins are strong enough to
+catch a wrong bit index, a dropped arc direction, a broken enumeration bound,
+a transposed operand or an incomplete permutation walk."""
+
+import json
+import math
+import os
+import subprocess
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1804_09741_amd import inputs as I
+
+import combinatorics as C
+
+SRC = os.path.join(os.path.dirname(O.__file__), "oracle.c")
+
+MUTANTS = {
+    "bit index keeps the diagonal": (
+        "return i * (k - 1) + j - (j > i ? 1 : 0);", "return i * (k - 1) + j - (j > i ? 0 : 0);"),
+    "connectivity follows out-arcs only": (
+        "if (!seen[w] && (a[u][w] || a[w][u])) {", "if (!seen[w] && (a[u][w])) {"),
+    "canonical form is the maximum": (
+        "if (c < best) best = c;", "if (c > best || best == 0xFFFFFFFFu) best = c;"),
+    "permutation walk starts at the last relabeling": (
+        "    for (int i = 0; i < k; ++i) p[i] = i;\n    uint32_t best",
+        "    for (int i = 0; i < k; ++i) p[i] = k - 1 - i;\n    uint32_t best"),
+    "extension ignores the root bound": (
+        "if (u > root && !in_closed_nbhd(e, depth, u)) child[cn++] = u;",
+        "if (u != root && !in_closed_nbhd(e, depth, u)) child[cn++] = u;"),
+    "exclusive test drops one arc direction": (
+        "if (s == u || arc(e, s, u) || arc(e, u, s)) return 1;",
+        "if (s == u || arc(e, s, u)) return 1;"),
+    "code operands transposed": (
+        "if (i != j && arc(e, e->sub[i], e->sub[j])) code |= 1u << bit_of(k, i, j);",
+        "if (i != j && arc(e, e->sub[j], e->sub[i])) code |= 1u << bit_of(k, i, j);"),
+    "child extension keeps the chosen vertex": (
+        "for (int j = i + 1; j < next; ++j) child[cn++] = ext[j];",
+        "for (int j = i; j < next; ++j) child[cn++] = ext[j];"),
+}
+
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _build(tmp_path, name, text):
+    src = tmp_path / (name + ".c")
+    lib = tmp_path / (name + ".so")
+    src.write_text(text)
+    subprocess.check_call(["gcc", "-O1", "-std=c99", "-shared", "-fPIC", str(src), "-o", str(lib)])
+    return str(lib)
+
+
+def _failed_pins_in_child(lib_path, timeout=120):
+    """Run the pins against a library in a child process (a planted bug may
+    loop forever; a timeout counts as caught)."""
+    code = ("import sys, json; sys.path[:0] = %r; import test_oracle_mutants as T; "
+            "from oracle import oracle as O; "
+            "print(json.dumps(T._failed_pins(O.load_library(%r))))"
+            % ([ROOT, os.path.join(ROOT, "tests")], lib_path))
+    try:
+        res = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True,
+                             timeout=timeout)
+    except subprocess.TimeoutExpired:
+        return ["timeout"]
+    if res.returncode != 0:
+        return ["crash: " + res.stderr[-300:]]
+    return json.loads(res.stdout.strip().splitlines()[-1])
+
+
+def _failed_pins(lib):
+    """Names of the pins this oracle library fails."""
+    failed = []
+    tables = {}
+    for k in (3, 4):
+        canon, conn = O.canon_table_with(lib, k)
+        tables[k] = canon
+        cc = np.unique(canon[conn.astype(bool)])
+        if len(cc) != {3: 13, 4: 199}[k]:
+            failed.append("class count k=%d" % k)
+        if len(np.unique(canon)) != C.unlabeled_digraphs(k):
+            failed.append("burnside k=%d" % k)
+        if int(conn.sum()) != C.labeled_connected_digraphs(k):
+            failed.append("labeled connected k=%d" % k)
+        if len(cc) and (int(cc[0]) != (1 << (k - 1)) - 1 or int(cc[-1]) != (1 << (k * (k - 1))) - 1):
+            failed.append("extreme classes k=%d" % k)
+    for k in (3, 4):
+        try:
+            star = O.count_with(lib, *I.out_star(7), k, tables[k])
+            if star != {(1 << (k - 1)) - 1: math.comb(7, k - 1)}:
+                failed.append("out-star k=%d" % k)
+            rng = np.random.default_rng([55, k])
+            for _ in range(3):
+                g = I.er_digraph(8, int(rng.integers(8, 24)), rng)
+                if O.count_with(lib, *g, k, tables[k]) != O.brute_force_count(*g, k):
+                    failed.append("brute force k=%d" % k)
+                    break
+        except O.OracleError:
+            failed.append("error k=%d" % k)
+    return failed
+
+
+def test_unmutated_oracle_passes(tmp_path):
+    lib = _build(tmp_path, "clean", open(SRC).read())
+    assert _failed_pins_in_child(lib) == []
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_mutant_is_caught(tmp_path, name):
+    before, after = MUTANTS[name]
+    text = open(SRC).read()
+    assert text.count(before) == 1, "mutation site not found: %s" % before
+    lib = _build(tmp_path, "mutant", text.replace(before, after))
+    assert _failed_pins_in_child(lib), "no pin catches: %s" % name
