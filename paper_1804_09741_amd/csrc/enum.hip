@@ -43,6 +43,7 @@
 // in the code -> class table and adds to the graph's histogram with 64-bit
 // atomics.
 #include <climits>
+#include <type_traits>
 
 #include "internal.h"
 
@@ -79,12 +80,38 @@ constexpr uint32_t kPendingMax = 1u << 30;
 // long are processed one at a time with their first vertex wave-uniform.
 constexpr int kRowMin = MK_ROW_MIN;
 
+// Byte offsets of one wave's LDS: marks (n x 2 or 4 bytes), extension
+// segments (u16), scratch, hash keys and counts; each part 4-byte aligned.
+struct LdsLayout {
+    int seg, scratch, total;
+};
+
+__host__ __device__ inline LdsLayout lds_layout(int k, int max_n, int seg_cap)
+{
+    const int segs = k == 3 ? 2 : k - 2;
+    const int mark_bytes = ((k <= 5 ? 2 : 4) * max_n + 3) & ~3;
+    const int seg_bytes = (2 * segs * seg_cap + 3) & ~3;
+    LdsLayout l;
+    l.seg = mark_bytes;
+    l.scratch = l.seg + seg_bytes;
+    l.total = l.scratch + 4 * (kScratchWords + 2 * kHashSlots);
+    return l;
+}
+
+// Marks hold, for members at positions 0..kSegments-1, the "in" bits spread
+// at stride k-1 (highest at (kSegments-1)(k-1)) and then one "out" bit per
+// position: 5 / 6 / 12 / 20 bits for k = 3 / 4 / 5 / 6, so 16-bit marks do
+// for k <= 5.
+template <int K>
+using MarkT = typename std::conditional<K <= 5, uint16_t, uint32_t>::type;
+
 template <int K>
 struct EnumState {
-    static constexpr int OUTB = (K - 2) * (K - 1) + 1;
+    static constexpr int OUTB = (kSegments<K> - 1) * (K - 1) + 1;
     static constexpr uint32_t INMASK = (1u << OUTB) - 1u;
-    uint32_t *mark;
-    uint32_t *seg;
+    static_assert(OUTB + kSegments<K> <= 8 * (int)sizeof(MarkT<K>), "mark bits do not fit");
+    MarkT<K> *mark;
+    uint16_t *seg;              // vertex ids (n <= MK_MAX_VERTICES < 65536)
     int seg_cap;
     int root;
     const int32_t *urow;
@@ -137,7 +164,7 @@ __device__ __forceinline__ void push(EnumState<K> &s, int x)
     const int lane = lane_id();
     const int r0 = uniform(s.urow[x]);
     const int r1 = uniform(s.urow[x + 1]);
-    uint32_t *seg = s.seg + D * s.seg_cap;
+    uint16_t *seg = s.seg + D * s.seg_cap;
     int cnt = 0;
     for (int base = r0; base < r1; base += kWave) {
         const int e = base + lane;
@@ -147,9 +174,9 @@ __device__ __forceinline__ void push(EnumState<K> &s, int x)
         const uint32_t m = valid ? s.mark[y] : 1u;
         const bool fresh = valid && y > s.root && m == 0u;
         const unsigned long long bal = __ballot(fresh);
-        if (fresh) seg[cnt + (int)lanes_below(bal)] = (uint32_t)y;
+        if (fresh) seg[cnt + (int)lanes_below(bal)] = (uint16_t)y;
         cnt += __popcll(bal);
-        if (valid) s.mark[y] = m | mark_bits<K>(D, ent & 3u);
+        if (valid) s.mark[y] = (MarkT<K>)(m | mark_bits<K>(D, ent & 3u));
     }
     s.len[D] = cnt;
     __syncthreads();
@@ -167,7 +194,7 @@ __device__ __forceinline__ void pop(EnumState<K> &s, int x)
         const int e = base + lane;
         if (e < r1) {
             const int y = (int)(s.uadj[e] >> 2);
-            s.mark[y] &= keep;
+            s.mark[y] = (MarkT<K>)(s.mark[y] & keep);
         }
     }
     __syncthreads();
@@ -568,12 +595,14 @@ __global__ __launch_bounds__(kWave) void enum_kernel(const DevGraph *graphs, con
 {
     extern __shared__ uint32_t lds[];
     EnumState<K> s;
-    s.mark = lds;
     const int max_n = cfg.max_n;
-    s.seg = lds + max_n;
+    const LdsLayout lay = lds_layout(K, max_n, cfg.seg_cap);
+    char *base = reinterpret_cast<char *>(lds);
+    s.mark = reinterpret_cast<MarkT<K> *>(base);
+    s.seg = reinterpret_cast<uint16_t *>(base + lay.seg);
     s.seg_cap = cfg.seg_cap;
     s.flags = cfg.flags;
-    s.scratch = lds + max_n + kSegments<K> * cfg.seg_cap;
+    s.scratch = reinterpret_cast<uint32_t *>(base + lay.scratch);
     s.hkey = s.scratch + kScratchWords;
     s.hcnt = s.hkey + kHashSlots;
     s.hused = 0;
@@ -592,7 +621,7 @@ __global__ __launch_bounds__(kWave) void enum_kernel(const DevGraph *graphs, con
     s.urow = nullptr;
     s.uadj = nullptr;
     s.hist = nullptr;
-    for (int i = lane_id(); i < max_n; i += kWave) lds[i] = 0u;
+    for (int i = lane_id(); i < max_n; i += kWave) s.mark[i] = 0;
     __syncthreads();
     const uint32_t navail = counters[kNumUnits];
     const uint32_t cap = unit_cap < unit_end ? unit_cap : unit_end;
@@ -636,11 +665,7 @@ __global__ __launch_bounds__(kWave) void enum_kernel(const DevGraph *graphs, con
     if (s.hused) flush_hash<K>(s);
 }
 
-int enum_lds_bytes(int k, int max_n, int seg_cap)
-{
-    const int segs = k == 3 ? 2 : k - 2;
-    return (int)sizeof(uint32_t) * (max_n + segs * seg_cap + kScratchWords + 2 * kHashSlots);
-}
+int enum_lds_bytes(int k, int max_n, int seg_cap) { return lds_layout(k, max_n, seg_cap).total; }
 
 template <int K>
 static const void *enum_fn()
