@@ -239,24 +239,22 @@ __device__ __forceinline__ void hash_insert(EnumState<K> &s, bool mine, uint32_t
         return;
     }
     if (mine) {
+        // one compare-and-swap either claims an empty slot or finds the code
+        // already there; only a collision probes on
         uint32_t h = (code * 2654435761u) >> (32 - kHashBits);
-        bool done = false;
-        for (int p = 0; p < kHashProbes && !done; ++p) {
-            uint32_t k = s.hkey[h];
-            if (k == kEmpty) {
-                k = atomicCAS(&s.hkey[h], kEmpty, code);
-                if (k == kEmpty) {
-                    fresh = true;
-                    k = code;
-                }
-            }
-            if (k == code) {
-                atomicAdd(&s.hcnt[h], n);
-                done = true;
-            }
+        uint32_t old = atomicCAS(&s.hkey[h], kEmpty, code);
+        bool ok = old == kEmpty || old == code;
+        for (int p = 1; p < kHashProbes && !ok; ++p) {
             h = (h + 1) & (kHashSlots - 1);
+            old = atomicCAS(&s.hkey[h], kEmpty, code);
+            ok = old == kEmpty || old == code;
         }
-        if (!done) add_global<K>(s, code, n);
+        if (ok) {
+            fresh = old == kEmpty;
+            atomicAdd(&s.hcnt[h], n);
+        } else {
+            add_global<K>(s, code, n);
+        }
     }
     s.hused += __popcll(__ballot(fresh));
     if (s.hused > kHashSlots / 2 || s.hpending >= kPendingMax || (s.flags & kDebugFlushAlways))
@@ -574,10 +572,8 @@ __device__ void run_unit(EnumState<K> &s, int v, int i, uint32_t range)
 #pragma unroll
         for (int q = 0; q < K - 1; ++q) st[q] = 0;
         st[0] = i + 1;
-        if (range == kFullChild)
-            visit<K, 1>(s, st, code, 0, INT_MAX);
-        else
-            visit<K, 1>(s, st, code, (int)(range & 0xFFFFu), (int)(range >> 16));
+        const bool full = range == kFullChild;
+        visit<K, 1>(s, st, code, full ? 0 : (int)(range & 0xFFFFu), full ? INT_MAX : (int)(range >> 16));
         pop<K, 1>(s, x);
     } else if (lane_id() == 0) {
         atomicAdd(s.errors, 1u);
