@@ -354,6 +354,121 @@ __device__ __forceinline__ uint32_t pair_type(const EnumState<K> &s, uint32_t w,
     return ((s.bits_out[word] >> sh) & 1u) | (((s.bits_in[word] >> sh) & 1u) << 1);
 }
 
+
+// lane l's value of v (ds_bpermute).  Call with every lane active: a
+// permute reads 0 from a lane that is masked off.
+__device__ __forceinline__ uint32_t from_lane(uint32_t v, int l)
+{
+    return (uint32_t)__builtin_amdgcn_ds_bpermute(l << 2, (int)v);
+}
+
+// last_two for an extension list that fits one wavefront and children
+// jlo..e-1: lane l holds E[l] with its code bits for positions k-2 and k-1
+// and its list row, so pair and neighbour items fetch them with one lane
+// permute each; pairs and neighbours share wave iterations.
+template <int K>
+__device__ void last_two_small(EnumState<K> &s, const int (&st)[K - 1],
+                               const int (&rem)[K - 2], int e, uint32_t code, int jlo)
+{
+    constexpr int NQ = K - 2;
+    constexpr int P1 = K - 2, P2 = K - 1;
+    constexpr int B_WU = (K - 2) * (K - 1) + (K - 2);
+    constexpr int B_UW = (K - 1) * (K - 1) + (K - 2);
+    const int lane = lane_id();
+    uint32_t vtx = 0, cb1 = 0, cb2 = 0;
+    int row = 0, deg = 0;
+    if (lane < e) {
+        vtx = s.seg[ext_addr<K, NQ>(s, st, rem, lane)];
+        const uint32_t m = s.mark[vtx];
+        cb1 = code_bits<K>(m, P1);
+        cb2 = code_bits<K>(m, P2);
+        row = s.urow[vtx];
+        deg = s.urow[vtx + 1] - row;
+    }
+    if (lane < jlo) deg = 0;
+    // children with long lists alone: only the arc type varies
+    unsigned long long big = __ballot(deg >= kRowMin);
+    while (big) {
+        const int l = __builtin_ctzll(big);
+        big &= big - 1;
+        const int brow = __builtin_amdgcn_readlane(row, l);
+        const int bdeg = __builtin_amdgcn_readlane(deg, l);
+        const uint32_t bcode = code | (uint32_t)__builtin_amdgcn_readlane((int)cb1, l);
+        uint32_t n1 = 0, n2 = 0, n3 = 0;
+        for (int b = 0; b < bdeg; b += kWave) {
+            const int e2 = b + lane;
+            uint32_t t = 0;
+            if (e2 < bdeg) {
+                const uint32_t ent = s.uadj[brow + e2];
+                const int u = (int)(ent >> 2);
+                if (u > s.root && s.mark[u] == 0u) t = ent & 3u;
+            }
+            n1 += (uint32_t)__popcll(__ballot(t == 1u));
+            n2 += (uint32_t)__popcll(__ballot(t == 2u));
+            n3 += (uint32_t)__popcll(__ballot(t == 3u));
+        }
+        const uint32_t tl = (uint32_t)lane + 1u;
+        const uint32_t nl = lane == 0 ? n1 : (lane == 1 ? n2 : n3);
+        s.hpending += n1 + n2 + n3;
+        hash_insert<K>(s, lane < 3 && nl > 0, bcode | ((tl & 1u) << B_WU) | ((tl >> 1) << B_UW), nl);
+    }
+    if (deg >= kRowMin) deg = 0;
+    int incl = deg;
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        const int o = __shfl_up(incl, d, kWave);
+        if (lane >= d) incl += o;
+    }
+    const int totB = uniform(__shfl(incl, kWave - 1, kWave));
+    uint32_t *pre = s.scratch;
+    pre[lane] = (uint32_t)incl;
+    __syncthreads();
+    const int mm = e - jlo;
+    const int npairs = mm * (mm - 1) / 2;
+    const int total = npairs + totB;
+    for (int base = 0; base < total; base += kWave) {
+        const int f = base + lane;
+        bool valid = f < total;
+        const bool pair = f < npairs;
+        // source lanes first; the permutes run with every lane active (a
+        // permute from an inactive lane reads 0)
+        int src1 = 0, src2 = 0, off = 0;
+        if (pair) {
+            int b = (int)((1.0f + __builtin_amdgcn_sqrtf(1.0f + 8.0f * (float)f)) * 0.5f);
+            b -= (b * (b - 1) / 2 > f) ? 1 : 0;
+            b += ((b + 1) * b / 2 <= f) ? 1 : 0;
+            src1 = jlo + (f - b * (b - 1) / 2);
+            src2 = jlo + b;
+        } else if (valid) {
+            const int fb = f - npairs;
+            int lo = 0;
+#pragma unroll
+            for (int step = kWave / 2; step > 0; step >>= 1)
+                lo += ((int)pre[lo + step - 1] <= fb) ? step : 0;
+            src1 = lo;
+            off = fb - (lo ? (int)pre[lo - 1] : 0);
+        }
+        const uint32_t w = from_lane(vtx, src1);
+        const uint32_t u2 = from_lane(vtx, src2);
+        const uint32_t c1 = from_lane(cb1, src1);
+        const uint32_t c2 = from_lane(cb2, src2);
+        const int r1 = (int)from_lane((uint32_t)row, src1);
+        uint32_t c = 0;
+        if (pair) {
+            const uint32_t t = pair_type<K>(s, w, u2);
+            c = code | c1 | c2 | ((t & 1u) << B_WU) | ((t >> 1) << B_UW);
+        } else if (valid) {
+            const uint32_t ent = s.uadj[r1 + off];
+            const int u = (int)(ent >> 2);
+            const uint32_t t = ent & 3u;
+            valid = u > s.root && s.mark[u] == 0u;
+            c = code | c1 | ((t & 1u) << B_WU) | ((t >> 1) << B_UW);
+        }
+        count_codes<K>(s, valid, c);
+    }
+    __syncthreads();
+}
+
 // The last two ESU levels of a node X with k-2 members s_0..s_{k-3} and
 // extension list E, done flat across the wavefront without adding members.
 // Child w = E[i] (i in [jlo, jhi)) closes the k-sets X + {w, u} for
@@ -381,6 +496,10 @@ __device__ void last_two(EnumState<K> &s, const int (&st)[K - 1], uint32_t code,
     }
     const int hi = e < jhi ? e : jhi;
     if (jlo >= hi) return;
+    if (e <= kWave && hi == e) {
+        last_two_small<K>(s, st, rem, e, code, jlo);
+        return;
+    }
 
     // (A) pairs (E[i], E[j]), j > i.  Long rows run one at a time with the
     // row's vertex w wave-uniform; the short rows left at the end run flat.
@@ -403,33 +522,46 @@ __device__ void last_two(EnumState<K> &s, const int (&st)[K - 1], uint32_t code,
             count_codes<K>(s, valid, c);
         }
     }
-    // flat: row r = i - i0 holds A - r pairs, A = e - 1 - i0 (< kRowMin here
-    // unless the range ends early)
+    // flat: the short rows left, i0 <= i < hi.  When they run to the end
+    // of E the pairs form the triangle a < b < m over E[i0..e) (m <= kRowMin),
+    // taken in b-major order: b = floor((1 + sqrt(1 + 8p)) / 2),
+    // a = p - b(b-1)/2.  Otherwise (a range-limited unit) row by row.
+    const int m = e - i0;
+    const bool tri = hi == e;
     const int A = e - 1 - i0;
     const int rows = hi - i0;
-    const int npairs = rows > 0 ? rows * A - rows * (rows - 1) / 2 : 0;
+    const int npairs = rows <= 0 ? 0 : (tri ? m * (m - 1) / 2 : rows * A - rows * (rows - 1) / 2);
     const float tA = 2.0f * (float)A + 1.0f;
     for (int base = 0; base < npairs; base += kWave) {
         const int p = base + lane;
         const bool valid = p < npairs;
         uint32_t c = 0;
         if (valid) {
-            float disc = tA * tA - 8.0f * (float)p;
-            disc = disc > 0.f ? disc : 0.f;
-            int r = (int)((tA - sqrtf(disc)) * 0.5f);
-            r = r < 0 ? 0 : (r > rows - 1 ? rows - 1 : r);
-            while (r + 1 < rows && (r + 1) * A - (r + 1) * r / 2 <= p) ++r;
-            while (r > 0 && r * A - r * (r - 1) / 2 > p) --r;
-            const int i = i0 + r;
-            const int j = i + 1 + (p - (r * A - r * (r - 1) / 2));
-            if (j < e) {
+            int i, j;
+            if (tri) {
+                int b = (int)((1.0f + __builtin_amdgcn_sqrtf(1.0f + 8.0f * (float)p)) * 0.5f);
+                b -= (b * (b - 1) / 2 > p) ? 1 : 0;
+                b += ((b + 1) * b / 2 <= p) ? 1 : 0;
+                i = i0 + (p - b * (b - 1) / 2);
+                j = i0 + b;
+            } else {
+                float disc = tA * tA - 8.0f * (float)p;
+                disc = disc > 0.f ? disc : 0.f;
+                int r = (int)((tA - __builtin_amdgcn_sqrtf(disc)) * 0.5f);
+                r = r < 0 ? 0 : (r > rows - 1 ? rows - 1 : r);
+                while (r + 1 < rows && (r + 1) * A - (r + 1) * r / 2 <= p) ++r;
+                while (r > 0 && r * A - r * (r - 1) / 2 > p) --r;
+                i = i0 + r;
+                j = i + 1 + (p - (r * A - r * (r - 1) / 2));
+            }
+            if (i < j && j < e) {
                 const uint32_t w = s.seg[ext_addr<K, NQ>(s, st, rem, i)];
                 const uint32_t u = s.seg[ext_addr<K, NQ>(s, st, rem, j)];
                 const uint32_t t = pair_type<K>(s, w, u);
                 c = code | code_bits<K>(s.mark[w], P1) | code_bits<K>(s.mark[u], P2) |
                     ((t & 1u) << B_WU) | ((t >> 1) << B_UW);
             } else {
-                atomicAdd(s.errors, 1u);  // unreachable: row search keeps j < e
+                atomicAdd(s.errors, 1u);  // unreachable: the decode keeps i < j < e
             }
         }
         count_codes<K>(s, valid && c != 0, c);
@@ -493,12 +625,11 @@ __device__ void last_two(EnumState<K> &s, const int (&st)[K - 1], uint32_t code,
             bool valid = f < tot;
             uint32_t c = 0;
             if (valid) {
-                int lo = 0, up = kWave - 1;
-                while (lo < up) {
-                    const int mid = (lo + up) >> 1;
-                    if ((int)pre[mid] > f) up = mid;
-                    else lo = mid + 1;
-                }
+                // first child lane whose inclusive degree prefix exceeds f
+                int lo = 0;
+#pragma unroll
+                for (int step = kWave / 2; step > 0; step >>= 1)
+                    lo += ((int)pre[lo + step - 1] <= f) ? step : 0;
                 const int before = lo ? (int)pre[lo - 1] : 0;
                 const uint32_t ent = s.uadj[start[lo] + (uint32_t)(f - before)];
                 const int u = (int)(ent >> 2);
