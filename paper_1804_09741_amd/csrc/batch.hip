@@ -29,6 +29,8 @@ struct mk_batch {
     uint64_t bits_words = 0;
     uint32_t *d_slot_cnt = nullptr;
     uint32_t *d_slot_off = nullptr;
+    uint32_t *d_slot_est = nullptr;
+    uint32_t *d_slot_vi = nullptr;
     uint32_t *d_scan_tmp = nullptr;
     uint32_t total_slots = 0;
     int4 *d_units = nullptr;
@@ -38,6 +40,7 @@ struct mk_batch {
     unsigned long long *hist_last = nullptr;
 
     int max_n = 0, max_words = 0, seg_cap = 0;
+    int64_t max_m = 0;
     int64_t max_nnz = 0;
     int grid = 0, max_grid = 0, lds_bytes = 0;
     uint64_t units = 0, split_pairs = 0;
@@ -123,7 +126,8 @@ static void batch_release(mk_batch *b)
         if (e) (void)hipEventDestroy(e);
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
     if (b->graph) (void)hipGraphDestroy(b->graph);
-    void *bufs[] = {b->d_graphs, b->d_ws, b->d_slot_cnt, b->d_slot_off, b->d_scan_tmp,
+    void *bufs[] = {b->d_graphs, b->d_ws, b->d_slot_cnt, b->d_slot_off, b->d_slot_est,
+                    b->d_slot_vi, b->d_scan_tmp,
                     b->d_units, b->d_counters, b->d_hist_own};
     for (void *p : bufs)
         if (p) (void)hipFree(p);
@@ -147,11 +151,12 @@ static int batch_enqueue_prep(mk_batch *b, unsigned long long *hist, hipStream_t
     if (rc) return rc;
     rc = fill_u32(hist, 0, (size_t)b->ng * b->table->num_classes * 2, stream);
     if (rc) return rc;
-    rc = launch_typed_csr(b->d_graphs, b->ng, b->max_n, b->max_words, b->bits_words, b->d_ws,
+    rc = launch_typed_csr(b->d_graphs, b->ng, b->max_n, b->max_m, b->bits_words, b->d_ws,
                           b->d_counters, stream);
     if (rc) return rc;
     return launch_plan(b->k, b->d_graphs, b->ng, b->max_nnz, b->total_slots, b->d_slot_cnt,
-                       b->d_slot_off, b->d_scan_tmp, b->d_units, b->unit_cap,
+                       b->d_slot_off, b->d_slot_est, b->d_slot_vi, b->d_scan_tmp, b->d_units,
+                       b->unit_cap,
                        b->opts.split_threshold, (uint32_t)b->max_grid, b->d_counters, stream);
 }
 
@@ -203,6 +208,7 @@ extern "C" int mk_batch_create(mk_ctx *ctx, const mk_graph *const *gs, int32_t n
         b->max_words = std::max<int>(b->max_words, (int)w);
         b->seg_cap = std::max(b->seg_cap, g->max_udeg);
         b->max_nnz = std::max<int64_t>(b->max_nnz, g->nnz_u);
+        b->max_m = std::max<int64_t>(b->max_m, g->m);
         slots += (uint64_t)g->nnz_u;
     }
     if (slots >= 0xFFFFFFFFull) {
@@ -262,6 +268,8 @@ extern "C" int mk_batch_create(mk_ctx *ctx, const mk_graph *const *gs, int32_t n
                                 hipMemcpyHostToDevice, ctx->stream));
     BAIL_HIP(hipMalloc(&b->d_slot_cnt, sizeof(uint32_t) * std::max<uint64_t>(slots, 1)));
     BAIL_HIP(hipMalloc(&b->d_slot_off, sizeof(uint32_t) * std::max<uint64_t>(slots, 1)));
+    BAIL_HIP(hipMalloc(&b->d_slot_est, sizeof(uint32_t) * std::max<uint64_t>(slots, 1)));
+    BAIL_HIP(hipMalloc(&b->d_slot_vi, sizeof(uint32_t) * std::max<uint64_t>(slots, 1)));
     BAIL_HIP(hipMalloc(&b->d_scan_tmp, sizeof(uint32_t) * scan_tmp_words(slots)));
     BAIL_HIP(hipMalloc(&b->d_counters, sizeof(uint32_t) * kNumCounters));
     for (hipEvent_t &e : b->ev) BAIL_HIP(hipEventCreate(&e));
@@ -276,11 +284,12 @@ extern "C" int mk_batch_create(mk_ctx *ctx, const mk_graph *const *gs, int32_t n
     // sizing pass: typed adjacency + unit counts only
     rc = fill_u32(b->d_counters, 0, kNumCounters, ctx->stream);
     if (!rc)
-        rc = launch_typed_csr(b->d_graphs, ng, b->max_n, b->max_words, bits, b->d_ws,
+        rc = launch_typed_csr(b->d_graphs, ng, b->max_n, b->max_m, bits, b->d_ws,
                               b->d_counters, ctx->stream);
     if (!rc)
         rc = launch_plan(b->k, b->d_graphs, ng, b->max_nnz, b->total_slots, b->d_slot_cnt,
-                         b->d_slot_off, b->d_scan_tmp, nullptr, 0, b->opts.split_threshold,
+                         b->d_slot_off, b->d_slot_est, b->d_slot_vi, b->d_scan_tmp, nullptr, 0,
+                         b->opts.split_threshold,
                          (uint32_t)b->max_grid, b->d_counters, ctx->stream);
     if (rc) return bail(rc);
     uint32_t cnt[kNumCounters];
@@ -417,7 +426,7 @@ uint64_t batch_device_bytes(const mk_batch *b)
         const uint64_t n = (uint64_t)g->n, w = (n + 31) / 32;
         words += 2 * n * w + n + 1 + (uint64_t)g->nnz_u;
     }
-    return 4 * words + 8ull * b->total_slots + 4 * scan_tmp_words(b->total_slots) +
+    return 4 * words + 16ull * b->total_slots + 4 * scan_tmp_words(b->total_slots) +
            16ull * b->unit_cap + 8ull * b->ng * b->table->num_classes +
            sizeof(DevGraph) * b->graphs.size() + 4 * kNumCounters;
 }

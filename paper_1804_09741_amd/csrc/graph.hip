@@ -19,17 +19,22 @@ namespace mk {
 
 constexpr int kRowThreads = 256;
 
+// one thread per arc u -> v (u found by binary search in the out-CSR)
 __global__ void arcs_kernel(const DevGraph *graphs)
 {
     const DevGraph &g = graphs[blockIdx.y];
-    const int u = blockIdx.x * blockDim.x + threadIdx.x;
-    if (u >= g.n) return;
-    const int w = g.words;
-    for (int e = g.out_row[u]; e < g.out_row[u + 1]; ++e) {
-        const int v = g.out_col[e];
-        atomicOr(&g.bits_out[(size_t)u * w + (v >> 5)], 1u << (v & 31));
-        atomicOr(&g.bits_in[(size_t)v * w + (u >> 5)], 1u << (u & 31));
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g.n == 0 || e >= g.out_row[g.n]) return;
+    int lo = 0, hi = g.n;  // u with out_row[u] <= e < out_row[u+1]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (g.out_row[mid] <= e) lo = mid;
+        else hi = mid;
     }
+    const int u = lo, v = g.out_col[e];
+    const int w = g.words;
+    atomicOr(&g.bits_out[(size_t)u * w + (v >> 5)], 1u << (v & 31));
+    atomicOr(&g.bits_in[(size_t)v * w + (u >> 5)], 1u << (u & 31));
 }
 
 __global__ void degree_kernel(const DevGraph *graphs)
@@ -102,16 +107,17 @@ __global__ void adjfill_kernel(const DevGraph *graphs, uint32_t *counters)
     }
 }
 
-int launch_typed_csr(const DevGraph *d_graphs, int ng, int max_n, int max_words,
+int launch_typed_csr(const DevGraph *d_graphs, int ng, int max_n, int64_t max_m,
                      uint64_t bits_words_total, uint32_t *bits_base, uint32_t *counters,
                      hipStream_t stream)
 {
-    (void)max_words;
     if (ng <= 0) return MK_OK;
     int rc = fill_u32(bits_base, 0, bits_words_total, stream);
     if (rc != MK_OK) return rc;
     const dim3 grid((unsigned)((max_n + 1 + kRowThreads - 1) / kRowThreads), (unsigned)ng);
-    hipLaunchKernelGGL(arcs_kernel, grid, dim3(kRowThreads), 0, stream, d_graphs);
+    const dim3 agrid((unsigned)std::max<int64_t>((max_m + kRowThreads - 1) / kRowThreads, 1),
+                     (unsigned)ng);
+    hipLaunchKernelGGL(arcs_kernel, agrid, dim3(kRowThreads), 0, stream, d_graphs);
     MK_HIP(hipGetLastError());
     hipLaunchKernelGGL(degree_kernel, grid, dim3(kRowThreads), 0, stream, d_graphs);
     MK_HIP(hipGetLastError());

@@ -120,7 +120,7 @@ int build_table(Table *t, hipStream_t stream);
 
 // Typed symmetric adjacency of every graph of a batch (bit matrices
 // zeroed, arcs set, degrees counted and scanned, lists written).
-int launch_typed_csr(const DevGraph *d_graphs, int ng, int max_n, int max_words,
+int launch_typed_csr(const DevGraph *d_graphs, int ng, int max_n, int64_t max_m,
                      uint64_t bits_words_total, uint32_t *bits_base, uint32_t *counters,
                      hipStream_t stream);
 
@@ -128,9 +128,9 @@ int launch_typed_csr(const DevGraph *d_graphs, int ng, int max_n, int max_words,
 // nullptr: sizing only).  Writes counters[kNumUnits].  The split threshold
 // is max(split_threshold, estimated total / (waves * 16)).
 int launch_plan(int k, const DevGraph *d_graphs, int ng, int64_t max_nnz, uint32_t total_slots,
-                uint32_t *slot_cnt, uint32_t *slot_off, uint32_t *scan_tmp, int4 *units,
-                uint32_t unit_cap, uint64_t split_threshold, uint32_t waves, uint32_t *counters,
-                hipStream_t stream);
+                uint32_t *slot_cnt, uint32_t *slot_off, uint32_t *slot_est, uint32_t *slot_vi,
+                uint32_t *scan_tmp, int4 *units, uint32_t unit_cap, uint64_t split_threshold,
+                uint32_t waves, uint32_t *counters, hipStream_t stream);
 
 // Enumeration + code + lookup + histogram over the queued units.
 int enum_lds_bytes(int k, int max_n, int seg_cap);

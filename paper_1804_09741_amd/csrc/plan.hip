@@ -81,12 +81,65 @@ __device__ __forceinline__ uint64_t effective_threshold(const uint32_t *counters
     return adaptive > floor_t ? adaptive : floor_t;
 }
 
+// Per-slot record of the estimate pass: (v, i) of a first-level node packed
+// as v | i << 13 (n <= 8192, degrees <= 4096), or kNoNode for a slot whose
+// neighbour is not above its owner.
+constexpr uint32_t kNoNode = 0xFFFFFFFFu;
+
+// greedy ranges over the children of (v, w_i): calls put(r, j0 | j1 << 16)
+// for every range when EMIT, returns the number of ranges
+template <int K, bool EMIT, typename Put>
+__device__ __forceinline__ uint32_t split_children(const DevGraph &g, int v, int first, int r1,
+                                                   int i, int y, int L2, uint64_t threshold,
+                                                   uint64_t *est, Put put)
+{
+    uint32_t cnt = 0;
+    int j = 0, j0 = 0;
+    uint64_t acc = 0;
+    auto child = [&](int x) {
+        const int dx = g.urow[x + 1] - g.urow[x];
+        const uint64_t cj = choose_small(L2 - j - 1 + dx - 1, K - 3) + 1;
+        *est += cj;
+        if (j > j0 && acc + cj > threshold) {
+            if (EMIT) put(cnt, (uint32_t)j0 | ((uint32_t)j << 16));
+            ++cnt;
+            j0 = j;
+            acc = 0;
+        }
+        acc += cj;
+        ++j;
+    };
+    for (int t = first + i + 1; t < r1; ++t) child((int)(g.uadj[t] >> 2));
+    for (int t = g.urow[y]; t < g.urow[y + 1]; ++t) {
+        const int x = (int)(g.uadj[t] >> 2);
+        if (x > v && !adjacent(g, v, x)) child(x);
+    }
+    if (L2 > j0) {
+        if (EMIT) put(cnt, (uint32_t)j0 | ((uint32_t)L2 << 16));
+        ++cnt;
+    }
+    return cnt;
+}
+
+// extension length L2 of the node (v, w_i = y)
+__device__ __forceinline__ int ext_len(const DevGraph &g, int v, int ext_v, int i, int y)
+{
+    int fresh = 0;
+    for (int t = g.urow[y]; t < g.urow[y + 1]; ++t) {
+        const int x = (int)(g.uadj[t] >> 2);
+        if (x > v && !adjacent(g, v, x)) ++fresh;
+    }
+    return ext_v - i - 1 + fresh;
+}
+
 template <int K, int PASS>
 __global__ __launch_bounds__(kPlanThreads) void plan_kernel(const DevGraph *graphs,
                                                             uint32_t *slot_cnt,
-                                                            const uint32_t *slot_off, int4 *units,
-                                                            uint32_t unit_cap, uint64_t floor_t,
-                                                            uint32_t waves, uint32_t *counters)
+                                                            const uint32_t *slot_off,
+                                                            uint32_t *slot_est, uint32_t *slot_vi,
+                                                            int4 *units, uint32_t unit_cap,
+                                                            uint64_t floor_t, uint32_t waves,
+                                                            uint32_t *counters)
 {
     const int gi = blockIdx.y;
     const DevGraph &g = graphs[gi];
@@ -96,63 +149,63 @@ __global__ __launch_bounds__(kPlanThreads) void plan_kernel(const DevGraph *grap
     const uint64_t threshold = PASS == kEstimate ? ~0ull : effective_threshold(counters, floor_t, waves);
     if (live) {
         const uint32_t slot = g.slot_base + (uint32_t)e;
-        const int v = owner_of(g.urow, g.n, e);
         const int y = (int)(g.uadj[e] >> 2);
-        uint32_t cnt = 0;
-        if (y > v) {
-            const int r1 = g.urow[v + 1];
-            const int first = first_above(g.uadj, g.urow[v], r1, v);
-            const int i = e - first;
-            const int ext_v = r1 - first;
-            int fresh = 0;
-            for (int t = g.urow[y]; t < g.urow[y + 1]; ++t) {
-                const int x = (int)(g.uadj[t] >> 2);
-                if (x > v && !adjacent(g, v, x)) ++fresh;
+        if (PASS == kEstimate) {
+            // the full walk: owner, position, extension length, child costs
+            const int v = owner_of(g.urow, g.n, e);
+            uint32_t vi = kNoNode;
+            if (y > v) {
+                const int r1 = g.urow[v + 1];
+                const int first = first_above(g.uadj, g.urow[v], r1, v);
+                const int i = e - first;
+                const int L2 = ext_len(g, v, r1 - first, i, y);
+                if (K == 3) est = (uint64_t)L2 + 1;
+                else split_children<K, false>(g, v, first, r1, i, y, L2, ~0ull, &est,
+                                              [](uint32_t, uint32_t) {});
+                vi = (uint32_t)v | ((uint32_t)i << 13);
             }
-            const int L2 = ext_v - i - 1 + fresh;
-            uint32_t base = 0;
-            if (PASS == kEmit) base = slot_off[slot];
-            auto put = [&](uint32_t r, uint32_t w) {
-                const uint32_t idx = base + r;
-                if (idx < unit_cap) units[idx] = make_int4(gi, v, i, (int)w);
-                else atomicOr(&counters[kErrors], 1u);
-            };
-            if (K == 3) {
-                if (PASS == kEmit) put(0, kFullChild);
-                cnt = 1;
-                est = (uint64_t)L2 + 1;
-            } else {
-                // children j of (v, w_i) in extension order: E_v[i+1:] then
-                // the exclusive neighbours of w_i; greedy ranges of estimated
-                // cost
-                int j = 0, j0 = 0;
-                uint64_t acc = 0;
-                auto child = [&](int x) {
-                    const int dx = g.urow[x + 1] - g.urow[x];
-                    const uint64_t cj = choose_small(L2 - j - 1 + dx - 1, K - 3) + 1;
-                    est += cj;
-                    if (j > j0 && acc + cj > threshold) {
-                        if (PASS == kEmit) put(cnt, (uint32_t)j0 | ((uint32_t)j << 16));
-                        ++cnt;
-                        j0 = j;
-                        acc = 0;
-                    }
-                    acc += cj;
-                    ++j;
-                };
-                for (int t = first + i + 1; t < r1; ++t) child((int)(g.uadj[t] >> 2));
-                for (int t = g.urow[y]; t < g.urow[y + 1]; ++t) {
-                    const int x = (int)(g.uadj[t] >> 2);
-                    if (x > v && !adjacent(g, v, x)) child(x);
+            slot_vi[slot] = vi;
+            slot_est[slot] = est > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)est;
+        } else {
+            const uint32_t vi = slot_vi[slot];
+            const uint32_t sest = slot_est[slot];
+            uint32_t cnt = 0;
+            if (vi != kNoNode) {
+                const int v = (int)(vi & 0x1FFFu), i = (int)(vi >> 13);
+                const bool split = K > 3 && sest != 0xFFFFFFFFu && sest > threshold
+                                       ? true : (K > 3 && sest == 0xFFFFFFFFu);
+                if (K == 3) {
+                    cnt = 1;
+                } else if (sest <= 1 && !split) {
+                    // no children below (v, w_i): L2 == 0 gives est 0
+                    cnt = sest == 0 ? 0 : 1;
+                } else if (!split) {
+                    cnt = 1;
+                } else {
+                    const int r1 = g.urow[v + 1];
+                    const int first = e - i;
+                    const int L2 = ext_len(g, v, r1 - first, i, y);
+                    uint32_t base = 0;
+                    if (PASS == kEmit) base = slot_off[slot];
+                    auto put = [&](uint32_t r, uint32_t w) {
+                        const uint32_t idx = base + r;
+                        if (idx < unit_cap) units[idx] = make_int4(gi, v, i, (int)w);
+                        else atomicOr(&counters[kErrors], 1u);
+                    };
+                    uint64_t dummy = 0;
+                    cnt = PASS == kEmit
+                              ? split_children<K, true>(g, v, first, r1, i, y, L2, threshold, &dummy, put)
+                              : split_children<K, false>(g, v, first, r1, i, y, L2, threshold, &dummy, put);
+                    if (PASS == kCount && cnt > 1) atomicAdd(&counters[kSplitPairs], 1u);
                 }
-                if (L2 > j0) {
-                    if (PASS == kEmit) put(cnt, (uint32_t)j0 | ((uint32_t)L2 << 16));
-                    ++cnt;
+                if (PASS == kEmit && cnt == 1 && !(K > 3 && split)) {
+                    const uint32_t idx = slot_off[slot];
+                    if (idx < unit_cap) units[idx] = make_int4(gi, v, i, (int)kFullChild);
+                    else atomicOr(&counters[kErrors], 1u);
                 }
-                if (PASS == kCount && cnt > 1) atomicAdd(&counters[kSplitPairs], 1u);
             }
+            if (PASS == kCount) slot_cnt[slot] = cnt;
         }
-        if (PASS == kCount) slot_cnt[slot] = cnt;
     }
     if (PASS == kEstimate) {
         // workgroup sum, one 64-bit atomic per workgroup
@@ -172,9 +225,9 @@ __global__ __launch_bounds__(kPlanThreads) void plan_kernel(const DevGraph *grap
 
 template <int K>
 static int plan_k(const DevGraph *d_graphs, int ng, int64_t max_nnz, uint32_t total_slots,
-                  uint32_t *slot_cnt, uint32_t *slot_off, uint32_t *scan_tmp, int4 *units,
-                  uint32_t unit_cap, uint64_t threshold, uint32_t waves, uint32_t *counters,
-                  hipStream_t stream)
+                  uint32_t *slot_cnt, uint32_t *slot_off, uint32_t *slot_est, uint32_t *slot_vi,
+                  uint32_t *scan_tmp, int4 *units, uint32_t unit_cap, uint64_t threshold,
+                  uint32_t waves, uint32_t *counters, hipStream_t stream)
 {
     const dim3 grid((unsigned)((max_nnz + kPlanThreads - 1) / kPlanThreads > 0
                                    ? (max_nnz + kPlanThreads - 1) / kPlanThreads
@@ -182,42 +235,42 @@ static int plan_k(const DevGraph *d_graphs, int ng, int64_t max_nnz, uint32_t to
                     (unsigned)ng);
     int rc = fill_u32(counters + kEstTotal, 0, 2, stream);
     if (rc != MK_OK) return rc;
-    if (K > 3) {
-        hipLaunchKernelGGL((plan_kernel<K, kEstimate>), grid, dim3(kPlanThreads), 0, stream,
-                           d_graphs, slot_cnt, slot_off, units, unit_cap, threshold, waves,
-                           counters);
-        MK_HIP(hipGetLastError());
-    }
+    hipLaunchKernelGGL((plan_kernel<K, kEstimate>), grid, dim3(kPlanThreads), 0, stream, d_graphs,
+                       slot_cnt, slot_off, slot_est, slot_vi, units, unit_cap, threshold, waves,
+                       counters);
+    MK_HIP(hipGetLastError());
     hipLaunchKernelGGL((plan_kernel<K, kCount>), grid, dim3(kPlanThreads), 0, stream, d_graphs,
-                       slot_cnt, slot_off, units, unit_cap, threshold, waves, counters);
+                       slot_cnt, slot_off, slot_est, slot_vi, units, unit_cap, threshold, waves,
+                       counters);
     MK_HIP(hipGetLastError());
     rc = scan_u32(slot_cnt, slot_off, total_slots, 0, &counters[kNumUnits], scan_tmp, stream);
     if (rc != MK_OK) return rc;
     if (!units) return MK_OK;  // sizing pass
     hipLaunchKernelGGL((plan_kernel<K, kEmit>), grid, dim3(kPlanThreads), 0, stream, d_graphs,
-                       slot_cnt, slot_off, units, unit_cap, threshold, waves, counters);
+                       slot_cnt, slot_off, slot_est, slot_vi, units, unit_cap, threshold, waves,
+                       counters);
     MK_HIP(hipGetLastError());
     return MK_OK;
 }
 
 int launch_plan(int k, const DevGraph *d_graphs, int ng, int64_t max_nnz, uint32_t total_slots,
-                uint32_t *slot_cnt, uint32_t *slot_off, uint32_t *scan_tmp, int4 *units,
-                uint32_t unit_cap, uint64_t split_threshold, uint32_t waves, uint32_t *counters,
-                hipStream_t stream)
+                uint32_t *slot_cnt, uint32_t *slot_off, uint32_t *slot_est, uint32_t *slot_vi,
+                uint32_t *scan_tmp, int4 *units, uint32_t unit_cap, uint64_t split_threshold,
+                uint32_t waves, uint32_t *counters, hipStream_t stream)
 {
     if (ng <= 0) return MK_OK;
     switch (k) {
     case 3:
-        return plan_k<3>(d_graphs, ng, max_nnz, total_slots, slot_cnt, slot_off, scan_tmp, units,
+        return plan_k<3>(d_graphs, ng, max_nnz, total_slots, slot_cnt, slot_off, slot_est, slot_vi, scan_tmp, units,
                          unit_cap, split_threshold, waves, counters, stream);
     case 4:
-        return plan_k<4>(d_graphs, ng, max_nnz, total_slots, slot_cnt, slot_off, scan_tmp, units,
+        return plan_k<4>(d_graphs, ng, max_nnz, total_slots, slot_cnt, slot_off, slot_est, slot_vi, scan_tmp, units,
                          unit_cap, split_threshold, waves, counters, stream);
     case 5:
-        return plan_k<5>(d_graphs, ng, max_nnz, total_slots, slot_cnt, slot_off, scan_tmp, units,
+        return plan_k<5>(d_graphs, ng, max_nnz, total_slots, slot_cnt, slot_off, slot_est, slot_vi, scan_tmp, units,
                          unit_cap, split_threshold, waves, counters, stream);
     case 6:
-        return plan_k<6>(d_graphs, ng, max_nnz, total_slots, slot_cnt, slot_off, scan_tmp, units,
+        return plan_k<6>(d_graphs, ng, max_nnz, total_slots, slot_cnt, slot_off, slot_est, slot_vi, scan_tmp, units,
                          unit_cap, split_threshold, waves, counters, stream);
     default: return fail(MK_ERANGE, "k=%d outside 3..6", k);
     }
