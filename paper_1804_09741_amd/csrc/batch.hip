@@ -460,6 +460,25 @@ int batch_enum_slice(mk_batch *b, uint32_t begin, uint32_t end, hipStream_t stre
                        grid, b->lds_bytes, stream);
 }
 
+// Copy the histograms of a prepared batch whose last slice is known to be
+// finished (its event completed) on `copy_stream`, check the device-side
+// counters, and wait only for that copy.
+int batch_collect(mk_batch *b, uint64_t *hist, hipStream_t copy_stream)
+{
+    MK_HIP(hipSetDevice(b->ctx->device));
+    if (b->ng == 0) return MK_OK;
+    uint32_t cnt[kNumCounters];
+    MK_HIP(hipMemcpyAsync(cnt, b->d_counters, sizeof(cnt), hipMemcpyDeviceToHost, copy_stream));
+    MK_HIP(hipMemcpyAsync(hist, b->d_hist_own,
+                          sizeof(uint64_t) * (size_t)b->ng * b->table->num_classes,
+                          hipMemcpyDeviceToHost, copy_stream));
+    MK_HIP(hipStreamSynchronize(copy_stream));
+    if (cnt[kErrors] != 0 || cnt[kAdjOverflow] != 0)
+        return fail(MK_EDEVICE, "device-side check failed (%u lookup/plan errors, %u adjacency overflows)",
+                    cnt[kErrors], cnt[kAdjOverflow]);
+    return MK_OK;
+}
+
 }  // namespace mk
 
 extern "C" int mk_batch_timing(mk_batch *b, double *pass_ms, double *enum_ms)

@@ -162,6 +162,7 @@ uint64_t batch_units(const mk_batch *b);
 uint64_t batch_device_bytes(const mk_batch *b);
 int batch_prepare(mk_batch *b, hipStream_t stream);
 int batch_enum_slice(mk_batch *b, uint32_t begin, uint32_t end, hipStream_t stream);
+int batch_collect(mk_batch *b, uint64_t *hist, hipStream_t copy_stream);
 
 }  // namespace mk
 

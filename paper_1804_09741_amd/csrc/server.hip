@@ -8,17 +8,20 @@
 //   submit   -> FIFO queue
 //   admit    -> while the head fits the HBM budget and a slot is free: plan it
 //               (typed adjacency + work units) on one of the server's streams
-//   tick     -> every admitted request gets a slice of at most tick_units of
-//               its work units, launched on its stream; the slices of all
-//               requests run on the device together
+//   slices   -> every admitted request has one slice of at most tick_units
+//               of its work units in flight on its stream; a HIP event marks
+//               the slice's end, and the server thread (polling the events)
+//               launches the request's next slice as soon as it is done
 //   complete -> a request whose units are all done has its histogram copied
-//               out, its memory released, and its waiter woken
+//               out on a separate copy stream, its memory released, and its
+//               waiter woken
 //
-// A request that arrives while others run is admitted at the next tick and
-// shares the device with them from then on; a long request cannot hold the
-// device for longer than one slice.  Each request has its own histogram and
-// its slices cover its units exactly once, so its result is the same as when
-// it runs alone.
+// A request that arrives while others run is admitted as soon as a slot and
+// the memory budget allow, and its slices then share the device with
+// everyone else's; a long request holds a stream for at most one slice at a
+// time.  There is no global barrier between slices.  Each request has its
+// own histogram and its slices cover its units exactly once, so its result
+// is the same as when it runs alone.
 #include <chrono>
 #include <condition_variable>
 #include <deque>
@@ -31,7 +34,7 @@ using namespace mk;
 
 namespace {
 
-constexpr int kServerStreams = 4;
+constexpr int kServerStreams = 8;
 constexpr uint64_t kDefaultBudget = 8ull << 30;
 constexpr int kDefaultSlots = 64;
 constexpr int kDefaultTickUnits = 8192;
@@ -50,6 +53,8 @@ struct Request {
     mk_batch *batch = nullptr;
     uint64_t units = 0, cursor = 0;
     int stream = 0;
+    hipEvent_t ev = nullptr;  // end of the work last launched for the request
+    bool inflight = false;
     std::vector<uint64_t> hist;
     mk_request_times times{};
 };
@@ -70,6 +75,10 @@ struct mk_server {
     bool stopping = false;
     int next_stream = 0;
     hipStream_t streams[kServerStreams] = {};
+    hipStream_t copy_stream = nullptr;
+    // finished requests' batches, freed only when nothing runs (a free can
+    // wait for every kernel in flight); their bytes stay in used_bytes
+    std::vector<std::pair<mk_batch *, uint64_t>> graveyard;
     std::chrono::steady_clock::time_point t0;
 
     double now_us() const
@@ -81,17 +90,40 @@ struct mk_server {
 
 static void finish(mk_server *s, Request *r, State st, int status, const char *why)
 {
-    if (r->batch) {
-        mk_batch_free(r->batch);
-        r->batch = nullptr;
-    }
     std::lock_guard<std::mutex> lock(s->mu);
+    if (r->batch) {
+        s->graveyard.emplace_back(r->batch, r->bytes);
+        r->batch = nullptr;
+    } else {
+        s->used_bytes -= std::min(s->used_bytes, r->bytes);
+    }
+    if (r->ev) {
+        (void)hipEventDestroy(r->ev);
+        r->ev = nullptr;
+    }
     r->state = st;
     r->status = status;
     if (why) r->error = why;
     r->times.done_us = s->now_us();
-    s->used_bytes -= std::min(s->used_bytes, r->bytes);
     s->cv_done.notify_all();
+}
+
+// free the finished batches (call when no request is in flight, or when
+// their memory is needed)
+static void bury(mk_server *s)
+{
+    std::vector<std::pair<mk_batch *, uint64_t>> g;
+    {
+        std::lock_guard<std::mutex> lock(s->mu);
+        g.swap(s->graveyard);
+    }
+    uint64_t freed = 0;
+    for (auto &e : g) {
+        mk_batch_free(e.first);
+        freed += e.second;
+    }
+    std::lock_guard<std::mutex> lock(s->mu);
+    s->used_bytes -= std::min(s->used_bytes, freed);
 }
 
 // plan an admitted request on its stream; false if it failed
@@ -105,6 +137,12 @@ static bool start_request(mk_server *s, Request *r)
         rc = mk_batch_create(s->ctx, &r->g, 1, t, &o, &r->batch);
     }
     if (rc == MK_OK) rc = batch_prepare(r->batch, s->streams[r->stream]);
+    if (rc == MK_OK) {
+        hipError_t e = hipEventCreateWithFlags(&r->ev, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventRecord(r->ev, s->streams[r->stream]);
+        if (e != hipSuccess) rc = fail(MK_EDEVICE, "server event: %s", hipGetErrorString(e));
+        r->inflight = true;
+    }
     if (rc != MK_OK) {
         finish(s, r, State::Failed, rc, mk_last_error());
         return false;
@@ -125,17 +163,26 @@ static void server_loop(mk_server *s)
     const size_t slots = (size_t)s->opts.max_slots;
     const uint64_t tick = (uint64_t)s->opts.tick_units;
     for (;;) {
+        bool need_bury = false;
+        {
+            std::lock_guard<std::mutex> lock(s->mu);
+            const bool blocked = !s->queue.empty() &&
+                                 s->used_bytes + s->queue.front()->est_bytes > budget;
+            need_bury = !s->graveyard.empty() && (s->active.empty() || blocked);
+        }
+        if (need_bury) bury(s);
         std::vector<Request *> admitted;
         {
             std::unique_lock<std::mutex> lock(s->mu);
-            s->cv_work.wait(lock, [&] {
-                return s->stopping || !s->active.empty() ||
-                       (!s->queue.empty() && s->active.size() < slots &&
-                        s->used_bytes + s->queue.front()->est_bytes <= budget);
-            });
-            if (s->stopping && s->queue.empty() && s->active.empty()) break;
-            while (!s->queue.empty() && s->active.size() + admitted.size() < slots &&
-                   s->used_bytes + s->queue.front()->est_bytes <= budget) {
+            auto can_admit = [&] {
+                return !s->queue.empty() && s->active.size() + admitted.size() < slots &&
+                       s->used_bytes + s->queue.front()->est_bytes <= budget;
+            };
+            if (s->active.empty() && s->graveyard.empty())
+                s->cv_work.wait(lock, [&] { return s->stopping || can_admit(); });
+            if (s->stopping && s->queue.empty() && s->active.empty() && s->graveyard.empty())
+                break;
+            while (can_admit()) {
                 Request *r = s->queue.front();
                 s->queue.pop_front();
                 r->state = State::Active;
@@ -149,36 +196,55 @@ static void server_loop(mk_server *s)
         for (Request *r : admitted)
             if (start_request(s, r)) s->active.push_back(r);
 
-        // one tick: a slice of every active request, all in flight together
-        bool used[kServerStreams] = {};
+        bool progress = !admitted.empty();
+        // finished slices
         for (Request *r : s->active) {
-            const uint64_t end = std::min(r->units, r->cursor + tick);
-            int rc = batch_enum_slice(r->batch, (uint32_t)r->cursor, (uint32_t)end,
-                                      s->streams[r->stream]);
-            if (rc != MK_OK) {
-                r->status = rc;
+            if (!r->inflight) continue;
+            const hipError_t q = hipEventQuery(r->ev);
+            if (q == hipSuccess) {
+                r->inflight = false;
+                progress = true;
+            } else if (q != hipErrorNotReady) {
+                r->status = fail(MK_EDEVICE, "request %llu: %s", (unsigned long long)r->ticket,
+                                 hipGetErrorString(q));
                 r->error = mk_last_error();
+                r->inflight = false;
                 r->cursor = r->units;
-            } else {
-                r->cursor = end;
             }
-            used[r->stream] = true;
         }
-        for (int i = 0; i < kServerStreams; ++i)
-            if (used[i]) (void)hipStreamSynchronize(s->streams[i]);
-
+        // next slices, and completions
         std::vector<Request *> still;
         for (Request *r : s->active) {
-            if (r->cursor < r->units) {
+            if (r->inflight) {
                 still.push_back(r);
                 continue;
             }
+            if (r->cursor < r->units && r->status == MK_OK) {
+                const uint64_t end = std::min(r->units, r->cursor + tick);
+                hipStream_t st = s->streams[r->stream];
+                int rc = batch_enum_slice(r->batch, (uint32_t)r->cursor, (uint32_t)end, st);
+                if (rc == MK_OK && hipEventRecord(r->ev, st) != hipSuccess)
+                    rc = fail(MK_EDEVICE, "server event record failed");
+                if (rc == MK_OK) {
+                    r->cursor = end;
+                    r->inflight = true;
+                    progress = true;
+                    still.push_back(r);
+                    continue;
+                }
+                // a failed launch ends the request now (reported below)
+                r->status = rc;
+                r->error = mk_last_error();
+                r->cursor = r->units;
+            }
             int rc = r->status;
-            if (rc == MK_OK) rc = mk_batch_read(r->batch, r->hist.data(), nullptr);
+            if (rc == MK_OK) rc = batch_collect(r->batch, r->hist.data(), s->copy_stream);
             if (rc == MK_OK) finish(s, r, State::Done, MK_OK, nullptr);
             else finish(s, r, State::Failed, rc, r->error.empty() ? mk_last_error() : r->error.c_str());
+            progress = true;
         }
         s->active.swap(still);
+        if (!progress) std::this_thread::sleep_for(std::chrono::microseconds(20));
     }
 }
 
@@ -195,9 +261,11 @@ extern "C" int mk_server_start(mk_ctx *ctx, const mk_server_opts *opts, mk_serve
     hipError_t e = hipSetDevice(ctx->device);
     for (int i = 0; i < kServerStreams && e == hipSuccess; ++i)
         e = hipStreamCreateWithFlags(&s->streams[i], hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->copy_stream, hipStreamNonBlocking);
     if (e != hipSuccess) {
         for (hipStream_t st : s->streams)
             if (st) (void)hipStreamDestroy(st);
+        if (s->copy_stream) (void)hipStreamDestroy(s->copy_stream);
         delete s;
         return fail(MK_EDEVICE, "mk_server_start: %s", hipGetErrorString(e));
     }
@@ -274,13 +342,16 @@ extern "C" int mk_server_stop(mk_server *s)
         s->cv_work.notify_all();
     }
     if (s->thread.joinable()) s->thread.join();
+    bury(s);
     for (auto &kv : s->all) {
         if (kv.second->batch) mk_batch_free(kv.second->batch);
+        if (kv.second->ev) (void)hipEventDestroy(kv.second->ev);
         delete kv.second;
     }
     (void)hipSetDevice(s->ctx->device);
     for (hipStream_t st : s->streams)
         if (st) (void)hipStreamDestroy(st);
+    if (s->copy_stream) (void)hipStreamDestroy(s->copy_stream);
     delete s;
     return MK_OK;
 }
