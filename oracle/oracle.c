@@ -30,6 +30,15 @@
  * k <= 5 and memoised per labeled code when k = 6 (a cache only: each entry
  * is the same brute-force minimum).
  *
+ * Section 3 also counts H_k from the connected (k-2)-sets X instead of the
+ * k-sets: every unordered pair {y, z} of vertices adjacent to X closes the
+ * connected k-set X + {y, z}.  A k-set S is then reached once per "core" X
+ * of S: a (k-2)-subset that induces a weakly connected subgraph and that
+ * both remaining vertices of S touch.  That number depends only on the
+ * class of G[S]; oracle_core_mult() computes it from this definition, by
+ * trying every (k-2)-subset of a k-vertex code.  (The paper does not state
+ * this divisor; see the readings of the paper in the design notes.)
+ *
  * Error codes: 0 ok, -1 bad argument, -2 k out of range, -3 graph not a
  * simple digraph CSR, -4 out of memory, -5 output buffer too small.
  */
@@ -73,6 +82,45 @@ int oracle_connected(int k, uint32_t code)
             }
     }
     return reached == k;
+}
+
+/* number of cores of the k-vertex digraph given by code: subsets X of
+ * k-2 vertices with G[X] weakly connected such that each of the two
+ * vertices outside X has an arc to or from some vertex of X */
+int oracle_core_mult(int k, uint32_t code)
+{
+    unsigned char a[6][6];
+    if (k < 3 || k > 6) return OR_ERANGE;
+    code_to_matrix(k, code, a);
+    int cores = 0;
+    for (int y = 0; y < k; ++y)
+        for (int z = y + 1; z < k; ++z) {
+            /* X = all vertices but y and z */
+            int x[6], nx = 0;
+            for (int v = 0; v < k; ++v)
+                if (v != y && v != z) x[nx++] = v;
+            int y_touches = 0, z_touches = 0;
+            for (int i = 0; i < nx; ++i) {
+                if (a[y][x[i]] || a[x[i]][y]) y_touches = 1;
+                if (a[z][x[i]] || a[x[i]][z]) z_touches = 1;
+            }
+            if (!y_touches || !z_touches) continue;
+            /* weak connectivity of G[X] by graph search from x[0] */
+            int seen[6] = {0}, stack[6], top = 0, reached = 1;
+            seen[0] = 1;
+            stack[top++] = 0;
+            while (top > 0) {
+                int i = stack[--top];
+                for (int j = 0; j < nx; ++j)
+                    if (!seen[j] && (a[x[i]][x[j]] || a[x[j]][x[i]])) {
+                        seen[j] = 1;
+                        ++reached;
+                        stack[top++] = j;
+                    }
+            }
+            if (reached == nx) ++cores;
+        }
+    return cores;
 }
 
 /* next permutation in lexicographic order; 0 when p was the last one */

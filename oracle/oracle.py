@@ -50,6 +50,8 @@ def load_library(path: str):
     lib.oracle_canon.argtypes = [ctypes.c_int, ctypes.c_uint32]
     lib.oracle_canon_table.restype = ctypes.c_int
     lib.oracle_canon_table.argtypes = [ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]
+    lib.oracle_core_mult.restype = ctypes.c_int
+    lib.oracle_core_mult.argtypes = [ctypes.c_int, ctypes.c_uint32]
     lib.oracle_count.restype = ctypes.c_int64
     lib.oracle_count.argtypes = [ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
                                  ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
@@ -150,6 +152,23 @@ def dense_hist(row_ptr, col, k: int) -> np.ndarray:
     return h
 
 
+def core_mult(k: int, code: int) -> int:
+    """Cores of the k-vertex digraph `code`: (k-2)-subsets X with G[X] weakly
+    connected that both remaining vertices touch (see oracle.c)."""
+    r = int(_lib().oracle_core_mult(k, code))
+    if r < 0:
+        raise OracleError(r)
+    return r
+
+
+@functools.lru_cache(maxsize=None)
+def core_mult_table(k: int) -> np.ndarray:
+    """core_mult of every class, in class-id order (k <= 5)."""
+    out = np.array([core_mult(k, int(c)) for c in class_codes(k)], dtype=np.uint8)
+    out.setflags(write=False)
+    return out
+
+
 # --------------------------------------------------------------------------
 # second, independent brute force (tiny graphs only)
 # --------------------------------------------------------------------------
@@ -189,4 +208,112 @@ def brute_force_count(row_ptr, col, k: int) -> Dict[int, int]:
             continue
         c = _py_canon(k, a)
         out[c] = out.get(c, 0) + 1
+    return out
+
+
+def _arcs_and_delta(row_ptr, col):
+    row_ptr = np.asarray(row_ptr)
+    n = len(row_ptr) - 1
+    arcs = set()
+    for u in range(n):
+        for t in range(row_ptr[u], row_ptr[u + 1]):
+            arcs.add((u, int(col[t])))
+    delta = [set() for _ in range(n)]
+    for u, v in arcs:
+        delta[u].add(v)
+        delta[v].add(u)
+    return n, arcs, delta
+
+
+def _weakly_connected(vs, delta) -> bool:
+    vs = list(vs)
+    seen, stack = {vs[0]}, [vs[0]]
+    while stack:
+        u = stack.pop()
+        for w in vs:
+            if w not in seen and w in delta[u]:
+                seen.add(w)
+                stack.append(w)
+    return len(seen) == len(vs)
+
+
+def _canon_of(sub, arcs, k):
+    return _py_canon(k, [[(sub[i], sub[j]) in arcs for j in range(k)] for i in range(k)])
+
+
+def core_pairs_count(row_ptr, col, k: int) -> Dict[int, int]:
+    """By definition, for tiny graphs: over every connected (k-2)-set X and
+    every unordered pair {y, z} of vertices of adj(X), count the class of
+    G[X + {y, z}] -- the raw sum that the (k-2)-set counting of Section 3
+    forms before any division."""
+    n, arcs, delta = _arcs_and_delta(row_ptr, col)
+    out: Dict[int, int] = {}
+    for X in itertools.combinations(range(n), k - 2):
+        if not _weakly_connected(X, delta):
+            continue
+        adj = sorted(set().union(*(delta[x] for x in X)) - set(X))
+        for y, z in itertools.combinations(adj, 2):
+            c = _canon_of(list(X) + [y, z], arcs, k)
+            out[c] = out.get(c, 0) + 1
+    return out
+
+
+def algorithm1_count(row_ptr, col, k: int) -> Dict[int, int]:
+    """Section 3's counting from L_{k-2}, step by step, for tiny graphs.
+
+    For each connected (k-2)-set X: partition adj(X) into cells by each
+    vertex's A/B/C/N relation to every member of X (Section 2); for every
+    unordered pair of cells {Y, Z} add C(|Y|, 2) (Y = Z) or |Y| |Z| to the
+    class of motif(X, Y, Z) -- X plus one vertex of each cell, no arc between
+    the two; then, for every pair u, v of adj(X) joined by an arc, add one to
+    the class of G[X + {u, v}] and take one from motif(X, cell(u), cell(v)).
+    Every connected k-set S is reached once per core of S, so the raw sums
+    are divided by core_mult of the class at the end.
+    """
+    n, arcs, delta = _arcs_and_delta(row_ptr, col)
+    raw: Dict[int, int] = {}
+
+    def add(c, w):
+        raw[c] = raw.get(c, 0) + w
+
+    def motif_code(X, ty, tz):
+        # vertices 0..k-3 = X, k-2 = a vertex of cell ty, k-1 = of cell tz;
+        # a cell is a tuple of (arc member -> vertex, arc vertex -> member)
+        a = [[False] * k for _ in range(k)]
+        for i in range(k - 2):
+            for j in range(k - 2):
+                a[i][j] = i != j and (X[i], X[j]) in arcs
+        for p, t in ((k - 2, ty), (k - 1, tz)):
+            for i in range(k - 2):
+                a[i][p], a[p][i] = t[i]
+        return _py_canon(k, a)
+
+    for X in itertools.combinations(range(n), k - 2):
+        if not _weakly_connected(X, delta):
+            continue
+        adj = sorted(set().union(*(delta[x] for x in X)) - set(X))
+        cell_of = {u: tuple(((x, u) in arcs, (u, x) in arcs) for x in X) for u in adj}
+        cells: Dict[tuple, int] = {}
+        for u in adj:
+            cells[cell_of[u]] = cells.get(cell_of[u], 0) + 1
+        keys = sorted(cells)
+        for i, ty in enumerate(keys):
+            for tz in keys[i:]:
+                w = cells[ty] * (cells[ty] - 1) // 2 if ty == tz else cells[ty] * cells[tz]
+                if w:
+                    add(motif_code(X, ty, tz), w)
+        for u, v in itertools.combinations(adj, 2):
+            if (u, v) in arcs or (v, u) in arcs:
+                add(_canon_of(list(X) + [u, v], arcs, k), 1)
+                add(motif_code(X, cell_of[u], cell_of[v]), -1)
+    out: Dict[int, int] = {}
+    for c, r in raw.items():
+        if r == 0:
+            continue
+        m = core_mult(k, c)
+        if r < 0:
+            raise ValueError("raw count of class %d is negative" % c)
+        if m == 0 or r % m:
+            raise ValueError("raw count %d of class %d is not a multiple of %d" % (r, c, m))
+        out[c] = r // m
     return out

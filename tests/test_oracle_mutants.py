@@ -38,6 +38,14 @@ MUTANTS = {
     "code operands transposed": (
         "if (i != j && arc(e, e->sub[i], e->sub[j])) code |= 1u << bit_of(k, i, j);",
         "if (i != j && arc(e, e->sub[j], e->sub[i])) code |= 1u << bit_of(k, i, j);"),
+    "core test skips the second vertex": (
+        "if (!y_touches || !z_touches) continue;", "if (!y_touches) continue;"),
+    "core connectivity not checked": (
+        "if (reached == nx) ++cores;", "++cores;"),
+    "core pairs counted in both orders": (
+        "for (int z = y + 1; z < k; ++z) {", "for (int z = 0; z < k; ++z) if (z != y) {"),
+    "core touch follows out-arcs only": (
+        "if (a[y][x[i]] || a[x[i]][y]) y_touches = 1;", "if (a[y][x[i]]) y_touches = 1;"),
     "child extension keeps the chosen vertex": (
         "for (int j = i + 1; j < next; ++j) child[cn++] = ext[j];",
         "for (int j = i; j < next; ++j) child[cn++] = ext[j];"),
@@ -101,6 +109,30 @@ def _failed_pins(lib):
                     break
         except O.OracleError:
             failed.append("error k=%d" % k)
+    # core multiplicity: closed forms, zero exactly on disconnected codes,
+    # and the raw pair sums of tiny graphs
+    try:
+        for k in (3, 4, 5):
+            full = (1 << (k * (k - 1))) - 1
+            star = (1 << (k - 1)) - 1
+            path = sum(1 << (i * (k - 1) + i) for i in range(k - 1))
+            if (lib.oracle_core_mult(k, full) != math.comb(k, 2)
+                    or lib.oracle_core_mult(k, star) != math.comb(k - 1, 2)
+                    or lib.oracle_core_mult(k, path) != 1):
+                failed.append("core closed forms k=%d" % k)
+        for code in range(1 << 6):
+            if (lib.oracle_core_mult(3, code) > 0) != bool(lib.oracle_connected(3, code)):
+                failed.append("core zero iff disconnected")
+                break
+        rng = np.random.default_rng(56)
+        for k in (3, 4):
+            g = I.er_digraph(7, 14, rng)
+            raw = O.core_pairs_count(*g, k)
+            hist = O.brute_force_count(*g, k)
+            if raw != {c: lib.oracle_core_mult(k, c) * v for c, v in hist.items()}:
+                failed.append("core raw sums k=%d" % k)
+    except O.OracleError:
+        failed.append("core error")
     return failed
 
 
