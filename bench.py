@@ -73,11 +73,15 @@ def _parse():
     p.add_argument("--k5-split", type=int, default=0,
                    help="k=5 split threshold (0: library default)")
     p.add_argument("--waves-per-cu", type=int, default=0)
+    p.add_argument("--method", choices=("auto", "esu", "cores"), default="auto",
+                   help="counting method of the batches (auto: the library's choice)")
     p.add_argument("--autotune", action="store_true",
                    help="pick the k=6 batch options with the library's autotuner first")
     p.add_argument("--copy-mib", type=int, default=0,
                    help="also run one device-to-device copy of this many MiB (a kernel of "
                         "known traffic, to scale hardware byte counters)")
+    p.add_argument("--no-methods", action="store_true",
+                   help="skip timing both counting methods on the k=6 and k=5 batches")
     p.add_argument("--serve", type=int, default=0, metavar="R",
                    help="also run the serving workload with R requests (0: skip)")
     p.add_argument("--serve-load", type=float, default=0.7,
@@ -111,9 +115,9 @@ def _timed_batch(ctx, M, graphs, table, steps, warmup, torch, **opts):
         b.free()
 
 
-def _plain(ctx, graphs, table, steps, torch):
+def _plain(ctx, graphs, table, steps, torch, **opts):
     """One prepared single-graph batch per graph, run one after another."""
-    bs = [ctx.batch([g], table) for g in graphs]
+    bs = [ctx.batch([g], table, **opts) for g in graphs]
     try:
         d = torch.zeros((1, table.num_classes), dtype=torch.int64, device="cuda:0")
         stream = torch.cuda.current_stream()
@@ -129,6 +133,30 @@ def _plain(ctx, graphs, table, steps, torch):
     finally:
         for b in bs:
             b.free()
+
+
+def _methods(ctx, M, I, torch):
+    """Both counting methods on the k=6 and k=5 batches: mean pass and
+    counting-kernel ms over a few steps, and whether the histograms agree."""
+    import numpy as np
+    res = {}
+    for k, w, steps in ((6, I.workload_k6_batch(), 4), (5, I.workload_k5_batch(), 2)):
+        t = ctx.table(k)
+        gs = [ctx.load_graph(*g) for g in w.graphs]
+        hists = {}
+        row = {}
+        for name, meth in (("esu", M.METHOD_ESU), ("cores", M.METHOD_CORES)):
+            r = _timed_batch(ctx, M, gs, t, steps, 1, torch, method=meth)
+            hists[name] = r["hist"]
+            row[name] = {"pass_ms": float(np.mean(r["pass_ms"])),
+                         "kernel_ms": float(np.mean(r["enum_ms"]))}
+        row["equal"] = bool(np.array_equal(hists["esu"], hists["cores"]))
+        _log("methods k=%d: esu %.3f ms, cores %.3f ms (kernel), equal=%s" % (
+            k, row["esu"]["kernel_ms"], row["cores"]["kernel_ms"], row["equal"]))
+        res["k%d" % k] = row
+        for g in gs:
+            g.free()
+    return res
 
 
 def _serving(ctx, M, I, R, load, torch):
@@ -226,7 +254,8 @@ def main():
     t6 = ctx.table(6)
     _log("k=6 table built in %.1f ms" % t6.build_ms)
     graphs = [ctx.load_graph(*g) for g in w.graphs]
-    opts = {}
+    method = {"auto": M.METHOD_AUTO, "esu": M.METHOD_ESU, "cores": M.METHOD_CORES}[args.method]
+    opts = {"method": method} if method else {}
     if args.split:
         opts["split_threshold"] = args.split
     if args.waves_per_cu:
@@ -270,7 +299,8 @@ def main():
     }
     _log("batched k=6: %.3f ms/step, enum kernel %.3f ms" % (ms_per_step, enum_ms))
     if not args.no_plain:
-        plain_s = _plain(ctx, graphs, t6, max(1, args.steps // 5), torch)
+        plain_s = _plain(ctx, graphs, t6, max(1, args.steps // 5), torch,
+                         **({"method": method} if method else {}))
         _log("plain k=6: %.3f ms/pass" % (1000 * plain_s))
         out["plain"] = {"value": subgraphs / plain_s, "ms_per_step": 1000.0 * plain_s,
                         "speedup_batched": plain_s / (r["wall_s"] / args.steps)}
@@ -303,6 +333,8 @@ def main():
         t5 = ctx.table(5)
         g5 = [ctx.load_graph(*g) for g in w5.graphs]
         o5 = {"split_threshold": args.k5_split} if args.k5_split else {}
+        if method:
+            o5["method"] = method
         r5 = _timed_batch(ctx, M, g5, t5, max(2, args.steps // 3), 1, torch, **o5)
         s5 = int(r5["totals"].sum())
         k5 = {"workload": w5.name, "value": s5 / (r5["wall_s"] / max(2, args.steps // 3)),
@@ -310,12 +342,14 @@ def main():
               "pass_ms": float(np.mean(r5["pass_ms"])), "table_build_ms": t5.build_ms,
               "batch_stats": r5["stats"]}
         if not args.no_plain:
-            p5 = _plain(ctx, g5, t5, 1, torch)
+            p5 = _plain(ctx, g5, t5, 1, torch, **({"method": method} if method else {}))
             k5["plain_value"] = s5 / p5
         out["k5_batch"] = k5
         _log("k=5 batch: %.3f ms/step" % k5["pass_ms"])
         for g in g5:
             g.free()
+    if not args.no_methods:
+        out["methods"] = _methods(ctx, M, I, torch)
     if args.serve:
         out["serving"] = _serving(ctx, M, I, args.serve, args.serve_load, torch)
     ctx.close()

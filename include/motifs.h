@@ -149,6 +149,16 @@ int mk_table_lookup(const mk_table *t, uint32_t code, uint32_t *id);
 /* Copy entries [first, first+count) of the table to host memory out[]. */
 int mk_table_read(const mk_table *t, uint64_t first, uint64_t count, uint32_t *out);
 
+/* Cores per class, classes [first, first+count) into out (host, count
+   bytes).  A core of a connected k-vertex digraph is a subset of k-2 of its
+   vertices that induces a weakly connected subgraph and that both other
+   vertices touch (an arc either way to some vertex of the subset).  Counting
+   H_k from the connected (k-2)-sets (Section 3: every pair of vertices of
+   adj(X) closes a k-set with X) reaches each k-set once per core, so these
+   are the divisors of that count (1..k(k-1)/2; the paper leaves them
+   implicit).  MK_ERANGE if the range leaves the classes. */
+int mk_table_core_mult(const mk_table *t, uint32_t first, uint32_t count, uint8_t *out);
+
 /* ------------------------------------------------------------------ count */
 
 /* H_k(G) for one graph (k = the table's k).  hist: host array of
@@ -179,7 +189,23 @@ typedef struct mk_batch_opts {
     int32_t debug_flags;      /* tests only: 1 = every code straight to the
                                  histogram, 2 = flush the per-wave count hash
                                  after every insert; results are the same */
+    int32_t method;           /* MK_METHOD_*: how H_k is counted (0: the
+                                 library's choice); results are the same */
 } mk_batch_opts;
+
+/* Counting methods of a batch.
+   MK_METHOD_ESU: every connected k-set is enumerated once (ESU) and its
+     adjacency code looked up in the class table (Section 3.2).
+   MK_METHOD_CORES: Section 3's loop over the connected (k-2)-sets X: the
+     vertices of adj(X) are grouped into cells by their relation to each
+     member (Section 2); each pair of cells adds C(|Y|,2) or |Y||Z| k-sets
+     of one class at once, each arc inside adj(X) moves one k-set to its
+     true class, and the sums are divided by the cores per class
+     (mk_table_core_mult). */
+/* MK_METHOD_AUTO: MK_METHOD_CORES for k <= 5, MK_METHOD_ESU for k = 6. */
+#define MK_METHOD_AUTO 0
+#define MK_METHOD_ESU 1
+#define MK_METHOD_CORES 2
 
 /* Prepare a batch: device workspace for the typed adjacency, the work
    units and the histograms of ng graphs (counted with table t), sized by
@@ -210,6 +236,7 @@ typedef struct mk_batch_stats {
     int32_t lds_bytes;
     int32_t k;
     int32_t ng;
+    int32_t method;           /* the MK_METHOD_* the batch runs */
 } mk_batch_stats;
 int mk_batch_stats_get(const mk_batch *b, mk_batch_stats *out);
 

@@ -43,16 +43,19 @@ struct mk_batch {
     int64_t max_m = 0;
     int64_t max_nnz = 0;
     int grid = 0, max_grid = 0, lds_bytes = 0;
+    int method = MK_METHOD_ESU;  // resolved (never MK_METHOD_AUTO)
+    int plan_k = 0;              // set size the planner cuts units for
     uint64_t units = 0, split_pairs = 0;
 
-    hipEvent_t ev[3] = {};  // pass start, enumeration start, enumeration end
+    // pass start, counting kernel start, counting kernel end, pass end
+    hipEvent_t ev[4] = {};
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     unsigned long long *exec_hist = nullptr;
     hipStream_t last_stream = nullptr;
 };
 
-static constexpr uint64_t kDefaultSplit[7] = {0, 0, 0, 1u << 30, 1u << 12, 1u << 12, 1u << 12};
+static constexpr uint64_t kDefaultSplit[7] = {0, 0, 1u << 30, 1u << 30, 1u << 12, 1u << 12, 1u << 12};
 
 // ----------------------------------------------------------------- context
 
@@ -154,21 +157,43 @@ static int batch_enqueue_prep(mk_batch *b, unsigned long long *hist, hipStream_t
     rc = launch_typed_csr(b->d_graphs, b->ng, b->max_n, b->max_m, b->bits_words, b->d_ws,
                           b->d_counters, stream);
     if (rc) return rc;
-    return launch_plan(b->k, b->d_graphs, b->ng, b->max_nnz, b->total_slots, b->d_slot_cnt,
+    return launch_plan(b->plan_k, b->d_graphs, b->ng, b->max_nnz, b->total_slots, b->d_slot_cnt,
                        b->d_slot_off, b->d_slot_est, b->d_slot_vi, b->d_scan_tmp, b->d_units,
                        b->unit_cap,
                        b->opts.split_threshold, (uint32_t)b->max_grid, b->d_counters, stream);
 }
 
-// the enumeration kernel between two timing events
+// the counting kernel over units [counters[kSliceBegin], unit_end)
+static int batch_launch_count(mk_batch *b, unsigned long long *hist, uint32_t unit_end, int grid,
+                              hipStream_t stream)
+{
+    if (b->method == MK_METHOD_CORES)
+        return launch_core(b->k, b->d_graphs, b->d_units, b->unit_cap, unit_end, b->d_counters,
+                           b->table->d_table, b->table->num_classes, hist, enum_config(b), grid,
+                           b->lds_bytes, stream);
+    return launch_enum(b->k, b->d_graphs, b->d_units, b->unit_cap, unit_end, b->d_counters,
+                       b->table->d_table, b->table->num_classes, hist, enum_config(b), grid,
+                       b->lds_bytes, stream);
+}
+
+// after the last unit: the cores method divides its raw sums
+static int batch_launch_finish(mk_batch *b, unsigned long long *hist, hipStream_t stream)
+{
+    if (b->method != MK_METHOD_CORES) return MK_OK;
+    return launch_core_divide(hist, b->ng, b->table->num_classes, b->table->d_core_mult,
+                              b->d_counters, stream);
+}
+
+// the counting kernel between two timing events, then the finish
 static int batch_enqueue_enum(mk_batch *b, unsigned long long *hist, hipStream_t stream)
 {
     MK_HIP(hipEventRecord(b->ev[1], stream));
-    int rc = launch_enum(b->k, b->d_graphs, b->d_units, b->unit_cap, kAllUnits, b->d_counters,
-                         b->table->d_table, b->table->num_classes, hist, enum_config(b), b->grid,
-                         b->lds_bytes, stream);
+    int rc = batch_launch_count(b, hist, kAllUnits, b->grid, stream);
     if (rc) return rc;
     MK_HIP(hipEventRecord(b->ev[2], stream));
+    rc = batch_launch_finish(b, hist, stream);
+    if (rc) return rc;
+    MK_HIP(hipEventRecord(b->ev[3], stream));
     return MK_OK;
 }
 
@@ -192,7 +217,17 @@ extern "C" int mk_batch_create(mk_ctx *ctx, const mk_graph *const *gs, int32_t n
     b->ng = ng;
     b->graphs.assign(gs, gs + ng);
     if (opts) b->opts = *opts;
-    if (b->opts.split_threshold == 0) b->opts.split_threshold = kDefaultSplit[b->k];
+    if (b->opts.method < MK_METHOD_AUTO || b->opts.method > MK_METHOD_CORES) {
+        delete b;
+        return fail(MK_EINVAL, "mk_batch_create: unknown method %d", opts->method);
+    }
+    // the library's choice: counting from the (k-2)-sets is the faster on
+    // sparse graphs for k <= 5; for k = 6 the per-core work (up to 255 cells)
+    // costs more than enumerating the k-sets
+    b->method = b->opts.method != MK_METHOD_AUTO ? b->opts.method
+                                                 : (b->k <= 5 ? MK_METHOD_CORES : MK_METHOD_ESU);
+    b->plan_k = b->method == MK_METHOD_CORES ? (b->k == 3 ? 2 : b->k - 1) : b->k;
+    if (b->opts.split_threshold == 0) b->opts.split_threshold = kDefaultSplit[b->plan_k];
     if (b->opts.use_graph == 0) b->opts.use_graph = 1;
 
     // workspace layout: [bits of every graph][urow of every graph][uadj ...]
@@ -218,7 +253,9 @@ extern "C" int mk_batch_create(mk_ctx *ctx, const mk_graph *const *gs, int32_t n
     b->bits_words = bits;
     b->total_slots = (uint32_t)slots;
     b->seg_cap = std::max(b->seg_cap, 1);
-    b->lds_bytes = enum_lds_bytes(b->k, std::max(b->max_n, 1), b->seg_cap);
+    b->lds_bytes = b->method == MK_METHOD_CORES
+                       ? core_lds_bytes(b->k, std::max(b->max_n, 1), b->seg_cap)
+                       : enum_lds_bytes(b->k, std::max(b->max_n, 1), b->seg_cap);
     if ((size_t)b->lds_bytes > ctx->max_lds) {
         delete b;
         return fail(MK_ERANGE, "graphs need %d bytes of LDS per wave (limit %zu)", b->lds_bytes,
@@ -275,7 +312,8 @@ extern "C" int mk_batch_create(mk_ctx *ctx, const mk_graph *const *gs, int32_t n
     for (hipEvent_t &e : b->ev) BAIL_HIP(hipEventCreate(&e));
 
     int per_cu = 0;
-    rc = enum_max_blocks_per_cu(b->k, b->lds_bytes, &per_cu);
+    rc = b->method == MK_METHOD_CORES ? core_max_blocks_per_cu(b->k, b->lds_bytes, &per_cu)
+                                      : enum_max_blocks_per_cu(b->k, b->lds_bytes, &per_cu);
     if (rc) return bail(rc);
     if (b->opts.waves_per_cu > 0) per_cu = std::min(per_cu, b->opts.waves_per_cu);
     per_cu = std::max(per_cu, 1);
@@ -287,7 +325,7 @@ extern "C" int mk_batch_create(mk_ctx *ctx, const mk_graph *const *gs, int32_t n
         rc = launch_typed_csr(b->d_graphs, ng, b->max_n, b->max_m, bits, b->d_ws,
                               b->d_counters, ctx->stream);
     if (!rc)
-        rc = launch_plan(b->k, b->d_graphs, ng, b->max_nnz, b->total_slots, b->d_slot_cnt,
+        rc = launch_plan(b->plan_k, b->d_graphs, ng, b->max_nnz, b->total_slots, b->d_slot_cnt,
                          b->d_slot_off, b->d_slot_est, b->d_slot_vi, b->d_scan_tmp, nullptr, 0,
                          b->opts.split_threshold,
                          (uint32_t)b->max_grid, b->d_counters, ctx->stream);
@@ -410,6 +448,7 @@ extern "C" int mk_batch_stats_get(const mk_batch *b, mk_batch_stats *out)
     out->lds_bytes = b->lds_bytes;
     out->k = b->k;
     out->ng = b->ng;
+    out->method = b->method;
     return MK_OK;
 }
 
@@ -455,9 +494,7 @@ int batch_enum_slice(mk_batch *b, uint32_t begin, uint32_t end, hipStream_t stre
     rc = fill_u32(b->d_counters + kSliceBegin, begin, 1, stream);
     if (rc) return rc;
     const int grid = (int)std::min<uint64_t>((uint64_t)b->grid, end - begin);
-    return launch_enum(b->k, b->d_graphs, b->d_units, b->unit_cap, end, b->d_counters,
-                       b->table->d_table, b->table->num_classes, b->d_hist_own, enum_config(b),
-                       grid, b->lds_bytes, stream);
+    return batch_launch_count(b, b->d_hist_own, end, grid, stream);
 }
 
 // Copy the histograms of a prepared batch whose last slice is known to be
@@ -467,6 +504,8 @@ int batch_collect(mk_batch *b, uint64_t *hist, hipStream_t copy_stream)
 {
     MK_HIP(hipSetDevice(b->ctx->device));
     if (b->ng == 0) return MK_OK;
+    int rc = batch_launch_finish(b, b->d_hist_own, copy_stream);
+    if (rc) return rc;
     uint32_t cnt[kNumCounters];
     MK_HIP(hipMemcpyAsync(cnt, b->d_counters, sizeof(cnt), hipMemcpyDeviceToHost, copy_stream));
     MK_HIP(hipMemcpyAsync(hist, b->d_hist_own,
@@ -487,9 +526,9 @@ extern "C" int mk_batch_timing(mk_batch *b, double *pass_ms, double *enum_ms)
     if (!b->hist_last || b->ng == 0) return fail(MK_EINVAL, "mk_batch_timing: batch has not run");
     std::lock_guard<std::recursive_mutex> lock(b->ctx->mu);
     MK_HIP(hipSetDevice(b->ctx->device));
-    MK_HIP(hipEventSynchronize(b->ev[2]));
+    MK_HIP(hipEventSynchronize(b->ev[3]));
     float a = 0.f, e = 0.f;
-    MK_HIP(hipEventElapsedTime(&a, b->ev[0], b->ev[2]));
+    MK_HIP(hipEventElapsedTime(&a, b->ev[0], b->ev[3]));
     MK_HIP(hipEventElapsedTime(&e, b->ev[1], b->ev[2]));
     if (pass_ms) *pass_ms = a;
     if (enum_ms) *enum_ms = e;
@@ -559,7 +598,12 @@ extern "C" int mk_autotune(mk_ctx *ctx, const mk_graph *const *gs, int32_t ng, c
         }
         return MK_OK;
     };
-    // coordinate search: split floor, then units per grab, then waves per CU
+    // coordinate search: method, split floor, units per grab, waves per CU
+    {
+        mk_batch_opts o = cur;
+        o.method = MK_METHOD_CORES;
+        if ((rc = trial(o))) return rc;
+    }
     static const uint64_t floors[] = {1u << 10, 1u << 14, 1u << 18, 1u << 22};
     const mk_batch_opts base1 = cur;
     for (uint64_t f : floors) {

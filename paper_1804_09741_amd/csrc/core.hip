@@ -1,0 +1,528 @@
+// Counting H_k from the connected (k-2)-sets (Section 3, the counting loop
+// over L_{k-2}).
+//
+// A connected (k-2)-set X and any two vertices y, z of adj(X) (the vertices
+// outside X with an arc to or from X, Section 2) form a connected k-set.
+// Section 2 partitions adj(X) into cells by each vertex's relation (A, B, C
+// or none) to every member of X; all vertices of one cell look alike from
+// X.  So for two cells Y, Z the k-sets X + {y, z} with no arc between y and z
+// all have one class, motif(X, Y, Z), and there are C(|Y|, 2) (Y = Z) or
+// |Y| |Z| of them.  Each arc pair u, v inside adj(X) moves one k-set from
+// motif(X, cell(u), cell(v)) to the class of G[X + {u, v}].  Summed over X,
+// a k-set S is reached once per core of S (a connected (k-2)-subset that both
+// other vertices touch); that number depends only on the class of S, so the
+// raw sums are divided by it at the end (core_mult of the class table).
+//
+// Kernel: one 64-lane wave per workgroup, persistent, on the same work
+// queues as the enumeration kernel.  The cores X are listed by ESU to depth
+// k-2 (the planner runs for (k-1)-sets, so a unit is a range of the nodes
+// just above the cores).  The marks that ESU keeps in LDS already hold, for
+// every vertex u of adj(X), its relation bits to each member -- its cell --
+// and the code bits u adds at any position.  Per core:
+//   1. cells: the members' lists are read flat; a vertex is taken from the
+//      first member it is adjacent to (no lower member bits in its mark), its
+//      cell counted in LDS, new cells appended to a list;
+//   2. arcs inside adj(X): the taken vertices' own lists are scanned flat
+//      (a lane-prefix sum of degrees); a neighbour v > u with a mark and not
+//      a member closes an arc pair.  With few cells the pair is counted in
+//      an LDS table per (cell pair, arc type); otherwise it goes straight to
+//      the per-wave hash, +1 for the code with the arcs and -1 without;
+//   3. cell pairs: lanes take pairs (Y, Z) of the list, form the code of X
+//      + one vertex of each (marks expanded back from the cell index) and
+//      add the weight, less the table's arc pairs, to the hash; the table's
+//      entries go to the codes with their arcs.
+// Hash counts are 32-bit two's complement (the -1s); a flush sign-extends
+// them into the 64-bit histogram, so partial sums may wrap and the totals
+// are exact modulo 2^64 -- which they are, being the final non-negative
+// raw counts.
+#include "esu.h"
+
+namespace mk {
+
+template <int K>
+constexpr int kCoreR = K - 2;                     // members of a core
+template <int K>
+constexpr int kCells = 1 << (2 * (K - 2));        // 4^(k-2) relation vectors
+// top bit of a mark: "member of the current core" while a core is processed
+template <int K>
+constexpr uint32_t kMemberFlag = 1u << (8 * sizeof(MarkT<K>) - 1);
+
+// Cores with at most kAggCells cells count their arc pairs in a small LDS
+// table per (cell pair, arc type) first; the pair phase then takes them off
+// the pair weights and adds them to the true classes, one insert per
+// non-empty entry.  Cores with more cells insert +1/-1 per arc pair.
+template <int K>
+constexpr int kAggCells = K == 6 ? 12 : 16;
+template <int K>
+constexpr int kAggWords = 3 * kAggCells<K> * (kAggCells<K> + 1) / 2;
+
+// LDS of the core kernel beyond the enumeration layout: cell counts (u32),
+// the list of non-empty cells and each cell's list position (u8), 64 vertex
+// ids for the arc scan, and the arc-pair table.
+struct CoreLds {
+    uint32_t *cnt;
+    uint8_t *list;
+    uint8_t *pos;
+    uint32_t *uid;
+    uint32_t *agg;
+};
+
+__host__ __device__ inline int core_extra_bytes(int k)
+{
+    const int cells = 1 << (2 * (k - 2));
+    const int agg_cells = k == 6 ? 12 : 16;
+    return 4 * cells + 2 * ((cells + 3) & ~3) + 4 * kWave + 4 * 3 * agg_cells * (agg_cells + 1) / 2;
+}
+
+// relation vector of a mark: bit 2d = arc s_d -> u, bit 2d+1 = arc u -> s_d
+template <int K>
+__device__ __forceinline__ uint32_t cell_of(uint32_t m)
+{
+    uint32_t c = 0;
+#pragma unroll
+    for (int d = 0; d < kCoreR<K>; ++d) {
+        c |= ((m >> (d * (K - 1))) & 1u) << (2 * d);
+        c |= ((m >> (EnumState<K>::OUTB + d)) & 1u) << (2 * d + 1);
+    }
+    return c;
+}
+
+// inverse of cell_of
+template <int K>
+__device__ __forceinline__ uint32_t mark_of_cell(uint32_t c)
+{
+    uint32_t m = 0;
+#pragma unroll
+    for (int d = 0; d < kCoreR<K>; ++d) {
+        m |= ((c >> (2 * d)) & 1u) << (d * (K - 1));
+        m |= ((c >> (2 * d + 1)) & 1u) << (EnumState<K>::OUTB + d);
+    }
+    return m;
+}
+
+// mark bits of member positions below d
+template <int K>
+__device__ __forceinline__ uint32_t lower_members(int d)
+{
+    uint32_t m = 0;
+#pragma unroll
+    for (int q = 0; q < kCoreR<K>; ++q)
+        if (q < d) m |= (1u << (q * (K - 1))) | (1u << (EnumState<K>::OUTB + q));
+    return m;
+}
+
+// s_D := x for the last member of a core: marks only (no extension segment)
+template <int K, int D>
+__device__ __forceinline__ void push_marks(EnumState<K> &s, int x)
+{
+    const int lane = lane_id();
+    const int r0 = uniform(s.urow[x]);
+    const int r1 = uniform(s.urow[x + 1]);
+    for (int base = r0; base < r1; base += kWave) {
+        const int e = base + lane;
+        if (e < r1) {
+            const uint32_t ent = s.uadj[e];
+            const int y = (int)(ent >> 2);
+            s.mark[y] = (MarkT<K>)(s.mark[y] | mark_bits<K>(D, ent & 3u));
+        }
+    }
+    __syncthreads();
+}
+
+// count codes with weight -1 (merged like count_codes)
+template <int K>
+__device__ __forceinline__ void uncount_codes(EnumState<K> &s, bool valid, uint32_t code)
+{
+    const int lane = lane_id();
+    unsigned long long act = __ballot(valid);
+    if (!act) return;
+    s.hpending += (uint32_t)__popcll(act);
+    uint32_t n = 1;
+    const int l = __builtin_ctzll(act);
+    const uint32_t c0 = (uint32_t)__builtin_amdgcn_readlane((int)code, l);
+    const unsigned long long eq = __ballot(code == c0) & act;
+    if (lane == l) n = (uint32_t)__popcll(eq);
+    else if ((eq >> lane) & 1ull) n = 0;
+    hash_insert<K>(s, valid && n > 0, code, 0u - n);
+}
+
+// Flat index a over the concatenated lists of the members: member d and
+// list position e.
+template <int R>
+__device__ __forceinline__ int member_entry(const int (&pre)[R + 1], const int (&r0)[R], int a,
+                                            int *d)
+{
+    int dd = 0;
+#pragma unroll
+    for (int q = 1; q < R; ++q) dd += a >= pre[q] ? 1 : 0;
+    int e = 0;
+#pragma unroll
+    for (int q = 0; q < R; ++q)
+        if (q == dd) e = r0[q] + (a - pre[q]);
+    *d = dd;
+    return e;
+}
+
+// one core X = mem[0..k-3] with internal code cx (all members pushed)
+template <int K>
+__device__ void core_node(EnumState<K> &s, const CoreLds &c, const int (&mem)[K], uint32_t cx)
+{
+    constexpr int R = kCoreR<K>;
+    constexpr uint32_t FLAG = kMemberFlag<K>;
+    // arc bits between positions k-2 and k-1
+    constexpr int B_YZ = (K - 2) * (K - 1) + (K - 1) - 1;
+    constexpr int B_ZY = (K - 1) * (K - 1) + (K - 2);
+    const int lane = lane_id();
+
+#pragma unroll
+    for (int d = 0; d < R; ++d)
+        if (lane == d) s.mark[mem[d]] = (MarkT<K>)(s.mark[mem[d]] | FLAG);
+    int r0[R], pre[R + 1];
+    pre[0] = 0;
+#pragma unroll
+    for (int d = 0; d < R; ++d) {
+        r0[d] = uniform(s.urow[mem[d]]);
+        pre[d + 1] = pre[d] + uniform(s.urow[mem[d] + 1]) - r0[d];
+    }
+    const int total = pre[R];
+    __syncthreads();
+
+    // 1. cells of adj(X)
+    int ncell = 0, nadj = 0;
+    for (int base = 0; base < total; base += kWave) {
+        const int a = base + lane;
+        bool mine = false;
+        uint32_t cell = 0;
+        if (a < total) {
+            int d;
+            const int e = member_entry<R>(pre, r0, a, &d);
+            const uint32_t m = s.mark[s.uadj[e] >> 2];
+            mine = !(m & FLAG) && !(m & lower_members<K>(d));
+            cell = cell_of<K>(m);
+        }
+        bool fresh = false;
+        if (mine) fresh = atomicAdd(&c.cnt[cell], 1u) == 0u;
+        const unsigned long long bal = __ballot(fresh);
+        if (fresh) {
+            const int at = ncell + (int)lanes_below(bal);
+            c.list[at] = (uint8_t)cell;
+            c.pos[cell] = (uint8_t)at;
+        }
+        ncell += __popcll(bal);
+        nadj += __popcll(__ballot(mine));
+    }
+    __syncthreads();
+    const bool agg = ncell <= kAggCells<K>;
+    const uint32_t pairs_w = (uint32_t)nadj * (uint32_t)(nadj - 1) / 2u;  // sum of the weights
+    if (s.hpending + pairs_w >= kPendingMax) flush_hash<K>(s);
+    s.hpending += pairs_w;
+
+    // 2. arc pairs inside adj(X): into the table, or +1 with the arcs and -1
+    // without straight into the hash
+    uint32_t *pre_deg = s.scratch, *start = s.scratch + kWave, *cw = s.scratch + 2 * kWave;
+    for (int base = 0; base < total; base += kWave) {
+        const int a = base + lane;
+        int deg = 0, row = 0, u = 0;
+        uint32_t key = 0;
+        if (a < total) {
+            int d;
+            const int e = member_entry<R>(pre, r0, a, &d);
+            u = (int)(s.uadj[e] >> 2);
+            const uint32_t m = s.mark[u];
+            if (!(m & FLAG) && !(m & lower_members<K>(d))) {
+                row = s.urow[u];
+                deg = s.urow[u + 1] - row;
+                key = agg ? (uint32_t)c.pos[cell_of<K>(m)] : code_bits<K>(m, K - 2);
+            }
+        }
+        int incl = deg;
+#pragma unroll
+        for (int d = 1; d < kWave; d <<= 1) {
+            const int o = __shfl_up(incl, d, kWave);
+            if (lane >= d) incl += o;
+        }
+        const int tot = uniform(__shfl(incl, kWave - 1, kWave));
+        pre_deg[lane] = (uint32_t)incl;
+        start[lane] = (uint32_t)row;
+        cw[lane] = key;
+        c.uid[lane] = (uint32_t)u;
+        __syncthreads();
+        for (int fb = 0; fb < tot; fb += kWave) {
+            const int f = fb + lane;
+            bool edge = false;
+            uint32_t mv = 0, t = 0, ukey = 0;
+            if (f < tot) {
+                // first lane whose inclusive degree prefix exceeds f
+                int lo = 0;
+#pragma unroll
+                for (int step = kWave / 2; step > 0; step >>= 1)
+                    lo += ((int)pre_deg[lo + step - 1] <= f) ? step : 0;
+                const int before = lo ? (int)pre_deg[lo - 1] : 0;
+                const uint32_t ent = s.uadj[start[lo] + (uint32_t)(f - before)];
+                const int v = (int)(ent >> 2);
+                mv = s.mark[v];
+                edge = mv != 0u && !(mv & FLAG) && v > (int)c.uid[lo];
+                t = ent & 3u;
+                ukey = cw[lo];
+            }
+            if (agg) {
+                if (edge) {
+                    uint32_t ia = ukey, ib = c.pos[cell_of<K>(mv)];
+                    if (ia > ib) {
+                        const uint32_t x = ia;
+                        ia = ib;
+                        ib = x;
+                        t = ((t & 1u) << 1) | (t >> 1);
+                    }
+                    atomicAdd(&c.agg[3u * (ib * (ib + 1u) / 2u + ia) + t - 1u], 1u);
+                }
+            } else {
+                const uint32_t cm = cx | ukey | code_bits<K>(mv, K - 1);
+                const uint32_t ct = cm | ((t & 1u) << B_YZ) | ((t >> 1) << B_ZY);
+                if (s.hpending >= kPendingMax - 2u * kWave) flush_hash<K>(s);
+                count_codes<K>(s, edge, ct);
+                uncount_codes<K>(s, edge, cm);
+            }
+        }
+        __syncthreads();
+    }
+
+    // 3. pairs of cells (Y <= Z): C(|Y|,2) or |Y||Z| k-sets of motif(X, Y, Z),
+    // less the arc pairs of the table, which go to their own classes
+    const int npairs = ncell * (ncell + 1) / 2;
+    for (int pb = 0; pb < npairs; pb += kWave) {
+        const int p = pb + lane;
+        bool valid = false;
+        uint32_t code = 0, w = 0, e1 = 0, e2 = 0, e3 = 0;
+        if (p < npairs) {
+            // p = z(z+1)/2 + y with y <= z
+            int z = (int)((__builtin_sqrtf(8.0f * (float)p + 1.0f) - 1.0f) * 0.5f);
+            if ((z + 1) * (z + 2) / 2 <= p) ++z;
+            if (z * (z + 1) / 2 > p) --z;
+            const int y = p - z * (z + 1) / 2;
+            const uint32_t cy = c.list[y], cz = c.list[z];
+            const uint32_t ny = c.cnt[cy], nz = c.cnt[cz];
+            w = y == z ? ny * (ny - 1u) / 2u : ny * nz;
+            if (agg) {
+                uint32_t *row = c.agg + 3 * p;
+                e1 = row[0];
+                e2 = row[1];
+                e3 = row[2];
+                row[0] = row[1] = row[2] = 0u;
+                w -= e1 + e2 + e3;
+            }
+            code = cx | code_bits<K>(mark_of_cell<K>(cy), K - 2) |
+                   code_bits<K>(mark_of_cell<K>(cz), K - 1);
+            valid = w > 0;
+        }
+        hash_insert<K>(s, valid, code, w);
+        if (agg && __ballot(e1 | e2 | e3)) {
+            hash_insert<K>(s, e1 > 0, code | (1u << B_YZ), e1);
+            hash_insert<K>(s, e2 > 0, code | (1u << B_ZY), e2);
+            hash_insert<K>(s, e3 > 0, code | (1u << B_YZ) | (1u << B_ZY), e3);
+        }
+    }
+
+    // reset the cell counts and the member flags
+    for (int i = lane; i < ncell; i += kWave) c.cnt[c.list[i]] = 0u;
+#pragma unroll
+    for (int d = 0; d < R; ++d)
+        if (lane == d) s.mark[mem[d]] = (MarkT<K>)(s.mark[mem[d]] & ~FLAG);
+    __syncthreads();
+}
+
+// node with members s_0..s_D (D < k-3): its children jlo..jhi-1 become
+// member D+1; at D+1 = k-3 each child completes a core
+template <int K, int D>
+__device__ void visit_core(EnumState<K> &s, const CoreLds &c, const int (&st)[K - 1],
+                           uint32_t code, int jlo, int jhi, int (&mem)[K])
+{
+    int rem[D + 1];
+    int total = 0;
+#pragma unroll
+    for (int q = 0; q <= D; ++q) {
+        rem[q] = s.len[q] - st[q];
+        total += rem[q];
+    }
+    const int hi = total < jhi ? total : jhi;
+    for (int j = jlo; j < hi; ++j) {
+        int a = j, L = 0, o = 0;
+        bool found = false;
+#pragma unroll
+        for (int q = 0; q <= D; ++q) {
+            if (!found) {
+                if (a < rem[q]) {
+                    L = q;
+                    o = st[q] + a;
+                    found = true;
+                } else {
+                    a -= rem[q];
+                }
+            }
+        }
+        const int x = uniform((int)s.seg[L * s.seg_cap + o]);
+        const uint32_t ccode = code | code_bits<K>((uint32_t)uniform((int)s.mark[x]), D + 1);
+        mem[D + 1] = x;
+        if constexpr (D + 1 == K - 3) {
+            push_marks<K, D + 1>(s, x);
+            core_node<K>(s, c, mem, ccode);
+            pop<K, D + 1>(s, x);
+        } else {
+            push<K, D + 1>(s, x);
+            int cst[K - 1];
+#pragma unroll
+            for (int q = 0; q < K - 1; ++q)
+                cst[q] = q < L ? s.len[q] : (q == L ? o + 1 : (q <= D ? st[q] : 0));
+            visit_core<K, D + 1>(s, c, cst, ccode, 0, INT_MAX, mem);
+            pop<K, D + 1>(s, x);
+        }
+    }
+}
+
+// A unit: k = 3, the core {v}; k = 4, the core {v, w_i}; k >= 5, the cores
+// below children jlo..jhi-1 of the node (v, w_i).
+template <int K>
+__device__ void run_core_unit(EnumState<K> &s, const CoreLds &c, int v, int i, uint32_t range)
+{
+    int mem[K];
+#pragma unroll
+    for (int q = 0; q < K; ++q) mem[q] = 0;
+    mem[0] = v;
+    s.root = v;
+    if constexpr (K == 3) {
+        push_marks<K, 0>(s, v);
+        core_node<K>(s, c, mem, 0u);
+        pop<K, 0>(s, v);
+    } else {
+        push<K, 0>(s, v);
+        if (i < s.len[0]) {
+            const int x = uniform((int)s.seg[i]);
+            const uint32_t code = code_bits<K>((uint32_t)uniform((int)s.mark[x]), 1);
+            mem[1] = x;
+            if constexpr (K == 4) {
+                push_marks<K, 1>(s, x);
+                core_node<K>(s, c, mem, code);
+                pop<K, 1>(s, x);
+            } else {
+                push<K, 1>(s, x);
+                int st[K - 1];
+#pragma unroll
+                for (int q = 0; q < K - 1; ++q) st[q] = 0;
+                st[0] = i + 1;
+                const bool full = range == kFullChild;
+                visit_core<K, 1>(s, c, st, code, full ? 0 : (int)(range & 0xFFFFu),
+                                 full ? INT_MAX : (int)(range >> 16), mem);
+                pop<K, 1>(s, x);
+            }
+        } else if (lane_id() == 0) {
+            atomicAdd(s.errors, 1u);
+        }
+        pop<K, 0>(s, v);
+    }
+}
+
+template <int K>
+__global__ __launch_bounds__(kWave) void core_kernel(const DevGraph *graphs, const int4 *units,
+                                                     uint32_t unit_cap, uint32_t unit_end,
+                                                     uint32_t *counters,
+                                                     const uint32_t *table, uint32_t num_classes,
+                                                     unsigned long long *hist_base,
+                                                     EnumConfig cfg)
+{
+    extern __shared__ uint32_t lds[];
+    EnumState<K> s;
+    const LdsLayout lay = lds_layout(K, cfg.max_n, cfg.seg_cap);
+    char *base = reinterpret_cast<char *>(lds);
+    CoreLds c;
+    c.cnt = reinterpret_cast<uint32_t *>(base + lay.total);
+    c.list = reinterpret_cast<uint8_t *>(c.cnt + kCells<K>);
+    c.pos = c.list + ((kCells<K> + 3) & ~3);
+    c.uid = reinterpret_cast<uint32_t *>(c.pos + ((kCells<K> + 3) & ~3));
+    c.agg = c.uid + kWave;
+    for (int i = lane_id(); i < kCells<K>; i += kWave) c.cnt[i] = 0u;
+    for (int i = lane_id(); i < kAggWords<K>; i += kWave) c.agg[i] = 0u;
+    init_state<K>(s, base, lay, cfg, counters, table, num_classes);
+    for_each_unit<K>(s, graphs, units, unit_cap, unit_end, counters, hist_base, cfg,
+                     [&](int v, int i, uint32_t range) { run_core_unit<K>(s, c, v, i, range); });
+}
+
+// hist[g][c] := raw / core_mult[c]; a raw count that is not a multiple (or
+// is negative as a 64-bit integer) is a device-side error.
+__global__ void core_divide_kernel(unsigned long long *hist, uint32_t num_classes,
+                                   const uint8_t *mult, uint32_t *errors)
+{
+    unsigned long long *h = hist + (size_t)blockIdx.y * num_classes;
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < num_classes;
+         i += gridDim.x * blockDim.x) {
+        const unsigned long long raw = h[i];
+        if (raw == 0) continue;
+        const uint32_t m = mult[i];
+        if (m == 0 || (long long)raw < 0) {
+            atomicAdd(errors, 1u);
+            continue;
+        }
+        const unsigned long long q = raw / m;
+        if (q * m != raw) atomicAdd(errors, 1u);
+        h[i] = q;
+    }
+}
+
+int core_lds_bytes(int k, int max_n, int seg_cap)
+{
+    return lds_layout(k, max_n, seg_cap).total + core_extra_bytes(k);
+}
+
+template <int K>
+static const void *core_fn()
+{
+    return reinterpret_cast<const void *>(&core_kernel<K>);
+}
+
+int core_max_blocks_per_cu(int k, int lds_bytes, int *blocks)
+{
+    const void *fn = nullptr;
+    switch (k) {
+    case 3: fn = core_fn<3>(); break;
+    case 4: fn = core_fn<4>(); break;
+    case 5: fn = core_fn<5>(); break;
+    case 6: fn = core_fn<6>(); break;
+    default: return fail(MK_ERANGE, "k=%d outside 3..6", k);
+    }
+    MK_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, fn, kWave, (size_t)lds_bytes));
+    return MK_OK;
+}
+
+int launch_core(int k, const DevGraph *d_graphs, const int4 *units, uint32_t unit_cap,
+                uint32_t unit_end, uint32_t *counters, const uint32_t *table, uint32_t num_classes,
+                unsigned long long *hist_base, const EnumConfig &cfg, int grid, int lds_bytes,
+                hipStream_t stream)
+{
+    if (grid <= 0) return MK_OK;
+#define MK_CORE_LAUNCH(KK)                                                                   \
+    hipLaunchKernelGGL(core_kernel<KK>, dim3(grid), dim3(kWave), lds_bytes, stream, d_graphs, \
+                       units, unit_cap, unit_end, counters, table, num_classes, hist_base, cfg)
+    switch (k) {
+    case 3: MK_CORE_LAUNCH(3); break;
+    case 4: MK_CORE_LAUNCH(4); break;
+    case 5: MK_CORE_LAUNCH(5); break;
+    case 6: MK_CORE_LAUNCH(6); break;
+    default: return fail(MK_ERANGE, "k=%d outside 3..6", k);
+    }
+#undef MK_CORE_LAUNCH
+    MK_HIP(hipGetLastError());
+    return MK_OK;
+}
+
+int launch_core_divide(unsigned long long *hist, int ng, uint32_t num_classes,
+                       const uint8_t *mult, uint32_t *counters, hipStream_t stream)
+{
+    if (ng <= 0 || num_classes == 0) return MK_OK;
+    constexpr int kThreads = 256;
+    const uint32_t blocks = std::min<uint32_t>((num_classes + kThreads * 4 - 1) / (kThreads * 4), 4096u);
+    hipLaunchKernelGGL(core_divide_kernel, dim3(blocks, (unsigned)ng), dim3(kThreads), 0, stream,
+                       hist, num_classes, mult, &counters[kErrors]);
+    MK_HIP(hipGetLastError());
+    return MK_OK;
+}
+
+}  // namespace mk

@@ -42,248 +42,9 @@
 // nodes, so the hash absorbs most of them, and only its flush looks codes up
 // in the code -> class table and adds to the graph's histogram with 64-bit
 // atomics.
-#include <climits>
-#include <type_traits>
-
-#include "internal.h"
+#include "esu.h"
 
 namespace mk {
-
-
-// members whose extension segment is kept: positions 0..k-3 (k >= 4; the
-// last two levels are flat), positions 0..1 for k = 3
-template <int K>
-constexpr int kSegments = K == 3 ? 2 : K - 2;
-constexpr int kScratchWords = 3 * kWave;
-// Compile-time tuning knobs (build flags may override them).
-#ifndef MK_HASH_BITS
-#define MK_HASH_BITS 8   // log2 of the per-wave hash slots
-#endif
-#ifndef MK_MERGE_ROUNDS
-#define MK_MERGE_ROUNDS 1  // ballot rounds merging equal codes before the hash
-#endif
-#ifndef MK_ROW_MIN
-#define MK_ROW_MIN 32    // see kRowMin
-#endif
-
-// Per-wave hash of pending (code, count) pairs; flushed to the histogram when
-// half full, at the end of a unit once a quarter full, on a graph switch and
-// at exit.
-constexpr int kHashBits = MK_HASH_BITS;
-constexpr int kHashSlots = 1 << kHashBits;
-constexpr int kHashProbes = 8;
-constexpr uint32_t kEmpty = 0xFFFFFFFFu;
-// A flush is forced once this many subgraphs are pending, so no 32-bit slot
-// count can overflow (every insert adds less than 2^31 on top).
-constexpr uint32_t kPendingMax = 1u << 30;
-// Rows of the last-level pair triangle, and children's lists, at least this
-// long are processed one at a time with their first vertex wave-uniform.
-constexpr int kRowMin = MK_ROW_MIN;
-
-// Byte offsets of one wave's LDS: marks (n x 2 or 4 bytes), extension
-// segments (u16), scratch, hash keys and counts; each part 4-byte aligned.
-struct LdsLayout {
-    int seg, scratch, total;
-};
-
-__host__ __device__ inline LdsLayout lds_layout(int k, int max_n, int seg_cap)
-{
-    const int segs = k == 3 ? 2 : k - 2;
-    const int mark_bytes = ((k <= 5 ? 2 : 4) * max_n + 3) & ~3;
-    const int seg_bytes = (2 * segs * seg_cap + 3) & ~3;
-    LdsLayout l;
-    l.seg = mark_bytes;
-    l.scratch = l.seg + seg_bytes;
-    l.total = l.scratch + 4 * (kScratchWords + 2 * kHashSlots);
-    return l;
-}
-
-// Marks hold, for members at positions 0..kSegments-1, the "in" bits spread
-// at stride k-1 (highest at (kSegments-1)(k-1)) and then one "out" bit per
-// position: 5 / 6 / 12 / 20 bits for k = 3 / 4 / 5 / 6, so 16-bit marks do
-// for k <= 5.
-template <int K>
-using MarkT = typename std::conditional<K <= 5, uint16_t, uint32_t>::type;
-
-template <int K>
-struct EnumState {
-    static constexpr int OUTB = (kSegments<K> - 1) * (K - 1) + 1;
-    static constexpr uint32_t INMASK = (1u << OUTB) - 1u;
-    static_assert(OUTB + kSegments<K> <= 8 * (int)sizeof(MarkT<K>), "mark bits do not fit");
-    MarkT<K> *mark;
-    uint16_t *seg;              // vertex ids (n <= MK_MAX_VERTICES < 65536)
-    int seg_cap;
-    int root;
-    const int32_t *urow;
-    const uint32_t *uadj;
-    const uint32_t *bits_out;   // row w bit u: arc w -> u
-    const uint32_t *bits_in;    // row w bit u: arc u -> w
-    int words;
-    uint32_t *scratch;          // 3 x 64 words of LDS per wave
-    uint32_t *hkey;             // per-wave LDS hash: code (kEmpty = free)
-    uint32_t *hcnt;             //   and its pending count
-    int hused;                  // keys in the hash (wave-uniform)
-    uint32_t hpending;          // subgraphs pending in the hash (wave-uniform)
-    uint32_t flags;             // kDebug* bits
-    unsigned long long *hist;
-    const uint32_t *table;
-    uint32_t num_classes;
-    uint32_t *errors;
-    int len[K - 1];
-};
-
-__device__ __forceinline__ int lane_id() { return (int)threadIdx.x; }
-
-__device__ __forceinline__ int uniform(int x) { return __builtin_amdgcn_readfirstlane(x); }
-
-__device__ __forceinline__ uint32_t lanes_below(unsigned long long mask)
-{
-    return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
-                                     __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
-}
-
-// both mark bits of member position d for a neighbour of type t
-template <int K>
-__device__ __forceinline__ uint32_t mark_bits(int d, uint32_t t)
-{
-    return ((t & 1u) << (d * (K - 1))) | (((t >> 1) & 1u) << (EnumState<K>::OUTB + d));
-}
-
-// code bits contributed by a vertex with mark m joining at position p >= 1
-template <int K>
-__device__ __forceinline__ uint32_t code_bits(uint32_t m, int p)
-{
-    return ((m >> EnumState<K>::OUTB) << (p * (K - 1))) | ((m & EnumState<K>::INMASK) << (p - 1));
-}
-
-// s_D := x.  Builds seg[D] (new exclusive extension vertices, ascending) and
-// ORs position D's bits into the marks of x's neighbours.
-template <int K, int D>
-__device__ __forceinline__ void push(EnumState<K> &s, int x)
-{
-    const int lane = lane_id();
-    const int r0 = uniform(s.urow[x]);
-    const int r1 = uniform(s.urow[x + 1]);
-    uint16_t *seg = s.seg + D * s.seg_cap;
-    int cnt = 0;
-    for (int base = r0; base < r1; base += kWave) {
-        const int e = base + lane;
-        const bool valid = e < r1;
-        const uint32_t ent = valid ? s.uadj[e] : 0u;
-        const int y = (int)(ent >> 2);
-        const uint32_t m = valid ? s.mark[y] : 1u;
-        const bool fresh = valid && y > s.root && m == 0u;
-        const unsigned long long bal = __ballot(fresh);
-        if (fresh) seg[cnt + (int)lanes_below(bal)] = (uint16_t)y;
-        cnt += __popcll(bal);
-        if (valid) s.mark[y] = (MarkT<K>)(m | mark_bits<K>(D, ent & 3u));
-    }
-    s.len[D] = cnt;
-    __syncthreads();
-}
-
-// undo push<D>(x)
-template <int K, int D>
-__device__ __forceinline__ void pop(EnumState<K> &s, int x)
-{
-    const int lane = lane_id();
-    const int r0 = uniform(s.urow[x]);
-    const int r1 = uniform(s.urow[x + 1]);
-    const uint32_t keep = ~mark_bits<K>(D, 3u);
-    for (int base = r0; base < r1; base += kWave) {
-        const int e = base + lane;
-        if (e < r1) {
-            const int y = (int)(s.uadj[e] >> 2);
-            s.mark[y] = (MarkT<K>)(s.mark[y] & keep);
-        }
-    }
-    __syncthreads();
-}
-
-// add n to the histogram bin of code (table lookup + global 64-bit atomic)
-template <int K>
-__device__ __forceinline__ void add_global(EnumState<K> &s, uint32_t code, uint32_t n)
-{
-    const uint32_t id = s.table[code];
-    if (id < s.num_classes) atomicAdd(&s.hist[id], (unsigned long long)n);
-    else atomicAdd(s.errors, 1u);
-}
-
-// move the wave's pending counts to the histogram and empty the hash
-template <int K>
-__device__ __forceinline__ void flush_hash(EnumState<K> &s)
-{
-    __syncthreads();
-    for (int i = lane_id(); i < kHashSlots; i += kWave) {
-        const uint32_t key = s.hkey[i];
-        if (key != kEmpty) {
-            add_global<K>(s, key, s.hcnt[i]);
-            s.hkey[i] = kEmpty;
-            s.hcnt[i] = 0u;
-        }
-    }
-    s.hused = 0;
-    s.hpending = 0;
-    __syncthreads();
-}
-
-// Add n to the pending count of code for every lane with `mine` set: the
-// wave's LDS hash (linear probing); a lane that finds no slot within
-// kHashProbes goes straight to the histogram.  Flushes when half full.
-template <int K>
-__device__ __forceinline__ void hash_insert(EnumState<K> &s, bool mine, uint32_t code, uint32_t n)
-{
-    bool fresh = false;
-    if (s.flags & kDebugNoHash) {
-        if (mine) add_global<K>(s, code, n);
-        return;
-    }
-    if (mine) {
-        // one compare-and-swap either claims an empty slot or finds the code
-        // already there; only a collision probes on
-        uint32_t h = (code * 2654435761u) >> (32 - kHashBits);
-        uint32_t old = atomicCAS(&s.hkey[h], kEmpty, code);
-        bool ok = old == kEmpty || old == code;
-        for (int p = 1; p < kHashProbes && !ok; ++p) {
-            h = (h + 1) & (kHashSlots - 1);
-            old = atomicCAS(&s.hkey[h], kEmpty, code);
-            ok = old == kEmpty || old == code;
-        }
-        if (ok) {
-            fresh = old == kEmpty;
-            atomicAdd(&s.hcnt[h], n);
-        } else {
-            add_global<K>(s, code, n);
-        }
-    }
-    s.hused += __popcll(__ballot(fresh));
-    if (s.hused > kHashSlots / 2 || s.hpending >= kPendingMax || (s.flags & kDebugFlushAlways))
-        flush_hash<K>(s);
-}
-
-// count one code per valid lane.  MK_MERGE_ROUNDS ballot rounds merge the
-// lanes that share the first remaining lane's code; every code left goes
-// into the hash.
-template <int K>
-__device__ __forceinline__ void count_codes(EnumState<K> &s, bool valid, uint32_t code)
-{
-    const int lane = lane_id();
-    unsigned long long act = __ballot(valid);
-    if (!act) return;
-    s.hpending += (uint32_t)__popcll(act);
-    uint32_t n = 1;
-#pragma unroll
-    for (int r = 0; r < MK_MERGE_ROUNDS; ++r) {
-        if (!act) break;
-        const int l = __builtin_ctzll(act);
-        const uint32_t c0 = (uint32_t)__builtin_amdgcn_readlane((int)code, l);
-        const unsigned long long eq = __ballot(code == c0) & act;
-        if (lane == l) n = (uint32_t)__popcll(eq);
-        else if ((eq >> lane) & 1ull) n = 0;
-        act &= ~eq;
-    }
-    hash_insert<K>(s, valid && n > 0, code, n);
-}
 
 // last level: members s_0..s_{K-2}; every extension vertex closes a k-set
 template <int K>
@@ -722,74 +483,10 @@ __global__ __launch_bounds__(kWave) void enum_kernel(const DevGraph *graphs, con
 {
     extern __shared__ uint32_t lds[];
     EnumState<K> s;
-    const int max_n = cfg.max_n;
-    const LdsLayout lay = lds_layout(K, max_n, cfg.seg_cap);
-    char *base = reinterpret_cast<char *>(lds);
-    s.mark = reinterpret_cast<MarkT<K> *>(base);
-    s.seg = reinterpret_cast<uint16_t *>(base + lay.seg);
-    s.seg_cap = cfg.seg_cap;
-    s.flags = cfg.flags;
-    s.scratch = reinterpret_cast<uint32_t *>(base + lay.scratch);
-    s.hkey = s.scratch + kScratchWords;
-    s.hcnt = s.hkey + kHashSlots;
-    s.hused = 0;
-    s.hpending = 0;
-    for (int i = lane_id(); i < kHashSlots; i += kWave) {
-        s.hkey[i] = kEmpty;
-        s.hcnt[i] = 0u;
-    }
-    s.bits_out = nullptr;
-    s.bits_in = nullptr;
-    s.words = 0;
-    s.table = table;
-    s.num_classes = num_classes;
-    s.errors = &counters[kErrors];
-    s.root = 0;
-    s.urow = nullptr;
-    s.uadj = nullptr;
-    s.hist = nullptr;
-    for (int i = lane_id(); i < max_n; i += kWave) s.mark[i] = 0;
-    __syncthreads();
-    const uint32_t navail = counters[kNumUnits];
-    const uint32_t cap = unit_cap < unit_end ? unit_cap : unit_end;
-    const uint32_t end = navail < cap ? navail : cap;
-    const uint32_t begin = counters[kSliceBegin];
-    const uint32_t span = end > begin ? end - begin : 0u;
-    // units per grab: about 1/16 of a wave's share, 1..16
-    uint32_t chunk = cfg.chunk ? cfg.chunk : span / (gridDim.x * 16u);
-    chunk = chunk < 1u ? 1u : (chunk > 256u ? 256u : chunk);
-    if (!cfg.chunk && chunk > 16u) chunk = 16u;
-    int cur = -1;
-    const int home = (int)(blockIdx.x % kQueues);
-    for (int q = 0; q < kQueues; ++q) {
-        const int x = (home + q) % kQueues;
-        const uint32_t lo = begin + (uint32_t)((uint64_t)span * x / kQueues);
-        const uint32_t hi = begin + (uint32_t)((uint64_t)span * (x + 1) / kQueues);
-        for (;;) {
-            uint32_t idx = 0;
-            if (lane_id() == 0) idx = atomicAdd(&counters[kQueueHeads + x * kHeadStride], chunk);
-            idx = lo + (uint32_t)uniform((int)idx);
-            if (idx >= hi) break;
-            const uint32_t stop = idx + chunk < hi ? idx + chunk : hi;
-            for (; idx < stop; ++idx) {
-                const int4 u = units[idx];
-                const int gi = uniform(u.x);
-                if (gi != cur) {
-                    if (s.hused) flush_hash<K>(s);
-                    s.urow = graphs[gi].urow;
-                    s.uadj = graphs[gi].uadj;
-                    s.bits_out = graphs[gi].bits_out;
-                    s.bits_in = graphs[gi].bits_in;
-                    s.words = graphs[gi].words;
-                    s.hist = hist_base + (size_t)gi * num_classes;
-                    cur = gi;
-                }
-                run_unit<K>(s, uniform(u.y), uniform(u.z), (uint32_t)uniform(u.w));
-                if (s.hused > kHashSlots / 4) flush_hash<K>(s);
-            }
-        }
-    }
-    if (s.hused) flush_hash<K>(s);
+    const LdsLayout lay = lds_layout(K, cfg.max_n, cfg.seg_cap);
+    init_state<K>(s, reinterpret_cast<char *>(lds), lay, cfg, counters, table, num_classes);
+    for_each_unit<K>(s, graphs, units, unit_cap, unit_end, counters, hist_base, cfg,
+                     [&](int v, int i, uint32_t range) { run_unit<K>(s, v, i, range); });
 }
 
 int enum_lds_bytes(int k, int max_n, int seg_cap) { return lds_layout(k, max_n, seg_cap).total; }

@@ -1,0 +1,378 @@
+// Wave-level building blocks of the ESU walk shared by the enumeration
+// kernel (every k-set, Section 3.2's O(1) lookup per subgraph) and the
+// (k-2)-set counting kernel (Section 3's loop over L_{k-2}): per-wave LDS
+// marks and extension segments, member push/pop, the per-wave hash of
+// pending (code, count) pairs with its flush into the histogram, and the
+// persistent work-queue loop.
+//
+// One 64-lane wavefront is one workgroup.  Waves are persistent: each takes
+// work units from global queues until they are empty.  The unit list is cut
+// into eight ranges with a head each (one per XCD, on separate cache lines);
+// a wave starts on the range of its own XCD (workgroups are dealt to the
+// XCDs round-robin, so consecutive units of one graph stay in one L2) and
+// then helps the others.  Units are grabbed a few at a time, so the head
+// atomics stay far below their throughput limit.
+// A unit is a first-level ESU node (root v, first extension vertex w_i),
+// possibly restricted to a range of that node's children (hub splitting).
+//
+// Per wave, LDS holds
+//   mark[n]        for every vertex x, its relation to the current members
+//                  s_0..s_d of the growing subgraph: "in" bit d(k-1) set iff
+//                  arc s_d -> x, "out" bit OUTB+d set iff arc x -> s_d.  The
+//                  in bits are already spread at stride k-1, so the code
+//                  bits that a vertex adds when it joins at position p are
+//                      (out << p(k-1)) | (in << (p-1))
+//                  -- exactly bits b(i,p) = i(k-1)+p-1 and b(p,i) = p(k-1)+i
+//                  of the adjacency code.  mark[x] == 0 also says "x is
+//                  neither a member nor a neighbour of one" (the exclusive
+//                  neighbourhood test of ESU).
+//   seg[l][.]      the vertices that joined the extension list when member
+//                  s_l was added (s_0's are the root's larger neighbours).
+// A node's extension list is the concatenation of the unconsumed tails of
+// seg[0..d]; it is never copied.
+//
+// Adding a member scans its typed adjacency list (Section 2's A/B/C types)
+// with all 64 lanes: each lane reads the mark of one neighbour, a ballot and
+// a lane-prefix count compact the new extension vertices into seg[d], and the
+// lane ORs the member's two bits into the neighbour's mark.  Removing it
+// clears those bits again, so marks are all zero between units.
+//
+// Counts are added to a small per-wave LDS hash of pending (code, count)
+// pairs; only its flush looks codes up in the code -> class table and adds
+// to the graph's histogram with 64-bit atomics.
+#pragma once
+
+#include <climits>
+#include <type_traits>
+
+#include "internal.h"
+
+namespace mk {
+
+
+
+// members whose extension segment is kept: positions 0..k-3 (k >= 4; the
+// last two levels are flat), positions 0..1 for k = 3
+template <int K>
+constexpr int kSegments = K == 3 ? 2 : K - 2;
+constexpr int kScratchWords = 3 * kWave;
+// Compile-time tuning knobs (build flags may override them).
+#ifndef MK_HASH_BITS
+#define MK_HASH_BITS 8   // log2 of the per-wave hash slots
+#endif
+#ifndef MK_MERGE_ROUNDS
+#define MK_MERGE_ROUNDS 1  // ballot rounds merging equal codes before the hash
+#endif
+#ifndef MK_ROW_MIN
+#define MK_ROW_MIN 32    // see kRowMin
+#endif
+
+// Per-wave hash of pending (code, count) pairs; flushed to the histogram when
+// half full, at the end of a unit once a quarter full, on a graph switch and
+// at exit.
+constexpr int kHashBits = MK_HASH_BITS;
+constexpr int kHashSlots = 1 << kHashBits;
+constexpr int kHashProbes = 8;
+constexpr uint32_t kEmpty = 0xFFFFFFFFu;
+// A flush is forced once this many subgraphs are pending, so no 32-bit slot
+// count can overflow (every insert adds less than 2^31 on top).
+constexpr uint32_t kPendingMax = 1u << 30;
+// Rows of the last-level pair triangle, and children's lists, at least this
+// long are processed one at a time with their first vertex wave-uniform.
+constexpr int kRowMin = MK_ROW_MIN;
+
+// Byte offsets of one wave's LDS: marks (n x 2 or 4 bytes), extension
+// segments (u16), scratch, hash keys and counts; each part 4-byte aligned.
+struct LdsLayout {
+    int seg, scratch, total;
+};
+
+__host__ __device__ inline LdsLayout lds_layout(int k, int max_n, int seg_cap)
+{
+    const int segs = k == 3 ? 2 : k - 2;
+    const int mark_bytes = ((k <= 5 ? 2 : 4) * max_n + 3) & ~3;
+    const int seg_bytes = (2 * segs * seg_cap + 3) & ~3;
+    LdsLayout l;
+    l.seg = mark_bytes;
+    l.scratch = l.seg + seg_bytes;
+    l.total = l.scratch + 4 * (kScratchWords + 2 * kHashSlots);
+    return l;
+}
+
+// Marks hold, for members at positions 0..kSegments-1, the "in" bits spread
+// at stride k-1 (highest at (kSegments-1)(k-1)) and then one "out" bit per
+// position: 5 / 6 / 12 / 20 bits for k = 3 / 4 / 5 / 6, so 16-bit marks do
+// for k <= 5.
+template <int K>
+using MarkT = typename std::conditional<K <= 5, uint16_t, uint32_t>::type;
+
+template <int K>
+struct EnumState {
+    static constexpr int OUTB = (kSegments<K> - 1) * (K - 1) + 1;
+    static constexpr uint32_t INMASK = (1u << OUTB) - 1u;
+    static_assert(OUTB + kSegments<K> <= 8 * (int)sizeof(MarkT<K>), "mark bits do not fit");
+    MarkT<K> *mark;
+    uint16_t *seg;              // vertex ids (n <= MK_MAX_VERTICES < 65536)
+    int seg_cap;
+    int root;
+    const int32_t *urow;
+    const uint32_t *uadj;
+    const uint32_t *bits_out;   // row w bit u: arc w -> u
+    const uint32_t *bits_in;    // row w bit u: arc u -> w
+    int words;
+    uint32_t *scratch;          // 3 x 64 words of LDS per wave
+    uint32_t *hkey;             // per-wave LDS hash: code (kEmpty = free)
+    uint32_t *hcnt;             //   and its pending count
+    int hused;                  // keys in the hash (wave-uniform)
+    uint32_t hpending;          // subgraphs pending in the hash (wave-uniform)
+    uint32_t flags;             // kDebug* bits
+    unsigned long long *hist;
+    const uint32_t *table;
+    uint32_t num_classes;
+    uint32_t *errors;
+    int len[K - 1];
+};
+
+__device__ __forceinline__ int lane_id() { return (int)threadIdx.x; }
+
+__device__ __forceinline__ int uniform(int x) { return __builtin_amdgcn_readfirstlane(x); }
+
+__device__ __forceinline__ uint32_t lanes_below(unsigned long long mask)
+{
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                     __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+// both mark bits of member position d for a neighbour of type t
+template <int K>
+__device__ __forceinline__ uint32_t mark_bits(int d, uint32_t t)
+{
+    return ((t & 1u) << (d * (K - 1))) | (((t >> 1) & 1u) << (EnumState<K>::OUTB + d));
+}
+
+// code bits contributed by a vertex with mark m joining at position p >= 1
+template <int K>
+__device__ __forceinline__ uint32_t code_bits(uint32_t m, int p)
+{
+    return ((m >> EnumState<K>::OUTB) << (p * (K - 1))) | ((m & EnumState<K>::INMASK) << (p - 1));
+}
+
+// s_D := x.  Builds seg[D] (new exclusive extension vertices, ascending) and
+// ORs position D's bits into the marks of x's neighbours.
+template <int K, int D>
+__device__ __forceinline__ void push(EnumState<K> &s, int x)
+{
+    const int lane = lane_id();
+    const int r0 = uniform(s.urow[x]);
+    const int r1 = uniform(s.urow[x + 1]);
+    uint16_t *seg = s.seg + D * s.seg_cap;
+    int cnt = 0;
+    for (int base = r0; base < r1; base += kWave) {
+        const int e = base + lane;
+        const bool valid = e < r1;
+        const uint32_t ent = valid ? s.uadj[e] : 0u;
+        const int y = (int)(ent >> 2);
+        const uint32_t m = valid ? s.mark[y] : 1u;
+        const bool fresh = valid && y > s.root && m == 0u;
+        const unsigned long long bal = __ballot(fresh);
+        if (fresh) seg[cnt + (int)lanes_below(bal)] = (uint16_t)y;
+        cnt += __popcll(bal);
+        if (valid) s.mark[y] = (MarkT<K>)(m | mark_bits<K>(D, ent & 3u));
+    }
+    s.len[D] = cnt;
+    __syncthreads();
+}
+
+// undo push<D>(x)
+template <int K, int D>
+__device__ __forceinline__ void pop(EnumState<K> &s, int x)
+{
+    const int lane = lane_id();
+    const int r0 = uniform(s.urow[x]);
+    const int r1 = uniform(s.urow[x + 1]);
+    const uint32_t keep = ~mark_bits<K>(D, 3u);
+    for (int base = r0; base < r1; base += kWave) {
+        const int e = base + lane;
+        if (e < r1) {
+            const int y = (int)(s.uadj[e] >> 2);
+            s.mark[y] = (MarkT<K>)(s.mark[y] & keep);
+        }
+    }
+    __syncthreads();
+}
+
+// add n to the histogram bin of code (table lookup + global 64-bit atomic)
+template <int K>
+__device__ __forceinline__ void add_global(EnumState<K> &s, uint32_t code, uint32_t n)
+{
+    const uint32_t id = s.table[code];
+    // n is a 32-bit two's complement count (negative only in the (k-2)-set
+    // counting); sign-extended, the 64-bit sums stay exact modulo 2^64
+    if (id < s.num_classes) atomicAdd(&s.hist[id], (unsigned long long)(long long)(int32_t)n);
+    else atomicAdd(s.errors, 1u);
+}
+
+// move the wave's pending counts to the histogram and empty the hash
+template <int K>
+__device__ __forceinline__ void flush_hash(EnumState<K> &s)
+{
+    __syncthreads();
+    for (int i = lane_id(); i < kHashSlots; i += kWave) {
+        const uint32_t key = s.hkey[i];
+        if (key != kEmpty) {
+            if (s.hcnt[i] != 0u) add_global<K>(s, key, s.hcnt[i]);
+            s.hkey[i] = kEmpty;
+            s.hcnt[i] = 0u;
+        }
+    }
+    s.hused = 0;
+    s.hpending = 0;
+    __syncthreads();
+}
+
+// Add n to the pending count of code for every lane with `mine` set: the
+// wave's LDS hash (linear probing); a lane that finds no slot within
+// kHashProbes goes straight to the histogram.  Flushes when half full.
+template <int K>
+__device__ __forceinline__ void hash_insert(EnumState<K> &s, bool mine, uint32_t code, uint32_t n)
+{
+    bool fresh = false;
+    if (s.flags & kDebugNoHash) {
+        if (mine) add_global<K>(s, code, n);
+        return;
+    }
+    if (mine) {
+        // one compare-and-swap either claims an empty slot or finds the code
+        // already there; only a collision probes on
+        uint32_t h = (code * 2654435761u) >> (32 - kHashBits);
+        uint32_t old = atomicCAS(&s.hkey[h], kEmpty, code);
+        bool ok = old == kEmpty || old == code;
+        for (int p = 1; p < kHashProbes && !ok; ++p) {
+            h = (h + 1) & (kHashSlots - 1);
+            old = atomicCAS(&s.hkey[h], kEmpty, code);
+            ok = old == kEmpty || old == code;
+        }
+        if (ok) {
+            fresh = old == kEmpty;
+            atomicAdd(&s.hcnt[h], n);
+        } else {
+            add_global<K>(s, code, n);
+        }
+    }
+    s.hused += __popcll(__ballot(fresh));
+    if (s.hused > kHashSlots / 2 || s.hpending >= kPendingMax || (s.flags & kDebugFlushAlways))
+        flush_hash<K>(s);
+}
+
+// count one code per valid lane.  MK_MERGE_ROUNDS ballot rounds merge the
+// lanes that share the first remaining lane's code; every code left goes
+// into the hash.
+template <int K>
+__device__ __forceinline__ void count_codes(EnumState<K> &s, bool valid, uint32_t code)
+{
+    const int lane = lane_id();
+    unsigned long long act = __ballot(valid);
+    if (!act) return;
+    s.hpending += (uint32_t)__popcll(act);
+    uint32_t n = 1;
+#pragma unroll
+    for (int r = 0; r < MK_MERGE_ROUNDS; ++r) {
+        if (!act) break;
+        const int l = __builtin_ctzll(act);
+        const uint32_t c0 = (uint32_t)__builtin_amdgcn_readlane((int)code, l);
+        const unsigned long long eq = __ballot(code == c0) & act;
+        if (lane == l) n = (uint32_t)__popcll(eq);
+        else if ((eq >> lane) & 1ull) n = 0;
+        act &= ~eq;
+    }
+    hash_insert<K>(s, valid && n > 0, code, n);
+}
+
+
+// Set up a wave's state on its LDS (marks zero, hash empty).
+template <int K>
+__device__ __forceinline__ void init_state(EnumState<K> &s, char *base, const LdsLayout &lay,
+                                           const EnumConfig &cfg, uint32_t *counters,
+                                           const uint32_t *table, uint32_t num_classes)
+{
+    s.mark = reinterpret_cast<MarkT<K> *>(base);
+    s.seg = reinterpret_cast<uint16_t *>(base + lay.seg);
+    s.seg_cap = cfg.seg_cap;
+    s.flags = cfg.flags;
+    s.scratch = reinterpret_cast<uint32_t *>(base + lay.scratch);
+    s.hkey = s.scratch + kScratchWords;
+    s.hcnt = s.hkey + kHashSlots;
+    s.hused = 0;
+    s.hpending = 0;
+    for (int i = lane_id(); i < kHashSlots; i += kWave) {
+        s.hkey[i] = kEmpty;
+        s.hcnt[i] = 0u;
+    }
+    s.bits_out = nullptr;
+    s.bits_in = nullptr;
+    s.words = 0;
+    s.table = table;
+    s.num_classes = num_classes;
+    s.errors = &counters[kErrors];
+    s.root = 0;
+    s.urow = nullptr;
+    s.uadj = nullptr;
+    s.hist = nullptr;
+    for (int i = lane_id(); i < cfg.max_n; i += kWave) s.mark[i] = 0;
+    __syncthreads();
+}
+
+// The persistent loop: take units from the kQueues queues (own XCD's range
+// first) and call run(v, i, range) for each, switching the graph (and
+// flushing the hash) when the unit's graph changes.  The hash is flushed at
+// the end.
+template <int K, typename Run>
+__device__ __forceinline__ void for_each_unit(EnumState<K> &s, const DevGraph *graphs,
+                                              const int4 *units, uint32_t unit_cap,
+                                              uint32_t unit_end, uint32_t *counters,
+                                              unsigned long long *hist_base, const EnumConfig &cfg,
+                                              Run run)
+{
+    const uint32_t navail = counters[kNumUnits];
+    const uint32_t cap = unit_cap < unit_end ? unit_cap : unit_end;
+    const uint32_t end = navail < cap ? navail : cap;
+    const uint32_t begin = counters[kSliceBegin];
+    const uint32_t span = end > begin ? end - begin : 0u;
+    // units per grab: about 1/16 of a wave's share, 1..16
+    uint32_t chunk = cfg.chunk ? cfg.chunk : span / (gridDim.x * 16u);
+    chunk = chunk < 1u ? 1u : (chunk > 256u ? 256u : chunk);
+    if (!cfg.chunk && chunk > 16u) chunk = 16u;
+    int cur = -1;
+    const int home = (int)(blockIdx.x % kQueues);
+    for (int q = 0; q < kQueues; ++q) {
+        const int x = (home + q) % kQueues;
+        const uint32_t lo = begin + (uint32_t)((uint64_t)span * x / kQueues);
+        const uint32_t hi = begin + (uint32_t)((uint64_t)span * (x + 1) / kQueues);
+        for (;;) {
+            uint32_t idx = 0;
+            if (lane_id() == 0) idx = atomicAdd(&counters[kQueueHeads + x * kHeadStride], chunk);
+            idx = lo + (uint32_t)uniform((int)idx);
+            if (idx >= hi) break;
+            const uint32_t stop = idx + chunk < hi ? idx + chunk : hi;
+            for (; idx < stop; ++idx) {
+                const int4 u = units[idx];
+                const int gi = uniform(u.x);
+                if (gi != cur) {
+                    if (s.hused) flush_hash<K>(s);
+                    s.urow = graphs[gi].urow;
+                    s.uadj = graphs[gi].uadj;
+                    s.bits_out = graphs[gi].bits_out;
+                    s.bits_in = graphs[gi].bits_in;
+                    s.words = graphs[gi].words;
+                    s.hist = hist_base + (size_t)gi * s.num_classes;
+                    cur = gi;
+                }
+                run(uniform(u.y), uniform(u.z), (uint32_t)uniform(u.w));
+                if (s.hused > kHashSlots / 4) flush_hash<K>(s);
+            }
+        }
+    }
+    if (s.hused) flush_hash<K>(s);
+}
+
+}  // namespace mk

@@ -38,6 +38,7 @@ struct Table {
     uint32_t num_classes = 0;
     uint32_t *d_table = nullptr;   // entries x uint32: code -> class id
     uint32_t *d_classes = nullptr; // num_classes canonical codes, ascending
+    uint8_t *d_core_mult = nullptr; // num_classes: cores per class ((k-2)-set counting)
     std::vector<uint32_t> classes; // host copy of d_classes
     double build_ms = 0.0;
 };
@@ -125,7 +126,7 @@ int launch_typed_csr(const DevGraph *d_graphs, int ng, int max_n, int64_t max_m,
                      hipStream_t stream);
 
 // Work-unit planner: cost estimate, counts per slot, scan, emit (units ==
-// nullptr: sizing only).  Writes counters[kNumUnits].  The split threshold
+// nullptr: sizing only).  k = 2 plans one unit per vertex with a neighbour.  Writes counters[kNumUnits].  The split threshold
 // is max(split_threshold, estimated total / (waves * 16)).
 int launch_plan(int k, const DevGraph *d_graphs, int ng, int64_t max_nnz, uint32_t total_slots,
                 uint32_t *slot_cnt, uint32_t *slot_off, uint32_t *slot_est, uint32_t *slot_vi,
@@ -154,6 +155,18 @@ int launch_enum(int k, const DevGraph *d_graphs, const int4 *units, uint32_t uni
                 uint32_t unit_end, uint32_t *counters, const uint32_t *table, uint32_t num_classes,
                 unsigned long long *hist_base, const EnumConfig &cfg, int grid, int lds_bytes,
                 hipStream_t stream);
+
+// Counting from the connected (k-2)-sets: same queues, units planned for
+// (k-1)-sets (k = 3: one unit per vertex), raw sums into the histograms,
+// then the division by the cores per class.
+int core_lds_bytes(int k, int max_n, int seg_cap);
+int core_max_blocks_per_cu(int k, int lds_bytes, int *blocks);
+int launch_core(int k, const DevGraph *d_graphs, const int4 *units, uint32_t unit_cap,
+                uint32_t unit_end, uint32_t *counters, const uint32_t *table, uint32_t num_classes,
+                unsigned long long *hist_base, const EnumConfig &cfg, int grid, int lds_bytes,
+                hipStream_t stream);
+int launch_core_divide(unsigned long long *hist, int ng, uint32_t num_classes,
+                       const uint8_t *mult, uint32_t *counters, hipStream_t stream);
 
 void free_table(Table *t);
 

@@ -154,12 +154,18 @@ __global__ __launch_bounds__(kPlanThreads) void plan_kernel(const DevGraph *grap
             // the full walk: owner, position, extension length, child costs
             const int v = owner_of(g.urow, g.n, e);
             uint32_t vi = kNoNode;
-            if (y > v) {
+            if constexpr (K == 2) {
+                // one unit per vertex, on its first list entry
+                if (e == g.urow[v]) {
+                    est = 1;
+                    vi = (uint32_t)v;
+                }
+            } else if (y > v) {
                 const int r1 = g.urow[v + 1];
                 const int first = first_above(g.uadj, g.urow[v], r1, v);
                 const int i = e - first;
                 const int L2 = ext_len(g, v, r1 - first, i, y);
-                if (K == 3) est = (uint64_t)L2 + 1;
+                if constexpr (K == 3) est = (uint64_t)L2 + 1;
                 else split_children<K, false>(g, v, first, r1, i, y, L2, ~0ull, &est,
                                               [](uint32_t, uint32_t) {});
                 vi = (uint32_t)v | ((uint32_t)i << 13);
@@ -174,14 +180,14 @@ __global__ __launch_bounds__(kPlanThreads) void plan_kernel(const DevGraph *grap
                 const int v = (int)(vi & 0x1FFFu), i = (int)(vi >> 13);
                 const bool split = K > 3 && sest != 0xFFFFFFFFu && sest > threshold
                                        ? true : (K > 3 && sest == 0xFFFFFFFFu);
-                if (K == 3) {
+                if (K <= 3) {
                     cnt = 1;
                 } else if (sest <= 1 && !split) {
                     // no children below (v, w_i): L2 == 0 gives est 0
                     cnt = sest == 0 ? 0 : 1;
                 } else if (!split) {
                     cnt = 1;
-                } else {
+                } else if constexpr (K > 3) {
                     const int r1 = g.urow[v + 1];
                     const int first = e - i;
                     const int L2 = ext_len(g, v, r1 - first, i, y);
@@ -260,6 +266,9 @@ int launch_plan(int k, const DevGraph *d_graphs, int ng, int64_t max_nnz, uint32
 {
     if (ng <= 0) return MK_OK;
     switch (k) {
+    case 2:
+        return plan_k<2>(d_graphs, ng, max_nnz, total_slots, slot_cnt, slot_off, slot_est, slot_vi, scan_tmp, units,
+                         unit_cap, split_threshold, waves, counters, stream);
     case 3:
         return plan_k<3>(d_graphs, ng, max_nnz, total_slots, slot_cnt, slot_off, slot_est, slot_vi, scan_tmp, units,
                          unit_cap, split_threshold, waves, counters, stream);
@@ -272,7 +281,7 @@ int launch_plan(int k, const DevGraph *d_graphs, int ng, int64_t max_nnz, uint32
     case 6:
         return plan_k<6>(d_graphs, ng, max_nnz, total_slots, slot_cnt, slot_off, slot_est, slot_vi, scan_tmp, units,
                          unit_cap, split_threshold, waves, counters, stream);
-    default: return fail(MK_ERANGE, "k=%d outside 3..6", k);
+    default: return fail(MK_ERANGE, "plan size k=%d outside 2..6", k);
     }
 }
 

@@ -198,6 +198,65 @@ static int launch_canon(uint32_t *table, uint32_t *repbits, uint64_t ncodes, int
     return MK_OK;
 }
 
+// Cores of every class (the divisor of the (k-2)-set counting): subsets X
+// of k-2 vertices whose induced subgraph is weakly connected and which both
+// other vertices touch.  One thread per class, on bitmasks: nb[i] = vertices
+// joined to i by an arc either way; X's connectivity by growing the set
+// reached from its lowest vertex.
+template <int K>
+__global__ void core_mult_kernel(const uint32_t *classes, uint32_t n, uint8_t *mult)
+{
+    const uint32_t id = blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= n) return;
+    const uint32_t code = classes[id];
+    uint32_t nb[K];
+#pragma unroll
+    for (int i = 0; i < K; ++i) nb[i] = 0;
+#pragma unroll
+    for (int i = 0; i < K; ++i)
+#pragma unroll
+        for (int j = 0; j < K; ++j)
+            if (i != j && ((code >> (i * (K - 1) + j - (j > i ? 1 : 0))) & 1u)) {
+                nb[i] |= 1u << j;
+                nb[j] |= 1u << i;
+            }
+    const uint32_t all = (1u << K) - 1u;
+    uint32_t cores = 0;
+#pragma unroll
+    for (int y = 0; y < K; ++y)
+#pragma unroll
+        for (int z = y + 1; z < K; ++z) {
+            const uint32_t x = all & ~(1u << y) & ~(1u << z);
+            if (!(nb[y] & x) || !(nb[z] & x)) continue;
+            uint32_t reach = x & (0u - x);
+#pragma unroll
+            for (int it = 0; it < K - 3; ++it) {
+                uint32_t grow = 0;
+#pragma unroll
+                for (int i = 0; i < K; ++i)
+                    if ((reach >> i) & 1u) grow |= nb[i];
+                reach |= grow & x;
+            }
+            cores += reach == x ? 1u : 0u;
+        }
+    mult[id] = (uint8_t)cores;
+}
+
+static int launch_core_mult(int k, const uint32_t *classes, uint32_t n, uint8_t *mult,
+                            hipStream_t stream)
+{
+    const dim3 grid((n + 255) / 256), block(256);
+    switch (k) {
+    case 3: hipLaunchKernelGGL(core_mult_kernel<3>, grid, block, 0, stream, classes, n, mult); break;
+    case 4: hipLaunchKernelGGL(core_mult_kernel<4>, grid, block, 0, stream, classes, n, mult); break;
+    case 5: hipLaunchKernelGGL(core_mult_kernel<5>, grid, block, 0, stream, classes, n, mult); break;
+    case 6: hipLaunchKernelGGL(core_mult_kernel<6>, grid, block, 0, stream, classes, n, mult); break;
+    default: return fail(MK_ERANGE, "k=%d outside 3..6", k);
+    }
+    MK_HIP(hipGetLastError());
+    return MK_OK;
+}
+
 int build_table(Table *t, hipStream_t stream)
 {
     const int k = t->k;
@@ -274,6 +333,8 @@ int build_table(Table *t, hipStream_t stream)
     hipLaunchKernelGGL(assign_kernel, dim3((unsigned)ablocks), dim3(256), 0, stream, t->d_table,
                        repbits, rankbase, ncodes);
     TRYHIP(hipGetLastError());
+    TRYHIP(hipMalloc(&t->d_core_mult, (size_t)num));
+    TRY(launch_core_mult(k, t->d_classes, num, t->d_core_mult, stream));
     TRYHIP(hipEventRecord(e1, stream));
     t->classes.resize(num);
     TRYHIP(hipMemcpyAsync(t->classes.data(), t->d_classes, (size_t)num * sizeof(uint32_t),
@@ -312,6 +373,7 @@ extern "C" int mk_table_build(mk_ctx *ctx, int k, mk_table **out)
     if (rc != MK_OK) {
         if (t->d_table) (void)hipFree(t->d_table);
         if (t->d_classes) (void)hipFree(t->d_classes);
+        if (t->d_core_mult) (void)hipFree(t->d_core_mult);
         delete t;
         return rc;
     }
@@ -326,6 +388,7 @@ void free_table(Table *t)
     if (!t) return;
     if (t->d_table) (void)hipFree(t->d_table);
     if (t->d_classes) (void)hipFree(t->d_classes);
+    if (t->d_core_mult) (void)hipFree(t->d_core_mult);
     delete static_cast<mk_table *>(t);
 }
 }  // namespace mk
@@ -391,4 +454,19 @@ extern "C" int mk_table_lookup(const mk_table *t, uint32_t code, uint32_t *id)
     if (!table_ok(t) || !id) return fail(MK_EINVAL, "mk_table_lookup: bad argument");
     if (code >= t->entries) return fail(MK_ERANGE, "code %u >= 2^(k(k-1))", code);
     return mk_table_read(t, code, 1, id);
+}
+
+extern "C" int mk_table_core_mult(const mk_table *t, uint32_t first, uint32_t count, uint8_t *out)
+{
+    if (!table_ok(t) || (!out && count)) return fail(MK_EINVAL, "mk_table_core_mult: bad argument");
+    if (first > t->num_classes || count > t->num_classes - first)
+        return fail(MK_ERANGE, "classes [%u, +%u) outside the %u classes", first, count,
+                    t->num_classes);
+    if (count == 0) return MK_OK;
+    std::lock_guard<std::recursive_mutex> lock(t->ctx->mu);
+    MK_HIP(hipSetDevice(t->ctx->device));
+    MK_HIP(hipMemcpyAsync(out, t->d_core_mult + first, count, hipMemcpyDeviceToHost,
+                          t->ctx->stream));
+    MK_HIP(hipStreamSynchronize(t->ctx->stream));
+    return MK_OK;
 }

@@ -47,13 +47,16 @@ class MotifsError(RuntimeError):
 class BatchOpts(ctypes.Structure):
     _fields_ = [("split_threshold", ctypes.c_uint64), ("waves_per_cu", ctypes.c_int32),
                 ("use_graph", ctypes.c_int32), ("units_per_grab", ctypes.c_int32),
-                ("debug_flags", ctypes.c_int32)]
+                ("debug_flags", ctypes.c_int32), ("method", ctypes.c_int32)]
+
+
+METHOD_AUTO, METHOD_ESU, METHOD_CORES = 0, 1, 2
 
 
 class BatchStats(ctypes.Structure):
     _fields_ = [("units", ctypes.c_uint64), ("split_pairs", ctypes.c_uint64),
                 ("grid", ctypes.c_int32), ("lds_bytes", ctypes.c_int32),
-                ("k", ctypes.c_int32), ("ng", ctypes.c_int32)]
+                ("k", ctypes.c_int32), ("ng", ctypes.c_int32), ("method", ctypes.c_int32)]
 
 
 class ServerOpts(ctypes.Structure):
@@ -90,6 +93,7 @@ SIGNATURES = {
     "mk_table_class_codes": (ctypes.c_int, [_P, _P, _U32]),
     "mk_table_lookup": (ctypes.c_int, [_P, _U32, ctypes.POINTER(_U32)]),
     "mk_table_read": (ctypes.c_int, [_P, _U64, _U64, _P]),
+    "mk_table_core_mult": (ctypes.c_int, [_P, _U32, _U32, _P]),
     "mk_count": (ctypes.c_int, [_P, _P, _P, _P, ctypes.POINTER(_U64)]),
     "mk_count_batch": (ctypes.c_int, [_P, _P, _I32, _P, _P, _P]),
     "mk_batch_create": (ctypes.c_int, [_P, _P, _I32, _P, ctypes.POINTER(BatchOpts),
@@ -253,6 +257,13 @@ def mk_table_read(t: int, first: int, count: int) -> np.ndarray:
     return out
 
 
+def mk_table_core_mult(t: int, first: int, count: int) -> np.ndarray:
+    out = np.empty(count, dtype=np.uint8)
+    _check(library().mk_table_core_mult(t, first, count,
+                                        out.ctypes.data_as(_P) if count else None))
+    return out
+
+
 # -------------------------------------------------------------------- count
 
 def mk_count(ctx: int, g: int, t: int) -> Tuple[np.ndarray, int]:
@@ -280,8 +291,9 @@ def mk_count_batch(ctx: int, gs: Sequence[int], t: int) -> Tuple[np.ndarray, np.
 
 def mk_batch_create(ctx: int, gs: Sequence[int], t: int, split_threshold: int = 0,
                     waves_per_cu: int = 0, use_graph: int = 0, units_per_grab: int = 0,
-                    debug_flags: int = 0) -> int:
-    opts = BatchOpts(split_threshold, waves_per_cu, use_graph, units_per_grab, debug_flags)
+                    debug_flags: int = 0, method: int = 0) -> int:
+    opts = BatchOpts(split_threshold, waves_per_cu, use_graph, units_per_grab, debug_flags,
+                     method)
     h = _P()
     _check(library().mk_batch_create(ctx, _handles(gs), len(gs), t, ctypes.byref(opts),
                                      ctypes.byref(h)))
@@ -392,6 +404,11 @@ class Table:
 
     def read(self, first: int, count: int) -> np.ndarray:
         return mk_table_read(self.handle, first, count)
+
+    def core_mult(self, first: int = 0, count: int = -1) -> np.ndarray:
+        if count < 0:
+            count = self.num_classes - first
+        return mk_table_core_mult(self.handle, first, count)
 
 
 class Batch:

@@ -1,4 +1,4 @@
-"""GPU enumeration + lookup + histogram against the CPU oracle.
+"""GPU enumeration (ESU) + lookup + histogram against the CPU oracle.
 
 Small cases compare every class bit-exactly; closed-form graphs check the
 known counts; batched, split and replayed runs must equal the plain run.
@@ -19,20 +19,35 @@ pytestmark = pytest.mark.gpu
 
 
 def _count(ctx, g, k, **opts):
+    """H_k of one graph by the enumeration method (ESU)."""
+    opts.setdefault("method", M.METHOD_ESU)
     gr = ctx.load_graph(*g)
     t = ctx.table(k)
     try:
-        if opts:
-            b = ctx.batch([gr], t, **opts)
-            try:
-                b.run()
-                hist, totals = b.read()
-                return hist[0], int(totals[0])
-            finally:
-                b.free()
-        return ctx.count(gr, t)
+        b = ctx.batch([gr], t, **opts)
+        try:
+            b.run()
+            hist, totals = b.read()
+            assert b.stats()["method"] == opts["method"]
+            return hist[0], int(totals[0])
+        finally:
+            b.free()
     finally:
         gr.free()
+
+
+@pytest.mark.parametrize("k", [3, 4, 5, 6])
+def test_count_entry_point(ctx, k):
+    """mk_count (the library's method choice) equals the enumeration."""
+    rng = np.random.default_rng([900, k])
+    g = I.chung_lu_digraph(60, 200, 2.2, 20, 0.2, rng)
+    gr = ctx.load_graph(*g)
+    try:
+        hist, total = ctx.count(gr, ctx.table(k))
+    finally:
+        gr.free()
+    ref, ref_total = _count(ctx, g, k)
+    assert np.array_equal(hist, ref) and total == ref_total
 
 
 @pytest.mark.parametrize("k", [3, 4, 5, 6])
