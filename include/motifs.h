@@ -188,7 +188,9 @@ typedef struct mk_batch_opts {
                                  (0: about 1/16 of a wave's share, <= 16) */
     int32_t debug_flags;      /* tests only: 1 = every code straight to the
                                  histogram, 2 = flush the per-wave count hash
-                                 after every insert; results are the same */
+                                 after every insert, 4 = MK_METHOD_CORES
+                                 rescans every list instead of sharing a
+                                 parent's arc pairs; results are the same */
     int32_t method;           /* MK_METHOD_*: how H_k is counted (0: the
                                  library's choice); results are the same */
 } mk_batch_opts;

@@ -37,6 +37,7 @@ struct mk_batch {
     uint32_t unit_cap = 0;
     uint32_t *d_counters = nullptr;
     unsigned long long *d_hist_own = nullptr;
+    uint32_t *d_wave_scratch = nullptr;  // core method: per-workgroup arc lists
     unsigned long long *hist_last = nullptr;
 
     int max_n = 0, max_words = 0, seg_cap = 0;
@@ -117,7 +118,10 @@ extern "C" int mk_graph_footprint(const mk_graph *g, int k, uint64_t *bytes)
     const uint64_t slots = 8 * (uint64_t)g->nnz_u + 4 * ((uint64_t)g->nnz_u / 4096 + 2);
     const uint64_t units = 16 * (uint64_t)g->nnz_u * 4;  // planning estimate
     const uint64_t hist = 8ull * classes_for_k(k);
-    *bytes = ws + slots + units + hist + sizeof(DevGraph) + 4 * kNumCounters;
+    // per-workgroup arc lists of the core method (the default for k <= 5),
+    // one workgroup per unit at most
+    const uint64_t scratch = k <= 5 ? 4ull * kParentArcCap * std::min<uint64_t>(g->nnz_u + 1, 8192) : 0;
+    *bytes = ws + slots + units + hist + scratch + sizeof(DevGraph) + 4 * kNumCounters;
     return MK_OK;
 }
 
@@ -131,7 +135,7 @@ static void batch_release(mk_batch *b)
     if (b->graph) (void)hipGraphDestroy(b->graph);
     void *bufs[] = {b->d_graphs, b->d_ws, b->d_slot_cnt, b->d_slot_off, b->d_slot_est,
                     b->d_slot_vi, b->d_scan_tmp,
-                    b->d_units, b->d_counters, b->d_hist_own};
+                    b->d_units, b->d_counters, b->d_hist_own, b->d_wave_scratch};
     for (void *p : bufs)
         if (p) (void)hipFree(p);
 }
@@ -143,6 +147,7 @@ static EnumConfig enum_config(const mk_batch *b)
     c.seg_cap = b->seg_cap;
     c.flags = (uint32_t)b->opts.debug_flags;
     c.chunk = (uint32_t)std::max(b->opts.units_per_grab, 0);
+    c.wave_scratch = b->d_wave_scratch;
     return c;
 }
 
@@ -341,6 +346,8 @@ extern "C" int mk_batch_create(mk_ctx *ctx, const mk_graph *const *gs, int32_t n
     BAIL_HIP(hipMalloc(&b->d_units, sizeof(int4) * b->unit_cap));
 
     b->grid = (int)std::min<uint64_t>((uint64_t)b->max_grid, std::max<uint64_t>(b->units, 1));
+    if (b->method == MK_METHOD_CORES)
+        BAIL_HIP(hipMalloc(&b->d_wave_scratch, sizeof(uint32_t) * kParentArcCap * (size_t)b->grid));
 #undef BAIL_HIP
     *out = b;
     return MK_OK;
@@ -467,7 +474,8 @@ uint64_t batch_device_bytes(const mk_batch *b)
     }
     return 4 * words + 16ull * b->total_slots + 4 * scan_tmp_words(b->total_slots) +
            16ull * b->unit_cap + 8ull * b->ng * b->table->num_classes +
-           sizeof(DevGraph) * b->graphs.size() + 4 * kNumCounters;
+           sizeof(DevGraph) * b->graphs.size() + 4 * kNumCounters +
+           (b->d_wave_scratch ? 4ull * kParentArcCap * (uint64_t)b->grid : 0);
 }
 
 // typed adjacency + plan into the batch's own histogram buffer

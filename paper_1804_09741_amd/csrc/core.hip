@@ -65,6 +65,7 @@ struct CoreLds {
     uint8_t *pos;
     uint32_t *uid;
     uint32_t *agg;
+    uint32_t *ap;  // global: this workgroup's arc list of the current parent
 };
 
 __host__ __device__ inline int core_extra_bytes(int k)
@@ -146,6 +147,24 @@ __device__ __forceinline__ void uncount_codes(EnumState<K> &s, bool valid, uint3
     hash_insert<K>(s, valid && n > 0, code, 0u - n);
 }
 
+// Class id of a code for the class-keyed hash of the core kernel (cores
+// stand for many differently labelled k-sets, so their codes rarely repeat
+// while their classes do).  A code outside the connected classes is a
+// device error and is dropped.
+template <int K>
+__device__ __forceinline__ uint32_t class_of(EnumState<K> &s, bool &valid, uint32_t code)
+{
+    uint32_t id = 0;
+    if (valid) {
+        id = s.table[code];
+        if (id >= s.num_classes) {
+            atomicAdd(s.errors, 1u);
+            valid = false;
+        }
+    }
+    return id;
+}
+
 // Flat index a over the concatenated lists of the members: member d and
 // list position e.
 template <int R>
@@ -163,9 +182,115 @@ __device__ __forceinline__ int member_entry(const int (&pre)[R + 1], const int (
     return e;
 }
 
+// Flat scan over the vertices u taken from the lists of members
+// from..NM-1 (first-seen -- no mark bits of a lower member -- and not a
+// member): every entry of u's own list is handed to
+// arc(edge, u, v, mark u, mark v, arc type), edge = v has a mark, is not a
+// member, and keep(v, u, mark v).  Padding lanes get edge = false.
+template <int K, int NM, typename Keep, typename Arc>
+__device__ __forceinline__ void scan_taken(EnumState<K> &s, const CoreLds &c,
+                                           const int (&pre)[NM + 1], const int (&r0)[NM],
+                                           int from, Keep keep, Arc arc)
+{
+    constexpr uint32_t FLAG = kMemberFlag<K>;
+    const int lane = lane_id();
+    uint32_t *pre_deg = s.scratch, *start = s.scratch + kWave, *cw = s.scratch + 2 * kWave;
+    for (int base = pre[from]; base < pre[NM]; base += kWave) {
+        const int a = base + lane;
+        int deg = 0, row = 0, u = 0;
+        uint32_t mu = 0;
+        if (a < pre[NM]) {
+            int d;
+            const int e = member_entry<NM>(pre, r0, a, &d);
+            u = (int)(s.uadj[e] >> 2);
+            const uint32_t m = s.mark[u];
+            if (!(m & FLAG) && !(m & lower_members<K>(d))) {
+                row = s.urow[u];
+                deg = s.urow[u + 1] - row;
+                mu = m;
+            }
+        }
+        int incl = deg;
+#pragma unroll
+        for (int d = 1; d < kWave; d <<= 1) {
+            const int o = __shfl_up(incl, d, kWave);
+            if (lane >= d) incl += o;
+        }
+        const int tot = uniform(__shfl(incl, kWave - 1, kWave));
+        pre_deg[lane] = (uint32_t)incl;
+        start[lane] = (uint32_t)row;
+        cw[lane] = mu;
+        c.uid[lane] = (uint32_t)u;
+        __syncthreads();
+        for (int fb = 0; fb < tot; fb += kWave) {
+            const int f = fb + lane;
+            bool edge = false;
+            int uu = 0, v = 0;
+            uint32_t m_u = 0, mv = 0, t = 0;
+            if (f < tot) {
+                // first lane whose inclusive degree prefix exceeds f
+                int lo = 0;
+#pragma unroll
+                for (int step = kWave / 2; step > 0; step >>= 1)
+                    lo += ((int)pre_deg[lo + step - 1] <= f) ? step : 0;
+                const int before = lo ? (int)pre_deg[lo - 1] : 0;
+                const uint32_t ent = s.uadj[start[lo] + (uint32_t)(f - before)];
+                v = (int)(ent >> 2);
+                mv = s.mark[v];
+                uu = (int)c.uid[lo];
+                m_u = cw[lo];
+                t = ent & 3u;
+                edge = mv != 0u && !(mv & FLAG) && keep(v, uu, mv);
+            }
+            arc(edge, uu, v, m_u, mv, t);
+        }
+        __syncthreads();
+    }
+}
+
+// The arc pairs (u, v), u < v, inside adj(P) for the parent P = mem[0..NP-1]
+// (all pushed, nothing below): into c.ap as u | v << 13 | type << 26.
+// Returns their number, or -1 when they exceed kParentArcCap.
+template <int K, int NP>
+__device__ int parent_arcs(EnumState<K> &s, const CoreLds &c, const int (&mem)[K])
+{
+    constexpr uint32_t FLAG = kMemberFlag<K>;
+    const int lane = lane_id();
+#pragma unroll
+    for (int d = 0; d < NP; ++d)
+        if (lane == d) s.mark[mem[d]] = (MarkT<K>)(s.mark[mem[d]] | FLAG);
+    int r0[NP], pre[NP + 1];
+    pre[0] = 0;
+#pragma unroll
+    for (int d = 0; d < NP; ++d) {
+        r0[d] = uniform(s.urow[mem[d]]);
+        pre[d + 1] = pre[d] + uniform(s.urow[mem[d] + 1]) - r0[d];
+    }
+    __syncthreads();
+    int nap = 0;
+    scan_taken<K, NP>(
+        s, c, pre, r0, 0, [](int v, int u, uint32_t) { return v > u; },
+        [&](bool edge, int u, int v, uint32_t, uint32_t, uint32_t t) {
+            const unsigned long long bal = __ballot(edge);
+            const int at = nap + (int)lanes_below(bal);
+            if (edge && at < (int)kParentArcCap)
+                c.ap[at] = (uint32_t)u | ((uint32_t)v << 13) | (t << 26);
+            nap += __popcll(bal);
+        });
+#pragma unroll
+    for (int d = 0; d < NP; ++d)
+        if (lane == d) s.mark[mem[d]] = (MarkT<K>)(s.mark[mem[d]] & ~FLAG);
+    __syncthreads();
+    return nap > (int)kParentArcCap ? -1 : nap;
+}
+
 // one core X = mem[0..k-3] with internal code cx (all members pushed)
+// nap >= 0: c.ap holds the nap arc pairs inside adj(P), P = X less its last
+// member z, so only the vertices z brings have their lists scanned; nap < 0:
+// every taken vertex's list is scanned.
 template <int K>
-__device__ void core_node(EnumState<K> &s, const CoreLds &c, const int (&mem)[K], uint32_t cx)
+__device__ void core_node(EnumState<K> &s, const CoreLds &c, const int (&mem)[K], uint32_t cx,
+                          int nap)
 {
     constexpr int R = kCoreR<K>;
     constexpr uint32_t FLAG = kMemberFlag<K>;
@@ -219,72 +344,53 @@ __device__ void core_node(EnumState<K> &s, const CoreLds &c, const int (&mem)[K]
 
     // 2. arc pairs inside adj(X): into the table, or +1 with the arcs and -1
     // without straight into the hash
-    uint32_t *pre_deg = s.scratch, *start = s.scratch + kWave, *cw = s.scratch + 2 * kWave;
-    for (int base = 0; base < total; base += kWave) {
-        const int a = base + lane;
-        int deg = 0, row = 0, u = 0;
-        uint32_t key = 0;
-        if (a < total) {
-            int d;
-            const int e = member_entry<R>(pre, r0, a, &d);
-            u = (int)(s.uadj[e] >> 2);
-            const uint32_t m = s.mark[u];
-            if (!(m & FLAG) && !(m & lower_members<K>(d))) {
-                row = s.urow[u];
-                deg = s.urow[u + 1] - row;
-                key = agg ? (uint32_t)c.pos[cell_of<K>(m)] : code_bits<K>(m, K - 2);
-            }
-        }
-        int incl = deg;
-#pragma unroll
-        for (int d = 1; d < kWave; d <<= 1) {
-            const int o = __shfl_up(incl, d, kWave);
-            if (lane >= d) incl += o;
-        }
-        const int tot = uniform(__shfl(incl, kWave - 1, kWave));
-        pre_deg[lane] = (uint32_t)incl;
-        start[lane] = (uint32_t)row;
-        cw[lane] = key;
-        c.uid[lane] = (uint32_t)u;
-        __syncthreads();
-        for (int fb = 0; fb < tot; fb += kWave) {
-            const int f = fb + lane;
-            bool edge = false;
-            uint32_t mv = 0, t = 0, ukey = 0;
-            if (f < tot) {
-                // first lane whose inclusive degree prefix exceeds f
-                int lo = 0;
-#pragma unroll
-                for (int step = kWave / 2; step > 0; step >>= 1)
-                    lo += ((int)pre_deg[lo + step - 1] <= f) ? step : 0;
-                const int before = lo ? (int)pre_deg[lo - 1] : 0;
-                const uint32_t ent = s.uadj[start[lo] + (uint32_t)(f - before)];
-                const int v = (int)(ent >> 2);
-                mv = s.mark[v];
-                edge = mv != 0u && !(mv & FLAG) && v > (int)c.uid[lo];
-                t = ent & 3u;
-                ukey = cw[lo];
-            }
-            if (agg) {
-                if (edge) {
-                    uint32_t ia = ukey, ib = c.pos[cell_of<K>(mv)];
-                    if (ia > ib) {
-                        const uint32_t x = ia;
-                        ia = ib;
-                        ib = x;
-                        t = ((t & 1u) << 1) | (t >> 1);
-                    }
-                    atomicAdd(&c.agg[3u * (ib * (ib + 1u) / 2u + ia) + t - 1u], 1u);
+    auto arc = [&](bool edge, int, int, uint32_t mu, uint32_t mv, uint32_t t) {
+        if (agg) {
+            if (edge) {
+                uint32_t ia = c.pos[cell_of<K>(mu)], ib = c.pos[cell_of<K>(mv)];
+                if (ia > ib) {
+                    const uint32_t x = ia;
+                    ia = ib;
+                    ib = x;
+                    t = ((t & 1u) << 1) | (t >> 1);
                 }
-            } else {
-                const uint32_t cm = cx | ukey | code_bits<K>(mv, K - 1);
-                const uint32_t ct = cm | ((t & 1u) << B_YZ) | ((t >> 1) << B_ZY);
-                if (s.hpending >= kPendingMax - 2u * kWave) flush_hash<K>(s);
-                count_codes<K>(s, edge, ct);
-                uncount_codes<K>(s, edge, cm);
+                atomicAdd(&c.agg[3u * (ib * (ib + 1u) / 2u + ia) + t - 1u], 1u);
             }
+        } else {
+            const uint32_t cm = cx | code_bits<K>(mu, K - 2) | code_bits<K>(mv, K - 1);
+            const uint32_t ct = cm | ((t & 1u) << B_YZ) | ((t >> 1) << B_ZY);
+            bool et = edge, em = edge;
+            const uint32_t it = class_of<K>(s, et, ct), im = class_of<K>(s, em, cm);
+            if (s.hpending >= kPendingMax - 2u * kWave) flush_hash<K>(s);
+            count_codes<K>(s, et, it);
+            uncount_codes<K>(s, em, im);
         }
-        __syncthreads();
+    };
+    if (nap >= 0) {
+        // the parent's arc pairs, less those at z
+        const int z = mem[R - 1];
+        for (int ib = 0; ib < nap; ib += kWave) {
+            const int i = ib + lane;
+            bool edge = false;
+            uint32_t mu = 0, mv = 0, t = 0;
+            if (i < nap) {
+                const uint32_t ent = c.ap[i];
+                const int u = (int)(ent & 0x1FFFu), v = (int)((ent >> 13) & 0x1FFFu);
+                t = ent >> 26;
+                edge = u != z && v != z;
+                mu = s.mark[u];
+                mv = s.mark[v];
+            }
+            arc(edge, 0, 0, mu, mv, t);
+        }
+        // arcs at the vertices z brings (no mark bits of P): to any vertex
+        // of adj(P), or to another new one above them
+        const uint32_t of_p = lower_members<K>(R - 1);
+        scan_taken<K, R>(
+            s, c, pre, r0, R - 1,
+            [of_p](int v, int u, uint32_t mv) { return (mv & of_p) != 0u || v > u; }, arc);
+    } else {
+        scan_taken<K, R>(s, c, pre, r0, 0, [](int v, int u, uint32_t) { return v > u; }, arc);
     }
 
     // 3. pairs of cells (Y <= Z): C(|Y|,2) or |Y||Z| k-sets of motif(X, Y, Z),
@@ -315,11 +421,15 @@ __device__ void core_node(EnumState<K> &s, const CoreLds &c, const int (&mem)[K]
                    code_bits<K>(mark_of_cell<K>(cz), K - 1);
             valid = w > 0;
         }
-        hash_insert<K>(s, valid, code, w);
+        hash_insert<K>(s, valid, class_of<K>(s, valid, code), w);
         if (agg && __ballot(e1 | e2 | e3)) {
-            hash_insert<K>(s, e1 > 0, code | (1u << B_YZ), e1);
-            hash_insert<K>(s, e2 > 0, code | (1u << B_ZY), e2);
-            hash_insert<K>(s, e3 > 0, code | (1u << B_YZ) | (1u << B_ZY), e3);
+            bool v1 = e1 > 0, v2 = e2 > 0, v3 = e3 > 0;
+            const uint32_t i1 = class_of<K>(s, v1, code | (1u << B_YZ));
+            const uint32_t i2 = class_of<K>(s, v2, code | (1u << B_ZY));
+            const uint32_t i3 = class_of<K>(s, v3, code | (1u << B_YZ) | (1u << B_ZY));
+            hash_insert<K>(s, v1, i1, e1);
+            hash_insert<K>(s, v2, i2, e2);
+            hash_insert<K>(s, v3, i3, e3);
         }
     }
 
@@ -345,6 +455,11 @@ __device__ void visit_core(EnumState<K> &s, const CoreLds &c, const int (&st)[K 
         total += rem[q];
     }
     const int hi = total < jhi ? total : jhi;
+    // a parent of cores (k >= 5): its arc list, shared by the children
+    int nap = -1;
+    if constexpr (D + 1 == K - 3) {
+        if (jlo < hi && c.ap && !(s.flags & kDebugNoShare)) nap = parent_arcs<K, D + 1>(s, c, mem);
+    }
     for (int j = jlo; j < hi; ++j) {
         int a = j, L = 0, o = 0;
         bool found = false;
@@ -365,7 +480,7 @@ __device__ void visit_core(EnumState<K> &s, const CoreLds &c, const int (&st)[K 
         mem[D + 1] = x;
         if constexpr (D + 1 == K - 3) {
             push_marks<K, D + 1>(s, x);
-            core_node<K>(s, c, mem, ccode);
+            core_node<K>(s, c, mem, ccode, nap);
             pop<K, D + 1>(s, x);
         } else {
             push<K, D + 1>(s, x);
@@ -391,7 +506,7 @@ __device__ void run_core_unit(EnumState<K> &s, const CoreLds &c, int v, int i, u
     s.root = v;
     if constexpr (K == 3) {
         push_marks<K, 0>(s, v);
-        core_node<K>(s, c, mem, 0u);
+        core_node<K>(s, c, mem, 0u, -1);
         pop<K, 0>(s, v);
     } else {
         push<K, 0>(s, v);
@@ -401,7 +516,7 @@ __device__ void run_core_unit(EnumState<K> &s, const CoreLds &c, int v, int i, u
             mem[1] = x;
             if constexpr (K == 4) {
                 push_marks<K, 1>(s, x);
-                core_node<K>(s, c, mem, code);
+                core_node<K>(s, c, mem, code, -1);
                 pop<K, 1>(s, x);
             } else {
                 push<K, 1>(s, x);
@@ -439,9 +554,11 @@ __global__ __launch_bounds__(kWave) void core_kernel(const DevGraph *graphs, con
     c.pos = c.list + ((kCells<K> + 3) & ~3);
     c.uid = reinterpret_cast<uint32_t *>(c.pos + ((kCells<K> + 3) & ~3));
     c.agg = c.uid + kWave;
+    c.ap = cfg.wave_scratch ? cfg.wave_scratch + (size_t)blockIdx.x * kParentArcCap : nullptr;
     for (int i = lane_id(); i < kCells<K>; i += kWave) c.cnt[i] = 0u;
     for (int i = lane_id(); i < kAggWords<K>; i += kWave) c.agg[i] = 0u;
     init_state<K>(s, base, lay, cfg, counters, table, num_classes);
+    s.class_keys = true;
     for_each_unit<K>(s, graphs, units, unit_cap, unit_end, counters, hist_base, cfg,
                      [&](int v, int i, uint32_t range) { run_core_unit<K>(s, c, v, i, range); });
 }

@@ -125,6 +125,7 @@ struct EnumState {
     uint32_t *hcnt;             //   and its pending count
     int hused;                  // keys in the hash (wave-uniform)
     uint32_t hpending;          // subgraphs pending in the hash (wave-uniform)
+    bool class_keys;            // hash keys are class ids, not codes
     uint32_t flags;             // kDebug* bits
     unsigned long long *hist;
     const uint32_t *table;
@@ -205,7 +206,7 @@ __device__ __forceinline__ void pop(EnumState<K> &s, int x)
 template <int K>
 __device__ __forceinline__ void add_global(EnumState<K> &s, uint32_t code, uint32_t n)
 {
-    const uint32_t id = s.table[code];
+    const uint32_t id = s.class_keys ? code : s.table[code];
     // n is a 32-bit two's complement count (negative only in the (k-2)-set
     // counting); sign-extended, the 64-bit sums stay exact modulo 2^64
     if (id < s.num_classes) atomicAdd(&s.hist[id], (unsigned long long)(long long)(int32_t)n);
@@ -304,6 +305,7 @@ __device__ __forceinline__ void init_state(EnumState<K> &s, char *base, const Ld
     s.hcnt = s.hkey + kHashSlots;
     s.hused = 0;
     s.hpending = 0;
+    s.class_keys = false;
     for (int i = lane_id(); i < kHashSlots; i += kWave) {
         s.hkey[i] = kEmpty;
         s.hcnt[i] = 0u;

@@ -144,9 +144,14 @@ struct EnumConfig {
     int seg_cap;     // largest undirected degree (LDS extension segments)
     uint32_t flags;  // kDebug* bits below (tests only; 0 in production)
     uint32_t chunk;  // units per queue grab; 0 = about 1/16 of a wave's share
+    uint32_t *wave_scratch;  // core kernel: kParentArcCap words per workgroup
 };
 constexpr uint32_t kDebugNoHash = 1u;      // every code straight to the histogram
 constexpr uint32_t kDebugFlushAlways = 2u; // flush the hash after every insert
+constexpr uint32_t kDebugNoShare = 4u;     // core kernel: no per-parent arc lists
+// Arc pairs inside adj(P) kept per parent node P by the core kernel (global
+// memory, one list per workgroup); a parent with more uses the per-core scan.
+constexpr uint32_t kParentArcCap = 2048;
 // The units [counters[kSliceBegin], min(counters[kNumUnits], unit_cap,
 // unit_end)) are cut into kQueues equal ranges; wave w starts on range
 // w % kQueues (the XCD the wave runs on) and then helps the others.  Heads

@@ -107,7 +107,8 @@ def test_cores_hub_and_counting_paths(ctx, k):
     rng = np.random.default_rng([5300, k])
     g = I.chung_lu_digraph(300, 1000, 2.1, 60 if k < 6 else 20, 0.15, rng)
     ref, _ = _count(ctx, g, k, method=M.METHOD_ESU)
-    for opts in ({}, {"debug_flags": 1}, {"debug_flags": 2}, {"units_per_grab": 1},
+    for opts in ({}, {"debug_flags": 1}, {"debug_flags": 2}, {"debug_flags": 4},
+                 {"units_per_grab": 1},
                  {"split_threshold": 1, "units_per_grab": 3},
                  {"split_threshold": 1 << 40, "waves_per_cu": 1}):
         h, _ = _count(ctx, g, k, **opts)
@@ -128,6 +129,16 @@ def test_cores_hub_star(ctx, k):
     h1, _ = _count(ctx, g, k)
     h2, _ = _count(ctx, g, k, method=M.METHOD_ESU)
     assert np.array_equal(h1, h2)
+
+
+@pytest.mark.parametrize("k", [5, 6])
+def test_cores_dense_parent_overflows_arc_list(ctx, k):
+    """K_70: a parent's adj(P) holds over 2,048 arc pairs, so the cores fall
+    back to scanning every vertex's list; the count is still C(70, k)."""
+    t = ctx.table(k)
+    hist, total = _count(ctx, I.complete_digraph(70), k)
+    assert total == math.comb(70, k)
+    assert hist[t.lookup((1 << (k * (k - 1))) - 1)] == total
 
 
 def _batch(ctx, graphs, t, **opts):
