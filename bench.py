@@ -32,7 +32,8 @@ HBM_PEAK_GBS = 8000.0
 BYTES_PER_SUBGRAPH = 4 + 8 + 8
 ROOT = os.path.dirname(os.path.abspath(__file__))
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "enum_kernel_hbm_traffic.json")
-KERNEL_SOURCES = ("paper_1804_09741_amd/csrc/enum.hip", "paper_1804_09741_amd/csrc/internal.h")
+KERNEL_SOURCES = ("paper_1804_09741_amd/csrc/enum.hip", "paper_1804_09741_amd/csrc/core.hip",
+                  "paper_1804_09741_amd/csrc/esu.h", "paper_1804_09741_amd/csrc/internal.h")
 
 
 def _measured_traffic(kernel):
@@ -52,6 +53,11 @@ def _measured_traffic(kernel):
         return rec["kernels"][kernel]["traffic_bytes"]
     except (OSError, KeyError, ValueError):
         return None
+
+
+def _kernel_name(k, stats):
+    """The counting kernel a batch ran (its stats name the method)."""
+    return ("core_kernel<%d>" if stats.get("method") == 2 else "enum_kernel<%d>") % k
 
 
 def _log(msg):
@@ -289,8 +295,8 @@ def main():
                    "subgraphs_per_step": subgraphs},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": _measured_traffic("enum_kernel<6>"),
-                     "kernel": "enum_kernel<6>", "kernel_ms": enum_ms,
+                     "traffic": _measured_traffic(_kernel_name(6, r["stats"])),
+                     "kernel": _kernel_name(6, r["stats"]), "kernel_ms": enum_ms,
                      "bytes_per_subgraph": BYTES_PER_SUBGRAPH},
         "pass_ms": float(np.mean(r["pass_ms"])),
         "batch_stats": r["stats"],
@@ -340,6 +346,8 @@ def main():
         k5 = {"workload": w5.name, "value": s5 / (r5["wall_s"] / max(2, args.steps // 3)),
               "subgraphs_per_step": s5, "kernel_ms": float(np.mean(r5["enum_ms"])),
               "pass_ms": float(np.mean(r5["pass_ms"])), "table_build_ms": t5.build_ms,
+              "kernel": _kernel_name(5, r5["stats"]),
+              "traffic": _measured_traffic(_kernel_name(5, r5["stats"])),
               "batch_stats": r5["stats"]}
         if not args.no_plain:
             p5 = _plain(ctx, g5, t5, 1, torch, **({"method": method} if method else {}))

@@ -28,7 +28,8 @@ import re
 from collections import defaultdict
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-KERNEL_SOURCES = ("paper_1804_09741_amd/csrc/enum.hip", "paper_1804_09741_amd/csrc/internal.h")
+KERNEL_SOURCES = ("paper_1804_09741_amd/csrc/enum.hip", "paper_1804_09741_amd/csrc/core.hip",
+                  "paper_1804_09741_amd/csrc/esu.h", "paper_1804_09741_amd/csrc/internal.h")
 COPY_KERNEL = "__amd_rocclr_copyBuffer"
 
 
@@ -93,7 +94,7 @@ def counter_means(dirs, copy_bytes):
             if copies:
                 acc[COPY_KERNEL + " (%d MiB)" % (copy_bytes >> 20)][cname].append(max(copies))
             for disp, v in vals.items():
-                if names[disp].startswith("enum_kernel"):
+                if names[disp].startswith(("enum_kernel", "core_kernel")):
                     acc[names[disp]][cname].append(v)
     means = {k: {c: sum(v) / len(v) for c, v in cs.items()} for k, cs in acc.items()}
     counts = {k: max(len(v) for v in cs.values()) for k, cs in acc.items()}
@@ -129,7 +130,7 @@ def main(argv=None):
         lines = ["# " + a.title, "",
                  "Command (from /tmp with TMPDIR=/tmp; $R is the repository root):", "",
                  "```", a.command, "```", "",
-                 "Kernel sources (enum.hip + internal.h) sha256[:16] = `%s`." % source_hash(),
+                 "Kernel sources (enum.hip, core.hip, esu.h, internal.h) sha256[:16] = `%s`." % source_hash(),
                  "Durations in microseconds.", ""]
         lines += stats_table(a.dir)
         if a.note:
@@ -145,11 +146,15 @@ def main(argv=None):
     fetch_scale = copy_bytes / (cal["FETCH_SIZE"] * 1024.0)
     write_scale = copy_bytes / (cal["WRITE_SIZE"] * 1024.0)
     bench = _bench_record(a.bench_log)
-    per_launch = {"enum_kernel<6>": (bench["config"]["workload"],
-                                     bench["config"]["subgraphs_per_step"])}
+    def kernel(k, stats):
+        # the method the batch ran: 1 enumeration, 2 counting from (k-2)-sets
+        return ("core_kernel<%d>" if stats.get("method") == 2 else "enum_kernel<%d>") % k
+
+    per_launch = {kernel(6, bench["batch_stats"]): (bench["config"]["workload"],
+                                                   bench["config"]["subgraphs_per_step"])}
     if "k5_batch" in bench:
-        per_launch["enum_kernel<5>"] = (bench["k5_batch"]["workload"],
-                                        bench["k5_batch"]["subgraphs_per_step"])
+        per_launch[kernel(5, bench["k5_batch"]["batch_stats"])] = (
+            bench["k5_batch"]["workload"], bench["k5_batch"]["subgraphs_per_step"])
     bps = bench["roofline"]["bytes_per_subgraph"]
     rec = {"source_sha256_16": source_hash(), "sources": list(KERNEL_SOURCES),
            "calibration": {"kernel": COPY_KERNEL + " (torch copy_ of %d MiB)" % a.copy_mib,
@@ -169,12 +174,12 @@ def main(argv=None):
         json.dump(rec, f, indent=1)
         f.write("\n")
 
-    kerns = sorted(k for k in means if k.startswith("enum_kernel")) + [copy_key]
+    kerns = sorted(k for k in means if k.startswith(("enum_kernel", "core_kernel"))) + [copy_key]
     lines = ["# " + a.title, "",
              "One rocprofv3 `--pmc` run per counter set, from /tmp with TMPDIR=/tmp; "
              "$R is the repository root:", "", "```"] + a.command + [
              "```", "",
-             "Kernel sources (enum.hip + internal.h) sha256[:16] = `%s`." % rec["source_sha256_16"],
+             "Kernel sources (enum.hip, core.hip, esu.h, internal.h) sha256[:16] = `%s`." % rec["source_sha256_16"],
              "Mean per dispatch over %s." % ", ".join(
                  "%s: %d dispatches" % (k, counts[k]) for k in kerns[:-1]), "",
              "| counter | " + " | ".join(kerns) + " |",
