@@ -450,3 +450,75 @@ done:
     free(bits);
     return result;
 }
+
+/* ------------------------------------------------------------------------
+ * Ensemble of random graphs (Section 1, step (a); the paper does not fix the
+ * null model).  Reading: degree-preserving directed switches.  Graph r of an
+ * ensemble with seed s draws from the SplitMix64 stream whose seed is output
+ * r of SplitMix64(s); each attempt t takes outputs 2t and 2t+1 of that
+ * stream, maps each to an arc index in [0, m) by the high 32 bits times m,
+ * and with arcs a -> b and c -> d:
+ *   rejects it when a = c or b = d (nothing would change), when a = d or
+ *   c = b (a loop), or when a -> d or c -> b already exists (a duplicate);
+ *   otherwise replaces the two arcs by a -> d and c -> b (each arc keeps its
+ *   position in the CSR, so every out- and in-degree is kept).
+ * Attempts go on until `target` switches are accepted or `max_attempts`
+ * attempts are made.
+ * ------------------------------------------------------------------------ */
+
+/* SplitMix64 (Steele, Lea and Flood, OOPSLA 2014): output i (i = 0, 1, ...)
+ * of seed s is the mixing function applied to s + (i + 1) * 0x9E3779B97F4A7C15. */
+uint64_t oracle_splitmix64(uint64_t seed, uint64_t i)
+{
+    uint64_t z = seed + (i + 1) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+static uint32_t arc_index(uint64_t r, int64_t m)
+{
+    return (uint32_t)(((r >> 32) * (uint64_t)m) >> 32);
+}
+
+/* Graph r of the ensemble of (n, row_ptr, col) with seed `seed`: its arc
+ * heads into out_col (m entries, same row_ptr).  Returns the number of
+ * accepted switches, or a negative error code. */
+int64_t oracle_switch_chain(int n, const int32_t *row_ptr, const int32_t *col, uint64_t seed,
+                            uint64_t r, uint64_t target, uint64_t max_attempts, int32_t *out_col)
+{
+    int rc = check_graph(n, row_ptr, col);
+    if (rc != OR_OK) return rc;
+    const int64_t m = row_ptr[n];
+    if (m > 0 && !out_col) return OR_EINVAL;
+    int32_t *src = (int32_t *)malloc(sizeof(int32_t) * (size_t)(m + 1));
+    size_t nbits = (size_t)n * (size_t)n;
+    unsigned char *arc = (unsigned char *)calloc(nbits + 1, 1);
+    if (!src || !arc) { free(src); free(arc); return OR_ENOMEM; }
+    for (int u = 0; u < n; ++u)
+        for (int32_t t = row_ptr[u]; t < row_ptr[u + 1]; ++t) {
+            src[t] = u;
+            out_col[t] = col[t];
+            arc[(size_t)u * n + col[t]] = 1;
+        }
+    const uint64_t stream = oracle_splitmix64(seed, r);
+    uint64_t accepted = 0;
+    for (uint64_t t = 0; m > 0 && accepted < target && t < max_attempts; ++t) {
+        uint32_t i = arc_index(oracle_splitmix64(stream, 2 * t), m);
+        uint32_t j = arc_index(oracle_splitmix64(stream, 2 * t + 1), m);
+        int a = src[i], b = out_col[i], c = src[j], d = out_col[j];
+        if (a == c || b == d) continue;
+        if (a == d || c == b) continue;
+        if (arc[(size_t)a * n + d] || arc[(size_t)c * n + b]) continue;
+        arc[(size_t)a * n + b] = 0;
+        arc[(size_t)c * n + d] = 0;
+        arc[(size_t)a * n + d] = 1;
+        arc[(size_t)c * n + b] = 1;
+        out_col[i] = d;
+        out_col[j] = b;
+        ++accepted;
+    }
+    free(src);
+    free(arc);
+    return (int64_t)accepted;
+}

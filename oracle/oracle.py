@@ -52,6 +52,12 @@ def load_library(path: str):
     lib.oracle_canon_table.argtypes = [ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]
     lib.oracle_core_mult.restype = ctypes.c_int
     lib.oracle_core_mult.argtypes = [ctypes.c_int, ctypes.c_uint32]
+    lib.oracle_splitmix64.restype = ctypes.c_uint64
+    lib.oracle_splitmix64.argtypes = [ctypes.c_uint64, ctypes.c_uint64]
+    lib.oracle_switch_chain.restype = ctypes.c_int64
+    lib.oracle_switch_chain.argtypes = [ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
+                                        ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64,
+                                        ctypes.c_uint64, ctypes.c_void_p]
     lib.oracle_count.restype = ctypes.c_int64
     lib.oracle_count.argtypes = [ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
                                  ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
@@ -167,6 +173,52 @@ def core_mult_table(k: int) -> np.ndarray:
     out = np.array([core_mult(k, int(c)) for c in class_codes(k)], dtype=np.uint8)
     out.setflags(write=False)
     return out
+
+
+# --------------------------------------------------------------------------
+# ensemble of random graphs and significance (Section 1, steps (a) and (c))
+# --------------------------------------------------------------------------
+
+def splitmix64(seed: int, i: int) -> int:
+    """Output i of SplitMix64 seeded with `seed` (see oracle.c)."""
+    return int(_lib().oracle_splitmix64(seed & (2**64 - 1), i))
+
+
+def switch_chain(row_ptr, col, seed: int, r: int, target: int, max_attempts: int):
+    """(new col, accepted): graph r of the ensemble with this seed (oracle.c
+    states the switch rule).  row_ptr is unchanged."""
+    row_ptr = np.ascontiguousarray(row_ptr, dtype=np.int32)
+    col = np.ascontiguousarray(col, dtype=np.int32)
+    out = np.empty(max(len(col), 1), dtype=np.int32)
+    acc = _lib().oracle_switch_chain(len(row_ptr) - 1, row_ptr.ctypes.data,
+                                     col.ctypes.data if len(col) else None, seed, r, target,
+                                     max_attempts, out.ctypes.data)
+    if acc < 0:
+        raise OracleError(int(acc))
+    return out[:len(col)], int(acc)
+
+
+def significance(hist) -> np.ndarray:
+    """(mean, std, z) per class, float64, of an ensemble's histograms: row 0
+    is the original graph, rows 1..R its random graphs (R >= 2).  mean and
+    the sample standard deviation (divisor R - 1) are over the random graphs;
+    z = (H_0 - mean) / std, with z = 0 where std = 0 and H_0 = mean and an
+    infinity of H_0 - mean's sign where std = 0 otherwise (Section 1, step
+    (c); the paper names no statistic, this is the usual z-score)."""
+    h = np.asarray(hist, dtype=np.uint64)
+    if h.ndim != 2 or h.shape[0] < 3:
+        raise ValueError("need the original and at least two random graphs")
+    rnd = h[1:].astype(np.float64)
+    mean = rnd.sum(axis=0) / rnd.shape[0]
+    var = ((rnd - mean) ** 2).sum(axis=0) / (rnd.shape[0] - 1)
+    std = np.sqrt(var)
+    diff = h[0].astype(np.float64) - mean
+    z = np.zeros_like(mean)
+    pos = std > 0
+    z[pos] = diff[pos] / std[pos]
+    z[~pos & (diff > 0)] = np.inf
+    z[~pos & (diff < 0)] = -np.inf
+    return np.stack([mean, std, z])
 
 
 # --------------------------------------------------------------------------

@@ -46,6 +46,12 @@ MUTANTS = {
         "for (int z = y + 1; z < k; ++z) {", "for (int z = 0; z < k; ++z) if (z != y) {"),
     "core touch follows out-arcs only": (
         "if (a[y][x[i]] || a[x[i]][y]) y_touches = 1;", "if (a[y][x[i]]) y_touches = 1;"),
+    "switch allows loops": (
+        "        if (a == d || c == b) continue;\n", ""),
+    "switch skips the duplicate test": (
+        "if (arc[(size_t)a * n + d] || arc[(size_t)c * n + b]) continue;", "if (0) continue;"),
+    "generator mixing constant off by one": (
+        "0xBF58476D1CE4E5B9ull", "0xBF58476D1CE4E5B8ull"),
     "child extension keeps the chosen vertex": (
         "for (int j = i + 1; j < next; ++j) child[cn++] = ext[j];",
         "for (int j = i; j < next; ++j) child[cn++] = ext[j];"),
@@ -133,6 +139,19 @@ def _failed_pins(lib):
                 failed.append("core raw sums k=%d" % k)
     except O.OracleError:
         failed.append("core error")
+    # ensemble: the generator's published values; switches keep the graph simple
+    if [lib.oracle_splitmix64(0, i) for i in range(3)] != [
+            0xe220a8397b1dcdaf, 0x6e789e6aa1b965f4, 0x06c45d188009454f]:
+        failed.append("splitmix64 values")
+    rp, col = I.chung_lu_digraph(30, 90, 2.2, 10, 0.2, np.random.default_rng(57))
+    rp = np.ascontiguousarray(rp, dtype=np.int32)
+    col = np.ascontiguousarray(col, dtype=np.int32)
+    out = np.empty(len(col), dtype=np.int32)
+    acc = lib.oracle_switch_chain(30, rp.ctypes.data, col.ctypes.data, 3, 0, 20 * len(col),
+                                  200 * len(col), out.ctypes.data)
+    arcs = {(u, int(out[t])) for u in range(30) for t in range(rp[u], rp[u + 1])}
+    if acc < 0 or len(arcs) != len(col) or any(u == v for u, v in arcs):
+        failed.append("switch simplicity")
     return failed
 
 
