@@ -88,6 +88,8 @@ def _parse():
                         "known traffic, to scale hardware byte counters)")
     p.add_argument("--no-methods", action="store_true",
                    help="skip timing both counting methods on the k=6 and k=5 batches")
+    p.add_argument("--no-ensemble", action="store_true",
+                   help="skip the ensemble pipeline (random graphs, counts, z-scores)")
     p.add_argument("--serve", type=int, default=0, metavar="R",
                    help="also run the serving workload with R requests (0: skip)")
     p.add_argument("--serve-load", type=float, default=0.7,
@@ -162,6 +164,46 @@ def _methods(ctx, M, I, torch):
         res["k%d" % k] = row
         for g in gs:
             g.free()
+    return res
+
+
+def _ensemble(ctx, M, I, torch, cpu=True, R=100, spa=10, seed=2024):
+    """The whole significance pipeline on the device for the k=5 original:
+    R degree-preserving random graphs (spa * m accepted switches each),
+    H_5 of all R + 1 graphs in one batch, z-scores of every class."""
+    import numpy as np
+    rp, col = I.k5_batch_graph(0)
+    g = ctx.load_graph(rp, col)
+    t = ctx.table(5)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    made, acc = ctx.randomise(g, R, seed, spa)
+    t1 = time.perf_counter()
+    b = ctx.batch([g] + made, t)
+    d_hist = torch.zeros((R + 1, t.num_classes), dtype=torch.int64, device="cuda:0")
+    d_out = torch.zeros((3, t.num_classes), dtype=torch.float64, device="cuda:0")
+    stream = torch.cuda.current_stream()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    b.run(d_hist, stream)
+    ctx.significance(d_hist, t.num_classes, d_out, stream)
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    z = d_out[2].cpu().numpy()
+    subgraphs = int(d_hist.sum().item())
+    res = {"random_graphs": R, "switches_per_arc": spa, "accepted_min": int(acc.min()),
+           "randomise_ms": 1000 * (t1 - t0), "count_and_z_ms": 1000 * (t3 - t2),
+           "subgraphs": subgraphs, "classes_z_above_2": int(np.sum(np.isfinite(z) & (z > 2)))}
+    if cpu:
+        from oracle import oracle as O
+        c0 = time.perf_counter()
+        O.switch_chain(rp, col, seed, 0, spa * len(col), 8 * spa * len(col) + 1024)
+        res["cpu_oracle_randomise_ms_per_graph"] = 1000 * (time.perf_counter() - c0)
+    _log("ensemble: %d random graphs in %.1f ms, counts + z-scores %.1f ms" % (
+        R, res["randomise_ms"], res["count_and_z_ms"]))
+    b.free()
+    for h in made + [g]:
+        h.free()
     return res
 
 
@@ -358,6 +400,8 @@ def main():
             g.free()
     if not args.no_methods:
         out["methods"] = _methods(ctx, M, I, torch)
+    if not args.no_ensemble:
+        out["ensemble"] = _ensemble(ctx, M, I, torch, cpu=not args.no_cpu_baseline)
     if args.serve:
         out["serving"] = _serving(ctx, M, I, args.serve, args.serve_load, torch)
     ctx.close()

@@ -117,6 +117,40 @@ int mk_graph_footprint(const mk_graph *g, int k, uint64_t *bytes);
 
 void mk_graph_free(mk_graph *g);
 
+/* Copy a graph's out-adjacency CSR back to host memory: row_ptr (n+1) and
+   col (m), either may be NULL.  Blocks. */
+int mk_graph_read(const mk_graph *g, int32_t *row_ptr, int32_t *col);
+
+/* ------------------------------------------------------- random ensembles */
+
+/* The ensemble of random graphs of Section 1 (subgraph counts of a graph are
+   compared with those of random graphs; the paper does not fix the model).
+   Makes `count` degree-preserving random versions of g on the device, each
+   by directed switches: arcs a -> b and c -> d become a -> d and c -> b
+   unless a = c, b = d, a = d, c = b or a -> d or c -> b exists.  Graph r
+   draws its arc pairs from SplitMix64 (Steele, Lea and Flood, 2014) seeded
+   with output r of SplitMix64(seed): attempt t uses outputs 2t and 2t+1,
+   each mapped to an arc index as (high 32 bits * m) >> 32.  A graph stops
+   after switches_per_arc * m accepted switches or 8 * that + 1024 attempts;
+   accepted (may be NULL) receives each graph's accepted count.  Every arc
+   keeps its CSR position, so out- and in-degrees are kept exactly.  out
+   receives `count` new graphs (free each with mk_graph_free); on error none
+   is left.  MK_ERANGE if a random graph's undirected degree exceeds
+   MK_MAX_DEGREE.  Blocks until the graphs are ready. */
+int mk_randomise(mk_ctx *ctx, const mk_graph *g, int32_t count, uint64_t seed,
+                 uint32_t switches_per_arc, mk_graph **out, uint64_t *accepted);
+
+/* Significance of every class against an ensemble (Section 1, step (c); the
+   paper names no statistic: this is the usual z-score).  d_hist: device
+   array of ng x num_classes uint64 histograms, row 0 the original graph and
+   rows 1..ng-1 its random graphs (ng >= 3).  d_out: device array of
+   3 x num_classes float64 receiving, per class, the mean and the sample
+   standard deviation (divisor ng - 2) of the random graphs' counts and
+   z = (H_0 - mean) / std (0 if std = 0 and H_0 = mean, +-infinity if std = 0
+   otherwise).  Enqueued on `stream` (NULL: the context's stream). */
+int mk_significance(mk_ctx *ctx, const uint64_t *d_hist, int32_t ng, uint32_t num_classes,
+                    double *d_out, void *stream);
+
 /* ------------------------------------------------------------ class table */
 
 /* The code -> class table for k (Section 3.2): 2^(k(k-1)) uint32 entries in

@@ -85,6 +85,9 @@ SIGNATURES = {
                                      ctypes.POINTER(_I32)]),
     "mk_graph_footprint": (ctypes.c_int, [_P, ctypes.c_int, ctypes.POINTER(_U64)]),
     "mk_graph_free": (None, [_P]),
+    "mk_graph_read": (ctypes.c_int, [_P, _P, _P]),
+    "mk_randomise": (ctypes.c_int, [_P, _P, _I32, _U64, _U32, _P, _P]),
+    "mk_significance": (ctypes.c_int, [_P, _P, _I32, _U32, _P, _P]),
     "mk_table_build": (ctypes.c_int, [_P, ctypes.c_int, ctypes.POINTER(_P)]),
     "mk_table_release": (ctypes.c_int, [_P, ctypes.c_int]),
     "mk_table_info": (ctypes.c_int, [_P, ctypes.POINTER(_I32), ctypes.POINTER(_U32),
@@ -207,6 +210,29 @@ def mk_graph_footprint(g: int, k: int) -> int:
     b = _U64()
     _check(library().mk_graph_footprint(g, k, ctypes.byref(b)))
     return b.value
+
+
+def mk_graph_read(g: int) -> Tuple[np.ndarray, np.ndarray]:
+    n, m, _ = mk_graph_info(g)
+    row_ptr = np.empty(n + 1, dtype=np.int32)
+    col = np.empty(max(m, 1), dtype=np.int32)
+    _check(library().mk_graph_read(g, row_ptr.ctypes.data_as(_P), col.ctypes.data_as(_P)))
+    return row_ptr, col[:m]
+
+
+def mk_randomise(ctx: int, g: int, count: int, seed: int,
+                 switches_per_arc: int) -> Tuple[list, np.ndarray]:
+    """(handles of `count` random graphs, accepted switches per graph)."""
+    hs = (_P * max(count, 1))()
+    acc = np.zeros(max(count, 1), dtype=np.uint64)
+    _check(library().mk_randomise(ctx, g, count, seed & (2**64 - 1), switches_per_arc, hs,
+                                  acc.ctypes.data_as(_P)))
+    return [hs[i] for i in range(count)], acc[:count]
+
+
+def mk_significance(ctx: int, d_hist: int, ng: int, num_classes: int, d_out: int,
+                    stream: int = 0) -> None:
+    _check(library().mk_significance(ctx, d_hist, ng, num_classes, d_out, stream or None))
 
 
 def mk_graph_free(g: int) -> None:
@@ -373,10 +399,14 @@ def mk_server_stop(s: int) -> None:
 # ------------------------------------------------------------ handle classes
 
 class Graph:
-    def __init__(self, ctx: "Context", row_ptr, col):
+    def __init__(self, ctx: "Context", row_ptr, col, handle: int = 0):
         self.ctx = ctx
-        self.handle = mk_graph_load_csr(ctx.handle, row_ptr, col)
+        self.handle = handle or mk_graph_load_csr(ctx.handle, row_ptr, col)
         self.n, self.m, self.max_degree = mk_graph_info(self.handle)
+
+    def read(self) -> Tuple[np.ndarray, np.ndarray]:
+        """(row_ptr, col) copied back from the device."""
+        return mk_graph_read(self.handle)
 
     def footprint(self, k: int) -> int:
         return mk_graph_footprint(self.handle, k)
@@ -491,6 +521,25 @@ class Context:
 
     def autotune(self, graphs: Sequence[Graph], table: Table, trials: int = 2):
         return mk_autotune(self.handle, [g.handle for g in graphs], table.handle, trials)
+
+    def randomise(self, graph: Graph, count: int, seed: int, switches_per_arc: int = 10):
+        """(random graphs, accepted switches): the ensemble of `graph`."""
+        hs, acc = mk_randomise(self.handle, graph.handle, count, seed, switches_per_arc)
+        return [Graph(self, None, None, handle=h) for h in hs], acc
+
+    def significance(self, d_hist, num_classes: int, d_out, stream=None) -> None:
+        """Per class mean / std / z of an ensemble's device histograms
+        (ng x num_classes, row 0 the original) into d_out (3 x num_classes
+        float64); torch tensors or device addresses."""
+        ptr = d_hist.data_ptr() if hasattr(d_hist, "data_ptr") else int(d_hist)
+        out = d_out.data_ptr() if hasattr(d_out, "data_ptr") else int(d_out)
+        ng = d_hist.shape[0] if hasattr(d_hist, "shape") else None
+        if ng is None:
+            raise ValueError("d_hist must be a 2-D tensor (ng x num_classes)")
+        sp = 0
+        if stream is not None:
+            sp = stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+        mk_significance(self.handle, ptr, ng, num_classes, out, sp)
 
     def server(self, **opts) -> Server:
         return Server(self, **opts)
