@@ -15,8 +15,9 @@
 //
 // One workgroup per random graph, the paper's parallelism over the graphs of
 // an ensemble: its 64 lanes copy the arcs and set an n x n arc bit matrix,
-// one lane runs the chain (each step depends on the last), then the lanes
-// count reciprocal arcs for the sizes of delta(v).  The output graphs are
+// run the chain 64 attempts at a time (tested together, committed in order
+// in registers, re-tested where an earlier commit of the round touched them,
+// written together), then count reciprocal arcs for the sizes of delta(v).  The output graphs are
 // ordinary device-resident graphs, ready for a batch.
 //
 // Significance: per class, over the random graphs 1..R of a batch's
@@ -82,30 +83,104 @@ __global__ __launch_bounds__(kWave) void switch_kernel(ChainArgs a)
         atomicOr(&bits[(size_t)u * a.words + (v >> 5)], 1u << (v & 31));
     }
     __syncthreads();
-    if (lane == 0) {
+    // The chain, 64 attempts per round: every lane draws and tests one
+    // attempt against the state at the start of the round (one round trip
+    // for all), then the attempts are committed in order without touching
+    // memory.  An attempt whose arc slots, or whose tested arcs, an earlier
+    // accepted attempt of the round has touched is decided again on the
+    // current state: a slot's head is the one the latest accepted attempt
+    // wrote there, an arc's presence is the stored bit flipped once per
+    // accepted attempt that removed or added it.  So the result is that of
+    // taking the attempts one by one.  The round's switches are then written
+    // together: bits by XOR (order-free), each slot by its last writer.
+    {
         const uint64_t stream = splitmix(a.seed, r);
-        uint64_t accepted = 0;
-        auto has = [&](int u, int v) {
+        auto stored = [&](int u, int v) {
             return (bits[(size_t)u * a.words + (v >> 5)] >> (v & 31)) & 1u;
         };
-        auto flip = [&](int u, int v) { bits[(size_t)u * a.words + (v >> 5)] ^= 1u << (v & 31); };
-        for (uint64_t t = 0; a.m >= 2 && accepted < a.target && t < a.max_attempts; ++t) {
-            const uint32_t i = draw_arc(splitmix(stream, 2 * t), a.m);
-            const uint32_t j = draw_arc(splitmix(stream, 2 * t + 1), a.m);
-            const int ta = a.src[i], hb = col[i], tc = a.src[j], hd = col[j];
-            if (ta == tc || hb == hd || ta == hd || tc == hb) continue;
-            if (has(ta, hd) || has(tc, hb)) continue;
-            flip(ta, hb);
-            flip(tc, hd);
-            flip(ta, hd);
-            flip(tc, hb);
-            col[i] = hd;
-            col[j] = hb;
-            ++accepted;
+        auto same = [](int u1, int v1, int u2, int v2) { return u1 == u2 && v1 == v2; };
+        uint64_t accepted = 0, t0 = 0;
+        while (a.m >= 2 && accepted < a.target && t0 < a.max_attempts) {
+            const uint64_t t = t0 + (uint64_t)lane;
+            uint32_t i = 0, j = 0;
+            int ta = -1, hb = -1, tc = -1, hd = -1;
+            bool ok = false;
+            if (t < a.max_attempts) {
+                i = draw_arc(splitmix(stream, 2 * t), a.m);
+                j = draw_arc(splitmix(stream, 2 * t + 1), a.m);
+                ta = a.src[i];
+                hb = col[i];
+                tc = a.src[j];
+                hd = col[j];
+                ok = ta != tc && hb != hd && ta != hd && tc != hb && !stored(ta, hd) &&
+                     !stored(tc, hb);
+            }
+            // acc: this lane's attempt was accepted, with heads hb, hd as they
+            // were then; sup_i / sup_j: a later accepted attempt rewrote slot i / j
+            bool acc = false, sup_i = false, sup_j = false;
+            // does an accepted attempt of this round flip arc (u, v)?  (its
+            // removed arcs ta->hb, tc->hd and added ta->hd, tc->hb)
+            auto flips = [&](int u, int v) {
+                return acc && (same(ta, hb, u, v) || same(tc, hd, u, v) || same(ta, hd, u, v) ||
+                               same(tc, hb, u, v));
+            };
+            int l = 0;
+            for (; l < kWave; ++l) {
+                if (accepted >= a.target || t0 + (uint64_t)l >= a.max_attempts) break;
+                const uint32_t il = (uint32_t)__builtin_amdgcn_readlane((int)i, l);
+                const uint32_t jl = (uint32_t)__builtin_amdgcn_readlane((int)j, l);
+                const int al = __builtin_amdgcn_readlane(ta, l);
+                const int cl = __builtin_amdgcn_readlane(tc, l);
+                int bl = __builtin_amdgcn_readlane(hb, l);
+                int dl = __builtin_amdgcn_readlane(hd, l);
+                bool okl = __builtin_amdgcn_readlane((int)ok, l) != 0;
+                const unsigned long long at_i = __ballot(acc && (i == il || j == il));
+                const unsigned long long at_j = __ballot(acc && (i == jl || j == jl));
+                const bool hit = (at_i | at_j) != 0ull ||
+                                 __ballot(flips(al, dl) || flips(cl, bl)) != 0ull;
+                if (hit) {
+                    // current heads of slots il, jl: the latest writer's
+                    if (at_i) {
+                        const int k = 63 - __builtin_clzll(at_i);
+                        bl = __builtin_amdgcn_readlane(i == il ? hd : hb, k);
+                    }
+                    if (at_j) {
+                        const int k = 63 - __builtin_clzll(at_j);
+                        dl = __builtin_amdgcn_readlane(i == jl ? hd : hb, k);
+                    }
+                    bool fine = al != cl && bl != dl && al != dl && cl != bl;
+                    if (fine) {
+                        // current presence of al->dl and cl->bl
+                        const uint32_t p1 = (uint32_t)__popcll(__ballot(flips(al, dl))) & 1u;
+                        const uint32_t p2 = (uint32_t)__popcll(__ballot(flips(cl, bl))) & 1u;
+                        fine = (stored(al, dl) ^ p1) == 0u && (stored(cl, bl) ^ p2) == 0u;
+                    }
+                    okl = fine;
+                }
+                if (okl) {
+                    if (acc && (i == il || i == jl)) sup_i = true;
+                    if (acc && (j == il || j == jl)) sup_j = true;
+                    if (lane == l) {
+                        acc = true;
+                        hb = bl;
+                        hd = dl;
+                    }
+                    ++accepted;
+                }
+            }
+            t0 += (uint64_t)l;
+            if (acc) {
+                atomicXor(&bits[(size_t)ta * a.words + (hb >> 5)], 1u << (hb & 31));
+                atomicXor(&bits[(size_t)tc * a.words + (hd >> 5)], 1u << (hd & 31));
+                atomicXor(&bits[(size_t)ta * a.words + (hd >> 5)], 1u << (hd & 31));
+                atomicXor(&bits[(size_t)tc * a.words + (hb >> 5)], 1u << (hb & 31));
+                if (!sup_i) col[i] = hd;
+                if (!sup_j) col[j] = hb;
+            }
+            __syncthreads();
         }
-        a.stats[3 * r] = accepted;
+        if (lane == 0) a.stats[3 * r] = accepted;
     }
-    __syncthreads();
     // reciprocal arcs: u -> v with v -> u
     for (uint32_t t = lane; t < a.m; t += kWave) {
         const int u = a.src[t], v = col[t];

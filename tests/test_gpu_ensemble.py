@@ -49,6 +49,15 @@ def test_randomise_matches_oracle_small(ctx, seed):
     _check_against_oracle(ctx, rp, col, count=4, seed=seed, spa=10)
 
 
+def test_randomise_matches_oracle_tiny_graphs(ctx):
+    """Few arcs: most rounds of 64 attempts hit arc slots already switched
+    in the round, so the re-test path runs all the time."""
+    rng = np.random.default_rng(84)
+    for n, m in ((4, 3), (6, 8), (8, 16), (12, 30)):
+        rp, col = I.er_digraph(n, m, rng)
+        _check_against_oracle(ctx, rp, col, count=3, seed=n * 31 + m, spa=50)
+
+
 def test_randomise_matches_oracle_k5_original(ctx):
     rp, col = I.k5_batch_graph(0)
     _check_against_oracle(ctx, rp, col, count=3, seed=2024, spa=10)
