@@ -148,6 +148,7 @@ static EnumConfig enum_config(const mk_batch *b)
     c.flags = (uint32_t)b->opts.debug_flags;
     c.chunk = (uint32_t)std::max(b->opts.units_per_grab, 0);
     c.wave_scratch = b->d_wave_scratch;
+    c.hash_bits = b->method == MK_METHOD_CORES ? core_hash_bits(b->k) : enum_hash_bits(b->k);
     return c;
 }
 

@@ -483,13 +483,18 @@ __global__ __launch_bounds__(kWave) void enum_kernel(const DevGraph *graphs, con
 {
     extern __shared__ uint32_t lds[];
     EnumState<K> s;
-    const LdsLayout lay = lds_layout(K, cfg.max_n, cfg.seg_cap);
+    const LdsLayout lay = lds_layout(K, cfg.max_n, cfg.seg_cap, cfg.hash_bits);
     init_state<K>(s, reinterpret_cast<char *>(lds), lay, cfg, counters, table, num_classes);
     for_each_unit<K>(s, graphs, units, unit_cap, unit_end, counters, hist_base, cfg,
                      [&](int v, int i, uint32_t range) { run_unit<K>(s, v, i, range); });
 }
 
-int enum_lds_bytes(int k, int max_n, int seg_cap) { return lds_layout(k, max_n, seg_cap).total; }
+int enum_hash_bits(int) { return kHashBits; }
+
+int enum_lds_bytes(int k, int max_n, int seg_cap)
+{
+    return lds_layout(k, max_n, seg_cap, enum_hash_bits(k)).total;
+}
 
 template <int K>
 static const void *enum_fn()

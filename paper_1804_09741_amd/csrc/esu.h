@@ -70,8 +70,7 @@ constexpr int kScratchWords = 3 * kWave;
 // Per-wave hash of pending (code, count) pairs; flushed to the histogram when
 // half full, at the end of a unit once a quarter full, on a graph switch and
 // at exit.
-constexpr int kHashBits = MK_HASH_BITS;
-constexpr int kHashSlots = 1 << kHashBits;
+constexpr int kHashBits = MK_HASH_BITS;  // the enumeration kernel's; see EnumConfig
 constexpr int kHashProbes = 8;
 constexpr uint32_t kEmpty = 0xFFFFFFFFu;
 // A flush is forced once this many subgraphs are pending, so no 32-bit slot
@@ -87,7 +86,7 @@ struct LdsLayout {
     int seg, scratch, total;
 };
 
-__host__ __device__ inline LdsLayout lds_layout(int k, int max_n, int seg_cap)
+__host__ __device__ inline LdsLayout lds_layout(int k, int max_n, int seg_cap, int hash_bits)
 {
     const int segs = k == 3 ? 2 : k - 2;
     const int mark_bytes = ((k <= 5 ? 2 : 4) * max_n + 3) & ~3;
@@ -95,7 +94,7 @@ __host__ __device__ inline LdsLayout lds_layout(int k, int max_n, int seg_cap)
     LdsLayout l;
     l.seg = mark_bytes;
     l.scratch = l.seg + seg_bytes;
-    l.total = l.scratch + 4 * (kScratchWords + 2 * kHashSlots);
+    l.total = l.scratch + 4 * (kScratchWords + 2 * (1 << hash_bits));
     return l;
 }
 
@@ -123,6 +122,8 @@ struct EnumState {
     uint32_t *scratch;          // 3 x 64 words of LDS per wave
     uint32_t *hkey;             // per-wave LDS hash: code (kEmpty = free)
     uint32_t *hcnt;             //   and its pending count
+    int hshift;                 // 32 - log2(hash slots)
+    uint32_t hmask;             // hash slots - 1
     int hused;                  // keys in the hash (wave-uniform)
     uint32_t hpending;          // subgraphs pending in the hash (wave-uniform)
     bool class_keys;            // hash keys are class ids, not codes
@@ -218,7 +219,7 @@ template <int K>
 __device__ __forceinline__ void flush_hash(EnumState<K> &s)
 {
     __syncthreads();
-    for (int i = lane_id(); i < kHashSlots; i += kWave) {
+    for (int i = lane_id(); i <= (int)s.hmask; i += kWave) {
         const uint32_t key = s.hkey[i];
         if (key != kEmpty) {
             if (s.hcnt[i] != 0u) add_global<K>(s, key, s.hcnt[i]);
@@ -245,11 +246,11 @@ __device__ __forceinline__ void hash_insert(EnumState<K> &s, bool mine, uint32_t
     if (mine) {
         // one compare-and-swap either claims an empty slot or finds the code
         // already there; only a collision probes on
-        uint32_t h = (code * 2654435761u) >> (32 - kHashBits);
+        uint32_t h = (code * 2654435761u) >> s.hshift;
         uint32_t old = atomicCAS(&s.hkey[h], kEmpty, code);
         bool ok = old == kEmpty || old == code;
         for (int p = 1; p < kHashProbes && !ok; ++p) {
-            h = (h + 1) & (kHashSlots - 1);
+            h = (h + 1) & s.hmask;
             old = atomicCAS(&s.hkey[h], kEmpty, code);
             ok = old == kEmpty || old == code;
         }
@@ -261,7 +262,8 @@ __device__ __forceinline__ void hash_insert(EnumState<K> &s, bool mine, uint32_t
         }
     }
     s.hused += __popcll(__ballot(fresh));
-    if (s.hused > kHashSlots / 2 || s.hpending >= kPendingMax || (s.flags & kDebugFlushAlways))
+    if (s.hused > (int)(s.hmask >> 1) || s.hpending >= kPendingMax ||
+        (s.flags & kDebugFlushAlways))
         flush_hash<K>(s);
 }
 
@@ -302,11 +304,13 @@ __device__ __forceinline__ void init_state(EnumState<K> &s, char *base, const Ld
     s.flags = cfg.flags;
     s.scratch = reinterpret_cast<uint32_t *>(base + lay.scratch);
     s.hkey = s.scratch + kScratchWords;
-    s.hcnt = s.hkey + kHashSlots;
+    s.hshift = 32 - cfg.hash_bits;
+    s.hmask = (1u << cfg.hash_bits) - 1u;
+    s.hcnt = s.hkey + s.hmask + 1;
     s.hused = 0;
     s.hpending = 0;
     s.class_keys = false;
-    for (int i = lane_id(); i < kHashSlots; i += kWave) {
+    for (int i = lane_id(); i <= (int)s.hmask; i += kWave) {
         s.hkey[i] = kEmpty;
         s.hcnt[i] = 0u;
     }
@@ -370,7 +374,7 @@ __device__ __forceinline__ void for_each_unit(EnumState<K> &s, const DevGraph *g
                     cur = gi;
                 }
                 run(uniform(u.y), uniform(u.z), (uint32_t)uniform(u.w));
-                if (s.hused > kHashSlots / 4) flush_hash<K>(s);
+                if (s.hused > (int)((s.hmask + 1) >> 2)) flush_hash<K>(s);
             }
         }
     }

@@ -145,7 +145,10 @@ struct EnumConfig {
     uint32_t flags;  // kDebug* bits below (tests only; 0 in production)
     uint32_t chunk;  // units per queue grab; 0 = about 1/16 of a wave's share
     uint32_t *wave_scratch;  // core kernel: kParentArcCap words per workgroup
+    int hash_bits;           // log2 of the per-wave hash slots (enum_/core_hash_bits)
 };
+int enum_hash_bits(int k);
+int core_hash_bits(int k);
 constexpr uint32_t kDebugNoHash = 1u;      // every code straight to the histogram
 constexpr uint32_t kDebugFlushAlways = 2u; // flush the hash after every insert
 constexpr uint32_t kDebugNoShare = 4u;     // core kernel: no per-parent arc lists
