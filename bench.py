@@ -312,7 +312,7 @@ def main():
     if args.autotune:
         tuned, tuned_ms = ctx.autotune(graphs, t6, trials=2)
         opts = {kk: v for kk, v in tuned.items() if kk != "debug_flags" and v}
-        _log("autotune: %s (enum kernel %.3f ms)" % (opts, tuned_ms))
+        _log("autotune: %s (pass %.3f ms)" % (opts, tuned_ms))
     r = _timed_batch(ctx, M, graphs, t6, args.steps, args.warmup, torch, **opts)
     subgraphs = int(r["totals"].sum())
     ms_per_step = 1000.0 * r["wall_s"] / args.steps

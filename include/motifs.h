@@ -284,9 +284,10 @@ int mk_batch_timing(mk_batch *b, double *pass_ms, double *enum_ms);
 void mk_batch_free(mk_batch *b);
 
 /* Autotuner: time the batch path on these graphs (best of `trials` runs
-   each) under candidate settings -- split-threshold floor, units per queue
-   grab, waves per CU, tried one knob at a time from the library defaults --
-   and return the fastest in *best and its enumeration-kernel time in
+   each) under candidate settings -- counting method, split-threshold floor,
+   units per queue grab, waves per CU, tried one knob at a time from the
+   library defaults -- and return the fastest in *best and its whole-pass
+   time (preparation, counting and, for MK_METHOD_CORES, the division) in
    *best_ms (may be NULL).  Every candidate's histograms must equal the
    defaults' (MK_EDEVICE otherwise).  Allocates and frees its own batches;
    takes as long as about a dozen runs of the batch. */

@@ -358,7 +358,7 @@ def mk_batch_free(b: int) -> None:
 
 
 def mk_autotune(ctx: int, gs: Sequence[int], t: int, trials: int = 2) -> Tuple[dict, float]:
-    """(fastest batch options, its enumeration-kernel ms) for these graphs."""
+    """(fastest batch options, its whole-pass ms) for these graphs."""
     o = BatchOpts()
     ms = ctypes.c_double()
     _check(library().mk_autotune(ctx, _handles(gs), len(gs), t, trials, ctypes.byref(o),

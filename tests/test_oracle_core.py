@@ -129,3 +129,31 @@ def test_algorithm1_equals_esu_oracle(k):
     rng = np.random.default_rng([64, k])
     g = I.chung_lu_digraph(12, 30, 2.2, 6, 0.2, rng)
     assert O.algorithm1_count(*g, k) == O.count(*g, k)
+
+
+def test_paper_motif_figure():
+    """Section 2's figure of motif(v, A(v), B(v)): the cells are read off the
+    A/B/C definitions, and the loop over L_1 = {v, a, b} counts the one
+    3-set in the class of that figure."""
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(__file__), "golden",
+                           "paper_fig_motif_example.json")) as f:
+        fig = json.load(f)
+    idx = {name: i for i, name in enumerate(fig["vertices"])}
+    arcs = {(idx[u], idx[v]) for u, v in fig["arcs"]}
+    v = idx["v"]
+    # A(v): arcs both ways; B(v): v -> u only; C(v): u -> v only
+    for name, cell in fig["cells"].items():
+        u = idx[name]
+        got = {(True, True): "A", (True, False): "B", (False, True): "C"}[((v, u) in arcs,
+                                                                          (u, v) in arcs)]
+        assert got == cell
+    rp, col = I.csr_from_arcs(3, [a for a, _ in sorted(arcs)], [b for _, b in sorted(arcs)])
+    code = code_of(3, sorted(arcs))
+    expected = {O.canon(3, code): 1}
+    assert O.algorithm1_count(rp, col, 3) == expected == O.brute_force_count(rp, col, 3)
+    # one cell pair (A, B) with weight 1 * 1 and no arc between a and b;
+    # the class has one core: {v} touches both a and b, {a} and {b} do not
+    assert O.core_pairs_count(rp, col, 3) == expected
+    assert O.core_mult(3, code) == 1
