@@ -15,9 +15,10 @@
 //
 // One workgroup per random graph, the paper's parallelism over the graphs of
 // an ensemble: its 64 lanes copy the arcs and set an n x n arc bit matrix,
-// run the chain 64 attempts at a time (tested together, committed in order
-// in registers, re-tested where an earlier commit of the round touched them,
-// written together), then count reciprocal arcs for the sizes of delta(v).  The output graphs are
+// run the chain 64 attempts at a time (tested together; only the attempts
+// that depend on an earlier one of the round are decided again, in order, in
+// registers; written together), then count reciprocal arcs for the sizes of
+// delta(v).  The output graphs are
 // ordinary device-resident graphs, ready for a batch.
 //
 // Significance: per class, over the random graphs 1..R of a batch's
@@ -67,9 +68,18 @@ struct ChainArgs {
     unsigned long long *stats;    // per graph of the ensemble: accepted, nnz_u, max |delta|
 };
 
+// round-stamped LDS tables of the chain's dependence test (slots, arcs)
+constexpr int kChainTableBits = 12;
+
 __global__ __launch_bounds__(kWave) void switch_kernel(ChainArgs a)
 {
+    __shared__ uint32_t slot_tab[1 << kChainTableBits];
+    __shared__ uint32_t arc_tab[1 << kChainTableBits];
     const int lane = threadIdx.x;
+    for (int x = lane; x < (1 << kChainTableBits); x += kWave) {
+        slot_tab[x] = 0u;
+        arc_tab[x] = 0u;
+    }
     const uint64_t r = a.first + blockIdx.x;
     int32_t *col = a.cols[blockIdx.x];
     uint32_t *bits = a.bits + (size_t)blockIdx.x * a.n * a.words;
@@ -83,92 +93,162 @@ __global__ __launch_bounds__(kWave) void switch_kernel(ChainArgs a)
         atomicOr(&bits[(size_t)u * a.words + (v >> 5)], 1u << (v & 31));
     }
     __syncthreads();
-    // The chain, 64 attempts per round: every lane draws and tests one
+    // The chain, 64 attempts per round.  Every lane draws and tests one
     // attempt against the state at the start of the round (one round trip
-    // for all), then the attempts are committed in order without touching
-    // memory.  An attempt whose arc slots, or whose tested arcs, an earlier
-    // accepted attempt of the round has touched is decided again on the
-    // current state: a slot's head is the one the latest accepted attempt
-    // wrote there, an arc's presence is the stored bit flipped once per
-    // accepted attempt that removed or added it.  So the result is that of
-    // taking the attempts one by one.  The round's switches are then written
-    // together: bits by XOR (order-free), each slot by its last writer.
+    // for all).  An attempt's outcome can differ from that test only if an
+    // earlier accepted attempt of the round rewrote one of its two arc slots
+    // or flipped one of the two arcs it tests.  So: (1) each lane registers
+    // its slots and its four switch arcs (as drawn) in round-stamped LDS
+    // tables and finds whether an earlier attempt registered one of its
+    // slots or tested arcs -- a dependence (hash collisions only add
+    // dependences); (2) attempts without one keep their test, the others are
+    // decided in order on the current state -- a slot's head from its latest
+    // accepted writer, an arc's presence from the stored bit and the parity
+    // of the round's accepted flips; an accepted attempt whose heads differ
+    // from its draw marks the later attempts it touches as dependent too;
+    // (3) the round's switches are written together (bits by XOR,
+    // order-free; each slot by its last writer).  The result is that of
+    // taking the attempts one by one.
     {
         const uint64_t stream = splitmix(a.seed, r);
         auto stored = [&](int u, int v) {
             return (bits[(size_t)u * a.words + (v >> 5)] >> (v & 31)) & 1u;
         };
         auto same = [](int u1, int v1, int u2, int v2) { return u1 == u2 && v1 == v2; };
+        auto slot_hash = [](uint32_t x) { return (x * 2654435761u) >> (32 - kChainTableBits); };
+        auto arc_hash = [](int u, int v) {
+            return (((uint32_t)u * 8192u + (uint32_t)v) * 2654435761u) >> (32 - kChainTableBits);
+        };
         uint64_t accepted = 0, t0 = 0;
+        uint32_t round = 0;
         while (a.m >= 2 && accepted < a.target && t0 < a.max_attempts) {
+            if (++round == (1u << 26)) {
+                // stamps would wrap: start the tables afresh
+                for (int x = lane; x < (1 << kChainTableBits); x += kWave) {
+                    slot_tab[x] = 0u;
+                    arc_tab[x] = 0u;
+                }
+                round = 1;
+                __syncthreads();
+            }
             const uint64_t t = t0 + (uint64_t)lane;
+            const bool live = t < a.max_attempts;
             uint32_t i = 0, j = 0;
             int ta = -1, hb = -1, tc = -1, hd = -1;
             bool ok = false;
-            if (t < a.max_attempts) {
+            uint32_t s1 = 1, s2 = 1;  // stored bits of the tested arcs ta->hd, tc->hb
+            if (live) {
                 i = draw_arc(splitmix(stream, 2 * t), a.m);
                 j = draw_arc(splitmix(stream, 2 * t + 1), a.m);
                 ta = a.src[i];
                 hb = col[i];
                 tc = a.src[j];
                 hd = col[j];
-                ok = ta != tc && hb != hd && ta != hd && tc != hb && !stored(ta, hd) &&
-                     !stored(tc, hb);
+                s1 = stored(ta, hd);
+                s2 = stored(tc, hb);
+                ok = ta != tc && hb != hd && ta != hd && tc != hb && !s1 && !s2;
             }
-            // acc: this lane's attempt was accepted, with heads hb, hd as they
-            // were then; sup_i / sup_j: a later accepted attempt rewrote slot i / j
-            bool acc = false, sup_i = false, sup_j = false;
-            // does an accepted attempt of this round flip arc (u, v)?  (its
-            // removed arcs ta->hb, tc->hd and added ta->hd, tc->hb)
-            auto flips = [&](int u, int v) {
-                return acc && (same(ta, hb, u, v) || same(tc, hd, u, v) || same(ta, hd, u, v) ||
-                               same(tc, hb, u, v));
+            // (1) dependences: the lowest lane of this round holding a bucket wins
+            const uint32_t stamp = (round << 6) | (uint32_t)(63 - lane);
+            if (live) {
+                atomicMax(&slot_tab[slot_hash(i)], stamp);
+                atomicMax(&slot_tab[slot_hash(j)], stamp);
+                atomicMax(&arc_tab[arc_hash(ta, hb)], stamp);
+                atomicMax(&arc_tab[arc_hash(tc, hd)], stamp);
+                atomicMax(&arc_tab[arc_hash(ta, hd)], stamp);
+                atomicMax(&arc_tab[arc_hash(tc, hb)], stamp);
+            }
+            __syncthreads();
+            auto earlier = [&](uint32_t e) {
+                return (e >> 6) == round && (int)(63u - (e & 63u)) < lane;
             };
-            int l = 0;
-            for (; l < kWave; ++l) {
-                if (accepted >= a.target || t0 + (uint64_t)l >= a.max_attempts) break;
+            const bool dep = live && (earlier(slot_tab[slot_hash(i)]) || earlier(slot_tab[slot_hash(j)]) ||
+                                      earlier(arc_tab[arc_hash(ta, hd)]) ||
+                                      earlier(arc_tab[arc_hash(tc, hb)]));
+            // (2) decisions: independent attempts keep their test
+            bool acc = live && ok && !dep;
+            unsigned long long pending = __ballot(dep);
+            unsigned long long redone = 0ull;
+            while (pending) {
+                const int l = __builtin_ctzll(pending);
+                pending &= pending - 1ull;
+                redone |= 1ull << l;
                 const uint32_t il = (uint32_t)__builtin_amdgcn_readlane((int)i, l);
                 const uint32_t jl = (uint32_t)__builtin_amdgcn_readlane((int)j, l);
                 const int al = __builtin_amdgcn_readlane(ta, l);
                 const int cl = __builtin_amdgcn_readlane(tc, l);
-                int bl = __builtin_amdgcn_readlane(hb, l);
-                int dl = __builtin_amdgcn_readlane(hd, l);
-                bool okl = __builtin_amdgcn_readlane((int)ok, l) != 0;
-                const unsigned long long at_i = __ballot(acc && (i == il || j == il));
-                const unsigned long long at_j = __ballot(acc && (i == jl || j == jl));
-                const bool hit = (at_i | at_j) != 0ull ||
-                                 __ballot(flips(al, dl) || flips(cl, bl)) != 0ull;
-                if (hit) {
-                    // current heads of slots il, jl: the latest writer's
-                    if (at_i) {
-                        const int k = 63 - __builtin_clzll(at_i);
-                        bl = __builtin_amdgcn_readlane(i == il ? hd : hb, k);
-                    }
-                    if (at_j) {
-                        const int k = 63 - __builtin_clzll(at_j);
-                        dl = __builtin_amdgcn_readlane(i == jl ? hd : hb, k);
-                    }
-                    bool fine = al != cl && bl != dl && al != dl && cl != bl;
-                    if (fine) {
-                        // current presence of al->dl and cl->bl
-                        const uint32_t p1 = (uint32_t)__popcll(__ballot(flips(al, dl))) & 1u;
-                        const uint32_t p2 = (uint32_t)__popcll(__ballot(flips(cl, bl))) & 1u;
-                        fine = (stored(al, dl) ^ p1) == 0u && (stored(cl, bl) ^ p2) == 0u;
-                    }
-                    okl = fine;
+                const int bl0 = __builtin_amdgcn_readlane(hb, l);
+                const int dl0 = __builtin_amdgcn_readlane(hd, l);
+                // the round's accepted attempts before l, with their applied heads
+                const bool prior = acc && lane < l;
+                const unsigned long long at_i = __ballot(prior && (i == il || j == il));
+                const unsigned long long at_j = __ballot(prior && (i == jl || j == jl));
+                int bl = bl0, dl = dl0;
+                if (at_i) {
+                    const int k = 63 - __builtin_clzll(at_i);
+                    bl = __builtin_amdgcn_readlane(i == il ? hd : hb, k);
                 }
-                if (okl) {
-                    if (acc && (i == il || i == jl)) sup_i = true;
-                    if (acc && (j == il || j == jl)) sup_j = true;
-                    if (lane == l) {
-                        acc = true;
-                        hb = bl;
-                        hd = dl;
-                    }
-                    ++accepted;
+                if (at_j) {
+                    const int k = 63 - __builtin_clzll(at_j);
+                    dl = __builtin_amdgcn_readlane(i == jl ? hd : hb, k);
+                }
+                auto flips = [&](int u, int v) {
+                    return prior && (same(ta, hb, u, v) || same(tc, hd, u, v) ||
+                                     same(ta, hd, u, v) || same(tc, hb, u, v));
+                };
+                bool fine = al != cl && bl != dl && al != dl && cl != bl;
+                if (fine) {
+                    // stored bits: those read at the draw while the heads are as drawn
+                    const bool drawn = bl == bl0 && dl == dl0;
+                    const uint32_t b1 = drawn ? (uint32_t)__builtin_amdgcn_readlane((int)s1, l)
+                                              : stored(al, dl);
+                    const uint32_t b2 = drawn ? (uint32_t)__builtin_amdgcn_readlane((int)s2, l)
+                                              : stored(cl, bl);
+                    const uint32_t p1 = (uint32_t)__popcll(__ballot(flips(al, dl))) & 1u;
+                    const uint32_t p2 = (uint32_t)__popcll(__ballot(flips(cl, bl))) & 1u;
+                    fine = (b1 ^ p1) == 0u && (b2 ^ p2) == 0u;
+                }
+                if (lane == l) {
+                    acc = fine;
+                    hb = bl;
+                    hd = dl;
+                }
+                if (fine && (bl != bl0 || dl != dl0)) {
+                    // heads other than drawn: later attempts whose tested
+                    // arcs these switch arcs meet now depend on l
+                    const bool touched =
+                        lane > l && live &&
+                        (same(al, bl, ta, hd) || same(cl, dl, ta, hd) || same(al, dl, ta, hd) ||
+                         same(cl, bl, ta, hd) || same(al, bl, tc, hb) || same(cl, dl, tc, hb) ||
+                         same(al, dl, tc, hb) || same(cl, bl, tc, hb));
+                    pending |= __ballot(touched) & ~redone;
                 }
             }
-            t0 += (uint64_t)l;
+            // the target cut: attempts after the one that reaches it do not happen
+            const unsigned long long accm = __ballot(acc);
+            int cut = kWave;
+            const uint64_t room = a.target - accepted;
+            if ((uint64_t)__popcll(accm) >= room) {
+                unsigned long long mm = accm;
+                for (uint64_t q = 1; q < room; ++q) mm &= mm - 1ull;
+                cut = __builtin_ctzll(mm) + 1;
+            }
+            if (t0 + (uint64_t)cut > a.max_attempts) cut = (int)(a.max_attempts - t0);
+            acc = acc && lane < cut;
+            accepted += (uint64_t)__popcll(__ballot(acc));
+            // (3) write: each slot by its last accepted writer (a later writer
+            // of a slot shares it with an earlier attempt, so it was redone),
+            // bits by XOR
+            bool sup_i = false, sup_j = false;
+            unsigned long long later = __ballot(acc) & redone;
+            while (later) {
+                const int mlane = __builtin_ctzll(later);
+                later &= later - 1ull;
+                const uint32_t im = (uint32_t)__builtin_amdgcn_readlane((int)i, mlane);
+                const uint32_t jm = (uint32_t)__builtin_amdgcn_readlane((int)j, mlane);
+                sup_i |= lane < mlane && (i == im || i == jm);
+                sup_j |= lane < mlane && (j == im || j == jm);
+            }
             if (acc) {
                 atomicXor(&bits[(size_t)ta * a.words + (hb >> 5)], 1u << (hb & 31));
                 atomicXor(&bits[(size_t)tc * a.words + (hd >> 5)], 1u << (hd & 31));
@@ -177,6 +257,7 @@ __global__ __launch_bounds__(kWave) void switch_kernel(ChainArgs a)
                 if (!sup_i) col[i] = hd;
                 if (!sup_j) col[j] = hb;
             }
+            t0 += (uint64_t)cut;
             __syncthreads();
         }
         if (lane == 0) a.stats[3 * r] = accepted;
