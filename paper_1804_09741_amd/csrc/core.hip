@@ -130,23 +130,6 @@ __device__ __forceinline__ void push_marks(EnumState<K> &s, int x)
     __syncthreads();
 }
 
-// count codes with weight -1 (merged like count_codes)
-template <int K>
-__device__ __forceinline__ void uncount_codes(EnumState<K> &s, bool valid, uint32_t code)
-{
-    const int lane = lane_id();
-    unsigned long long act = __ballot(valid);
-    if (!act) return;
-    s.hpending += (uint32_t)__popcll(act);
-    uint32_t n = 1;
-    const int l = __builtin_ctzll(act);
-    const uint32_t c0 = (uint32_t)__builtin_amdgcn_readlane((int)code, l);
-    const unsigned long long eq = __ballot(code == c0) & act;
-    if (lane == l) n = (uint32_t)__popcll(eq);
-    else if ((eq >> lane) & 1ull) n = 0;
-    hash_insert<K>(s, valid && n > 0, code, 0u - n);
-}
-
 // Class id of a code for the class-keyed hash of the core kernel (cores
 // stand for many differently labelled k-sets, so their codes rarely repeat
 // while their classes do).  A code outside the connected classes is a

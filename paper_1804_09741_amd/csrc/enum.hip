@@ -230,6 +230,182 @@ __device__ void last_two_small(EnumState<K> &s, const int (&st)[K - 1],
     __syncthreads();
 }
 
+// k = 6 nodes with at most one wave of extension vertices: the pairs inside
+// E are counted per pair of cells, as in Section 3's loop over L_{k-2}.  Two
+// vertices with equal marks relate alike to the members, so all pairs of E
+// from cells A and B without an arc between them have one code; there are
+// C(n_A, 2) or n_A n_B of them.  The arcs inside E are found while the
+// children's lists are scanned for Part B: E's vertices carry kETag and
+// their lane in their (32-bit) marks meanwhile, and each arc (w, u), u
+// after w, adds one to its own code and takes one from its cell pair's.
+// Part B is counted as in last_two_small.
+constexpr uint32_t kETag = 1u << 30;  // mark bits 24..29: the vertex's lane
+
+template <int K>
+__device__ void last_two_cells(EnumState<K> &s, const int (&st)[K - 1],
+                               const int (&rem)[K - 2], int e, uint32_t code, int jlo)
+{
+    static_assert(K == 6, "E tags need the 32-bit marks of k = 6");
+    constexpr int NQ = K - 2;
+    constexpr int P1 = K - 2, P2 = K - 1;
+    constexpr int B_WU = (K - 2) * (K - 1) + (K - 2);
+    constexpr int B_UW = (K - 1) * (K - 1) + (K - 2);
+    const int lane = lane_id();
+    const bool inE = lane >= jlo && lane < e;
+    uint32_t vtx = 0, cb1 = 0, cb2 = 0, m0 = 0;
+    int row = 0, deg = 0;
+    if (lane < e) {
+        vtx = s.seg[ext_addr<K, NQ>(s, st, rem, lane)];
+        m0 = s.mark[vtx];
+        cb1 = code_bits<K>(m0, P1);
+        cb2 = code_bits<K>(m0, P2);
+        row = s.urow[vtx];
+        deg = s.urow[vtx + 1] - row;
+    }
+    if (!inE) deg = 0;
+    if (inE) s.mark[vtx] = (MarkT<K>)(m0 | kETag | ((uint32_t)lane << 24));
+    __syncthreads();
+    auto tbits = [](uint32_t t) { return ((t & 1u) << B_WU) | ((t >> 1) << B_UW); };
+
+    // children with long lists alone: exclusive neighbours by type, arcs to
+    // later vertices of E one by one
+    unsigned long long big = __ballot(deg >= kRowMin);
+    while (big) {
+        const int l = __builtin_ctzll(big);
+        big &= big - 1;
+        const int brow = __builtin_amdgcn_readlane(row, l);
+        const int bdeg = __builtin_amdgcn_readlane(deg, l);
+        const uint32_t bcode = code | (uint32_t)__builtin_amdgcn_readlane((int)cb1, l);
+        uint32_t n1 = 0, n2 = 0, n3 = 0;
+        for (int b = 0; b < bdeg; b += kWave) {
+            const int e2 = b + lane;
+            uint32_t tb = 0, t = 0;
+            bool arc = false;
+            int q = 0;
+            if (e2 < bdeg) {
+                const uint32_t ent = s.uadj[brow + e2];
+                const int u = (int)(ent >> 2);
+                const uint32_t mu = s.mark[u];
+                t = ent & 3u;
+                if (mu & kETag) {
+                    q = (int)((mu >> 24) & 63u);
+                    arc = q > l;
+                } else if (u > s.root && mu == 0u) {
+                    tb = t;
+                }
+            }
+            n1 += (uint32_t)__popcll(__ballot(tb == 1u));
+            n2 += (uint32_t)__popcll(__ballot(tb == 2u));
+            n3 += (uint32_t)__popcll(__ballot(tb == 3u));
+            const uint32_t cm = bcode | from_lane(cb2, q);
+            count_codes<K>(s, arc, cm | tbits(t));
+            uncount_codes<K>(s, arc, cm);
+        }
+        const uint32_t tl = (uint32_t)lane + 1u;
+        const uint32_t nl = lane == 0 ? n1 : (lane == 1 ? n2 : n3);
+        s.hpending += n1 + n2 + n3;
+        hash_insert<K>(s, lane < 3 && nl > 0, bcode | tbits(tl), nl);
+    }
+    if (deg >= kRowMin) deg = 0;
+    int incl = deg;
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        const int o = __shfl_up(incl, d, kWave);
+        if (lane >= d) incl += o;
+    }
+    const int totB = uniform(__shfl(incl, kWave - 1, kWave));
+    uint32_t *pre = s.scratch;
+    pre[lane] = (uint32_t)incl;
+    __syncthreads();
+    // the short lists, flat: Part B entries and arcs inside E
+    for (int base = 0; base < totB; base += kWave) {
+        const int f = base + lane;
+        const bool valid = f < totB;
+        int src1 = 0, off = 0;
+        if (valid) {
+            int lo = 0;
+#pragma unroll
+            for (int step = kWave / 2; step > 0; step >>= 1)
+                lo += ((int)pre[lo + step - 1] <= f) ? step : 0;
+            src1 = lo;
+            off = f - (lo ? (int)pre[lo - 1] : 0);
+        }
+        // the permutes run with every lane active
+        const int r1 = (int)from_lane((uint32_t)row, src1);
+        const uint32_t c1 = from_lane(cb1, src1);
+        bool bv = false, arc = false;
+        uint32_t t = 0;
+        int q = 0;
+        if (valid) {
+            const uint32_t ent = s.uadj[r1 + off];
+            const int u = (int)(ent >> 2);
+            const uint32_t mu = s.mark[u];
+            t = ent & 3u;
+            if (mu & kETag) {
+                q = (int)((mu >> 24) & 63u);
+                arc = q > src1;
+            } else {
+                bv = u > s.root && mu == 0u;
+            }
+        }
+        const uint32_t cm = code | c1 | from_lane(cb2, q);
+        count_codes<K>(s, bv, code | c1 | tbits(t));
+        count_codes<K>(s, arc, cm | tbits(t));
+        uncount_codes<K>(s, arc, cm);
+    }
+    __syncthreads();
+
+    // the cells of E (vertices with equal marks) and their pairs
+    const uint32_t key = inE ? cb1 : 0xFFFFFFFFu;
+    unsigned long long left = __ballot(inE);
+    bool leader = false;
+    uint32_t size = 0;
+    while (left) {
+        const int l = __builtin_ctzll(left);
+        const uint32_t k0 = (uint32_t)__builtin_amdgcn_readlane((int)key, l);
+        const unsigned long long eq = __ballot(key == k0) & left;
+        if (lane == l) {
+            leader = true;
+            size = (uint32_t)__popcll(eq);
+        }
+        left &= ~eq;
+    }
+    const unsigned long long leaders = __ballot(leader);
+    const int ncell = __popcll(leaders);
+    uint32_t *cc1 = s.scratch + kWave, *cc2 = s.scratch + 2 * kWave;
+    if (leader) {
+        const int rk = (int)lanes_below(leaders);
+        cc1[rk] = cb1 | (size << 24);  // cb1 < 2^24 for k = 6
+        cc2[rk] = cb2;
+    }
+    __syncthreads();
+    const int mm = e - jlo;
+    const uint32_t all_pairs = (uint32_t)(mm * (mm - 1) / 2);
+    if (s.hpending + all_pairs >= kPendingMax) flush_hash<K>(s);
+    s.hpending += all_pairs;
+    const int ncp = ncell * (ncell + 1) / 2;
+    for (int pb = 0; pb < ncp; pb += kWave) {
+        const int p = pb + lane;
+        bool valid = p < ncp;
+        uint32_t c = 0, w = 0;
+        if (valid) {
+            // p = z(z+1)/2 + y with y <= z
+            int z = (int)((__builtin_amdgcn_sqrtf(8.0f * (float)p + 1.0f) - 1.0f) * 0.5f);
+            if ((z + 1) * (z + 2) / 2 <= p) ++z;
+            if (z * (z + 1) / 2 > p) --z;
+            const int y = p - z * (z + 1) / 2;
+            const uint32_t xy = cc1[y], xz = cc1[z];
+            const uint32_t ny = xy >> 24, nz = xz >> 24;
+            w = y == z ? ny * (ny - 1u) / 2u : ny * nz;
+            c = code | (xy & 0xFFFFFFu) | cc2[z];
+            valid = w > 0u;
+        }
+        hash_insert<K>(s, valid, c, w);
+    }
+    if (inE) s.mark[vtx] = (MarkT<K>)m0;
+    __syncthreads();
+}
+
 // The last two ESU levels of a node X with k-2 members s_0..s_{k-3} and
 // extension list E, done flat across the wavefront without adding members.
 // Child w = E[i] (i in [jlo, jhi)) closes the k-sets X + {w, u} for
@@ -258,7 +434,8 @@ __device__ void last_two(EnumState<K> &s, const int (&st)[K - 1], uint32_t code,
     const int hi = e < jhi ? e : jhi;
     if (jlo >= hi) return;
     if (e <= kWave && hi == e) {
-        last_two_small<K>(s, st, rem, e, code, jlo);
+        if constexpr (K == 6) last_two_cells<K>(s, st, rem, e, code, jlo);
+        else last_two_small<K>(s, st, rem, e, code, jlo);
         return;
     }
 

@@ -292,6 +292,23 @@ __device__ __forceinline__ void count_codes(EnumState<K> &s, bool valid, uint32_
 }
 
 
+// count codes with weight -1 (merged like count_codes)
+template <int K>
+__device__ __forceinline__ void uncount_codes(EnumState<K> &s, bool valid, uint32_t code)
+{
+    const int lane = lane_id();
+    unsigned long long act = __ballot(valid);
+    if (!act) return;
+    s.hpending += (uint32_t)__popcll(act);
+    uint32_t n = 1;
+    const int l = __builtin_ctzll(act);
+    const uint32_t c0 = (uint32_t)__builtin_amdgcn_readlane((int)code, l);
+    const unsigned long long eq = __ballot(code == c0) & act;
+    if (lane == l) n = (uint32_t)__popcll(eq);
+    else if ((eq >> lane) & 1ull) n = 0;
+    hash_insert<K>(s, valid && n > 0, code, 0u - n);
+}
+
 // Set up a wave's state on its LDS (marks zero, hash empty).
 template <int K>
 __device__ __forceinline__ void init_state(EnumState<K> &s, char *base, const LdsLayout &lay,
