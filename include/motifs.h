@@ -9,9 +9,14 @@
  *   - mk_table_*   the code -> class table of Section 3.2 (isomorphism in
  *                  O(1) by precomputing the class of every adjacency matrix);
  *   - mk_count*,
- *     mk_batch_*   enumeration of every connected induced k-set exactly once,
- *                  its adjacency code, the table lookup and the histogram;
- *   - mk_server_*  a continuous-batching request server over the same path.
+ *     mk_batch_*   the histograms of one graph or a batch of graphs, by
+ *                  enumeration of every connected induced k-set exactly once
+ *                  (its adjacency code, the table lookup) or by Section 3's
+ *                  counting from the connected (k-2)-sets (MK_METHOD_*);
+ *   - mk_server_*  a continuous-batching request server over the same path;
+ *   - mk_randomise,
+ *     mk_significance  the ensemble of random graphs and the z-score of each
+ *                  class against it (Section 1's steps (a) and (c)).
  *
  * Conventions used throughout:
  *
