@@ -617,13 +617,13 @@ __device__ void visit(EnumState<K> &s, const int (&st)[K - 1], uint32_t code, in
             const int x = uniform((int)s.seg[L * s.seg_cap + o]);
             const uint32_t mx = (uint32_t)uniform((int)s.mark[x]);
             const uint32_t ccode = code | code_bits<K>(mx, D + 1);
-            push<K, D + 1>(s, x);
+            const Held held = push_held<K, D + 1>(s, x);
             int cst[K - 1];
 #pragma unroll
             for (int q = 0; q < K - 1; ++q)
                 cst[q] = q < L ? s.len[q] : (q == L ? o + 1 : (q <= D ? st[q] : 0));
             visit<K, D + 1>(s, cst, ccode, 0, INT_MAX);
-            pop<K, D + 1>(s, x);
+            pop_held<K, D + 1>(s, x, held);
         }
     }
 }
@@ -632,22 +632,22 @@ template <int K>
 __device__ void run_unit(EnumState<K> &s, int v, int i, uint32_t range)
 {
     s.root = v;
-    push<K, 0>(s, v);
+    const Held held0 = push_held<K, 0>(s, v);
     if (i < s.len[0]) {
         const int x = uniform((int)s.seg[i]);
         const uint32_t code = code_bits<K>((uint32_t)uniform((int)s.mark[x]), 1);
-        push<K, 1>(s, x);
+        const Held held1 = push_held<K, 1>(s, x);
         int st[K - 1];
 #pragma unroll
         for (int q = 0; q < K - 1; ++q) st[q] = 0;
         st[0] = i + 1;
         const bool full = range == kFullChild;
         visit<K, 1>(s, st, code, full ? 0 : (int)(range & 0xFFFFu), full ? INT_MAX : (int)(range >> 16));
-        pop<K, 1>(s, x);
+        pop_held<K, 1>(s, x, held1);
     } else if (lane_id() == 0) {
         atomicAdd(s.errors, 1u);
     }
-    pop<K, 0>(s, v);
+    pop_held<K, 0>(s, v, held0);
 }
 
 template <int K>

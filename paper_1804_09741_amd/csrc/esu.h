@@ -203,6 +203,57 @@ __device__ __forceinline__ void pop(EnumState<K> &s, int x)
     __syncthreads();
 }
 
+// A member's list when it fits one wave: each lane keeps its entry and the
+// neighbour's mark from before the push, so the pop restores the marks
+// without reading the list again (deeper levels undo their own bits, so the
+// marks at the pop are exactly these plus the member's).
+struct Held {
+    uint32_t ent;  // this lane's list entry (lanes < n)
+    uint32_t m;    // the neighbour's mark before the push
+    int n;         // list length (wave-uniform)
+};
+
+// push<D>(x), keeping the list for pop_held
+template <int K, int D>
+__device__ __forceinline__ Held push_held(EnumState<K> &s, int x)
+{
+    const int lane = lane_id();
+    const int r0 = uniform(s.urow[x]);
+    const int r1 = uniform(s.urow[x + 1]);
+    Held h;
+    h.n = r1 - r0;
+    h.ent = 0u;
+    h.m = 0u;
+    if (h.n > kWave) {
+        push<K, D>(s, x);
+        return h;
+    }
+    uint16_t *seg = s.seg + D * s.seg_cap;
+    const bool valid = lane < h.n;
+    if (valid) h.ent = s.uadj[r0 + lane];
+    const int y = (int)(h.ent >> 2);
+    if (valid) h.m = s.mark[y];
+    const bool fresh = valid && y > s.root && h.m == 0u;
+    const unsigned long long bal = __ballot(fresh);
+    if (fresh) seg[(int)lanes_below(bal)] = (uint16_t)y;
+    if (valid) s.mark[y] = (MarkT<K>)(h.m | mark_bits<K>(D, h.ent & 3u));
+    s.len[D] = __popcll(bal);
+    __syncthreads();
+    return h;
+}
+
+// undo push_held<D>(x)
+template <int K, int D>
+__device__ __forceinline__ void pop_held(EnumState<K> &s, int x, const Held &h)
+{
+    if (h.n > kWave) {
+        pop<K, D>(s, x);
+        return;
+    }
+    if (lane_id() < h.n) s.mark[h.ent >> 2] = (MarkT<K>)h.m;
+    __syncthreads();
+}
+
 // add n to the histogram bin of code (table lookup + global 64-bit atomic)
 template <int K>
 __device__ __forceinline__ void add_global(EnumState<K> &s, uint32_t code, uint32_t n)
