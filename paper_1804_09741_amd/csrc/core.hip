@@ -130,6 +130,31 @@ __device__ __forceinline__ void push_marks(EnumState<K> &s, int x)
     __syncthreads();
 }
 
+// push_marks<D>(x) keeping the list for pop_held (see push_held)
+template <int K, int D>
+__device__ __forceinline__ Held push_marks_held(EnumState<K> &s, int x)
+{
+    const int lane = lane_id();
+    const int r0 = uniform(s.urow[x]);
+    const int r1 = uniform(s.urow[x + 1]);
+    Held h;
+    h.n = r1 - r0;
+    h.ent = 0u;
+    h.m = 0u;
+    if (h.n > kWave) {
+        push_marks<K, D>(s, x);
+        return h;
+    }
+    if (lane < h.n) {
+        h.ent = s.uadj[r0 + lane];
+        const int y = (int)(h.ent >> 2);
+        h.m = s.mark[y];
+        s.mark[y] = (MarkT<K>)(h.m | mark_bits<K>(D, h.ent & 3u));
+    }
+    __syncthreads();
+    return h;
+}
+
 // Class id of a code for the class-keyed hash of the core kernel (cores
 // stand for many differently labelled k-sets, so their codes rarely repeat
 // while their classes do).  A code outside the connected classes is a
@@ -462,17 +487,17 @@ __device__ void visit_core(EnumState<K> &s, const CoreLds &c, const int (&st)[K 
         const uint32_t ccode = code | code_bits<K>((uint32_t)uniform((int)s.mark[x]), D + 1);
         mem[D + 1] = x;
         if constexpr (D + 1 == K - 3) {
-            push_marks<K, D + 1>(s, x);
+            const Held held = push_marks_held<K, D + 1>(s, x);
             core_node<K>(s, c, mem, ccode, nap);
-            pop<K, D + 1>(s, x);
+            pop_held<K, D + 1>(s, x, held);
         } else {
-            push<K, D + 1>(s, x);
+            const Held held = push_held<K, D + 1>(s, x);
             int cst[K - 1];
 #pragma unroll
             for (int q = 0; q < K - 1; ++q)
                 cst[q] = q < L ? s.len[q] : (q == L ? o + 1 : (q <= D ? st[q] : 0));
             visit_core<K, D + 1>(s, c, cst, ccode, 0, INT_MAX, mem);
-            pop<K, D + 1>(s, x);
+            pop_held<K, D + 1>(s, x, held);
         }
     }
 }
@@ -488,21 +513,21 @@ __device__ void run_core_unit(EnumState<K> &s, const CoreLds &c, int v, int i, u
     mem[0] = v;
     s.root = v;
     if constexpr (K == 3) {
-        push_marks<K, 0>(s, v);
+        const Held held0 = push_marks_held<K, 0>(s, v);
         core_node<K>(s, c, mem, 0u, -1);
-        pop<K, 0>(s, v);
+        pop_held<K, 0>(s, v, held0);
     } else {
-        push<K, 0>(s, v);
+        const Held held0 = push_held<K, 0>(s, v);
         if (i < s.len[0]) {
             const int x = uniform((int)s.seg[i]);
             const uint32_t code = code_bits<K>((uint32_t)uniform((int)s.mark[x]), 1);
             mem[1] = x;
             if constexpr (K == 4) {
-                push_marks<K, 1>(s, x);
+                const Held held1 = push_marks_held<K, 1>(s, x);
                 core_node<K>(s, c, mem, code, -1);
-                pop<K, 1>(s, x);
+                pop_held<K, 1>(s, x, held1);
             } else {
-                push<K, 1>(s, x);
+                const Held held1 = push_held<K, 1>(s, x);
                 int st[K - 1];
 #pragma unroll
                 for (int q = 0; q < K - 1; ++q) st[q] = 0;
@@ -510,12 +535,12 @@ __device__ void run_core_unit(EnumState<K> &s, const CoreLds &c, int v, int i, u
                 const bool full = range == kFullChild;
                 visit_core<K, 1>(s, c, st, code, full ? 0 : (int)(range & 0xFFFFu),
                                  full ? INT_MAX : (int)(range >> 16), mem);
-                pop<K, 1>(s, x);
+                pop_held<K, 1>(s, x, held1);
             }
         } else if (lane_id() == 0) {
             atomicAdd(s.errors, 1u);
         }
-        pop<K, 0>(s, v);
+        pop_held<K, 0>(s, v, held0);
     }
 }
 
