@@ -78,10 +78,16 @@ extern "C" {
 
 #define MK_INVALID_CLASS 0xFFFFFFFFu
 
-/* Largest graph the enumeration accepts: n <= MK_MAX_VERTICES and undirected
-   degree (|delta(v)|) <= MK_MAX_DEGREE.  The paper's graphs have n <= 6175. */
-#define MK_MAX_VERTICES 8192
+/* Largest graph the library accepts: n <= MK_MAX_VERTICES and undirected
+   degree (|delta(v)|) <= MK_MAX_DEGREE.  The paper's graphs have n <= 6175.
+   Batches whose graphs all have n <= MK_LDS_MARKS_MAX_VERTICES keep each
+   wave's per-vertex marks in LDS; larger ones keep them in device memory
+   (MK_MARKS_GLOBAL, slower), count by enumeration only, and test arcs on the
+   sorted lists (MK_ADJ_LISTS).  mk_randomise takes graphs up to
+   MK_LDS_MARKS_MAX_VERTICES vertices. */
+#define MK_MAX_VERTICES (1 << 20)
 #define MK_MAX_DEGREE 4096
+#define MK_LDS_MARKS_MAX_VERTICES 8192
 
 typedef struct mk_ctx mk_ctx;
 typedef struct mk_graph mk_graph;
@@ -140,8 +146,9 @@ int mk_graph_read(const mk_graph *g, int32_t *row_ptr, int32_t *col);
    accepted (may be NULL) receives each graph's accepted count.  Every arc
    keeps its CSR position, so out- and in-degrees are kept exactly.  out
    receives `count` new graphs (free each with mk_graph_free); on error none
-   is left.  MK_ERANGE if a random graph's undirected degree exceeds
-   MK_MAX_DEGREE.  Blocks until the graphs are ready. */
+   is left.  MK_ERANGE if g has more than MK_LDS_MARKS_MAX_VERTICES vertices
+   or a random graph's undirected degree exceeds MK_MAX_DEGREE.  Blocks until
+   the graphs are ready. */
 int mk_randomise(mk_ctx *ctx, const mk_graph *g, int32_t count, uint64_t seed,
                  uint32_t switches_per_arc, mk_graph **out, uint64_t *accepted);
 
@@ -232,6 +239,12 @@ typedef struct mk_batch_opts {
                                  parent's arc pairs; results are the same */
     int32_t method;           /* MK_METHOD_*: how H_k is counted (0: the
                                  library's choice); results are the same */
+    int32_t adjacency;        /* MK_ADJ_*: how arcs between extension
+                                 vertices are tested (0: the library's
+                                 choice); results are the same */
+    int32_t marks;            /* MK_MARKS_*: where each wave keeps its
+                                 per-vertex marks (0: the library's choice);
+                                 results are the same */
 } mk_batch_opts;
 
 /* Counting methods of a batch.
@@ -243,10 +256,38 @@ typedef struct mk_batch_opts {
      of one class at once, each arc inside adj(X) moves one k-set to its
      true class, and the sums are divided by the cores per class
      (mk_table_core_mult). */
-/* MK_METHOD_AUTO: MK_METHOD_CORES for k <= 5, MK_METHOD_ESU for k = 6. */
+/* MK_METHOD_AUTO: MK_METHOD_CORES for k <= 5, MK_METHOD_ESU for k = 6 and
+   for graphs with more than MK_LDS_MARKS_MAX_VERTICES vertices (which
+   MK_METHOD_CORES rejects with MK_ERANGE). */
 #define MK_METHOD_AUTO 0
 #define MK_METHOD_ESU 1
 #define MK_METHOD_CORES 2
+
+/* Arc tests between two extension vertices w, u in the last two levels of
+   the enumeration (the pair test of Section 3.1's Algorithm 2; the rest of
+   the code comes from marks left by scanning the members' lists, as in its
+   Algorithm 3).
+   MK_ADJ_BITS: two n x n bit matrices (out- and in-arcs) per graph, built
+     each pass; one bit read per test; the typed lists are built from them.
+   MK_ADJ_LISTS: no bit matrix: the typed lists are built by sorting each
+     vertex's out- and in-arcs, and a test is a binary search in the shorter
+     of the two vertices' lists (the degree split of Algorithms 4 and 5).
+   MK_ADJ_AUTO: MK_ADJ_BITS while every graph has n <=
+     MK_LDS_MARKS_MAX_VERTICES, else MK_ADJ_LISTS. */
+#define MK_ADJ_AUTO 0
+#define MK_ADJ_BITS 1
+#define MK_ADJ_LISTS 2
+
+/* Per-vertex marks of each wave (every vertex's relation to the current
+   members; 2 bytes per vertex for k <= 5, 4 for k = 6).
+   MK_MARKS_LDS: in LDS; needs n <= MK_LDS_MARKS_MAX_VERTICES.
+   MK_MARKS_GLOBAL: a private n-entry array per wave in device memory (kept
+     zero between work units; fewer waves when they would take more than
+     1/16 of the device memory); needs MK_ADJ_LISTS and MK_METHOD_ESU.
+   MK_MARKS_AUTO: MK_MARKS_LDS when the graphs fit, else MK_MARKS_GLOBAL. */
+#define MK_MARKS_AUTO 0
+#define MK_MARKS_LDS 1
+#define MK_MARKS_GLOBAL 2
 
 /* Prepare a batch: device workspace for the typed adjacency, the work
    units and the histograms of ng graphs (counted with table t), sized by
@@ -278,6 +319,8 @@ typedef struct mk_batch_stats {
     int32_t k;
     int32_t ng;
     int32_t method;           /* the MK_METHOD_* the batch runs */
+    int32_t adjacency;        /* the MK_ADJ_* it runs */
+    int32_t marks;            /* the MK_MARKS_* it runs */
 } mk_batch_stats;
 int mk_batch_stats_get(const mk_batch *b, mk_batch_stats *out);
 

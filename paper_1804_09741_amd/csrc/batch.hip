@@ -25,8 +25,8 @@ struct mk_batch {
     mk_batch_opts opts{};
 
     DevGraph *d_graphs = nullptr;
-    uint32_t *d_ws = nullptr;  // bits, urow, uadj
-    uint64_t bits_words = 0;
+    uint32_t *d_ws = nullptr;  // bit matrices (or list-build arrays), urow, uadj
+    uint64_t bits_words = 0;   // MK_ADJ_BITS: words of all bit matrices
     uint32_t *d_slot_cnt = nullptr;
     uint32_t *d_slot_off = nullptr;
     uint32_t *d_slot_est = nullptr;
@@ -38,13 +38,20 @@ struct mk_batch {
     uint32_t *d_counters = nullptr;
     unsigned long long *d_hist_own = nullptr;
     uint32_t *d_wave_scratch = nullptr;  // core method: per-workgroup arc lists
+    void *d_marks = nullptr;             // MK_MARKS_GLOBAL: per-workgroup marks
+    size_t mark_stride = 0;              //   marks per workgroup
+    size_t mark_bytes = 0;               //   bytes of d_marks
     unsigned long long *hist_last = nullptr;
 
     int max_n = 0, max_words = 0, seg_cap = 0;
     int64_t max_m = 0;
     int64_t max_nnz = 0;
+    uint64_t total_n = 0, total_m = 0;  // over the batch (list-built adjacency)
     int grid = 0, max_grid = 0, lds_bytes = 0;
     int method = MK_METHOD_ESU;  // resolved (never MK_METHOD_AUTO)
+    int adjacency = MK_ADJ_BITS; // resolved MK_ADJ_*
+    int marks = MK_MARKS_LDS;    // resolved MK_MARKS_*
+    int variant = 0;             // kVar* bits of the enumeration kernel
     int plan_k = 0;              // set size the planner cuts units for
     uint64_t units = 0, split_pairs = 0;
 
@@ -114,14 +121,23 @@ extern "C" int mk_graph_footprint(const mk_graph *g, int k, uint64_t *bytes)
     if (!g || !bytes) return fail(MK_EINVAL, "mk_graph_footprint: NULL argument");
     if (k < 3 || k > 6) return fail(MK_ERANGE, "k=%d outside 3..6", k);
     const uint64_t n = (uint64_t)g->n, w = (n + 31) / 32;
-    const uint64_t ws = 4 * (2 * n * w + (n + 1) + (uint64_t)g->nnz_u);
+    const bool big = g->n > MK_LDS_MARKS_MAX_VERTICES;  // list-built adjacency, global marks
+    const uint64_t region = big ? list_ws_words(n, (uint64_t)g->m) : 2 * n * w;
+    const uint64_t ws = 4 * (region + (n + 1) + (uint64_t)g->nnz_u);
     const uint64_t slots = 8 * (uint64_t)g->nnz_u + 4 * ((uint64_t)g->nnz_u / 4096 + 2);
     const uint64_t units = 16 * (uint64_t)g->nnz_u * 4;  // planning estimate
     const uint64_t hist = 8ull * classes_for_k(k);
-    // per-workgroup arc lists of the core method (the default for k <= 5),
-    // one workgroup per unit at most
-    const uint64_t scratch = k <= 5 ? 4ull * kParentArcCap * std::min<uint64_t>(g->nnz_u + 1, 8192) : 0;
-    *bytes = ws + slots + units + hist + scratch + sizeof(DevGraph) + 4 * kNumCounters;
+    // per-workgroup arc lists of the core method (the default for k <= 5 on
+    // graphs with LDS marks), one workgroup per unit at most
+    const uint64_t scratch =
+        k <= 5 && !big ? 4ull * kParentArcCap * std::min<uint64_t>(g->nnz_u + 1, 8192) : 0;
+    // per-workgroup marks, at most 32 workgroups per CU and 1/16 of the memory
+    const uint64_t per_wave = ((n + 63) & ~63ull) * (k <= 5 ? 2 : 4);
+    const uint64_t marks =
+        big ? std::min<uint64_t>((uint64_t)g->ctx->hbm_bytes / 16,
+                                 (uint64_t)g->ctx->num_cus * 32 * per_wave)
+            : 0;
+    *bytes = ws + slots + units + hist + scratch + marks + sizeof(DevGraph) + 4 * kNumCounters;
     return MK_OK;
 }
 
@@ -135,7 +151,7 @@ static void batch_release(mk_batch *b)
     if (b->graph) (void)hipGraphDestroy(b->graph);
     void *bufs[] = {b->d_graphs, b->d_ws, b->d_slot_cnt, b->d_slot_off, b->d_slot_est,
                     b->d_slot_vi, b->d_scan_tmp,
-                    b->d_units, b->d_counters, b->d_hist_own, b->d_wave_scratch};
+                    b->d_units, b->d_counters, b->d_hist_own, b->d_wave_scratch, b->d_marks};
     for (void *p : bufs)
         if (p) (void)hipFree(p);
 }
@@ -149,7 +165,20 @@ static EnumConfig enum_config(const mk_batch *b)
     c.chunk = (uint32_t)std::max(b->opts.units_per_grab, 0);
     c.wave_scratch = b->d_wave_scratch;
     c.hash_bits = b->method == MK_METHOD_CORES ? core_hash_bits(b->k) : enum_hash_bits(b->k);
+    c.variant = b->variant;
+    c.marks = b->d_marks;
+    c.mark_stride = b->mark_stride;
     return c;
+}
+
+// typed adjacency of every graph (from bit matrices or by sorting lists)
+static int batch_enqueue_typed(mk_batch *b, hipStream_t stream)
+{
+    if (b->adjacency == MK_ADJ_LISTS)
+        return launch_typed_lists(b->d_graphs, b->ng, b->max_n, b->max_m, b->total_n, b->total_m,
+                                  2 * b->seg_cap, b->d_ws, b->d_counters, stream);
+    return launch_typed_csr(b->d_graphs, b->ng, b->max_n, b->max_m, b->bits_words, b->d_ws,
+                            b->d_counters, stream);
 }
 
 // enqueue the preparation part of one pass on stream: counters and
@@ -160,8 +189,7 @@ static int batch_enqueue_prep(mk_batch *b, unsigned long long *hist, hipStream_t
     if (rc) return rc;
     rc = fill_u32(hist, 0, (size_t)b->ng * b->table->num_classes * 2, stream);
     if (rc) return rc;
-    rc = launch_typed_csr(b->d_graphs, b->ng, b->max_n, b->max_m, b->bits_words, b->d_ws,
-                          b->d_counters, stream);
+    rc = batch_enqueue_typed(b, stream);
     if (rc) return rc;
     return launch_plan(b->plan_k, b->d_graphs, b->ng, b->max_nnz, b->total_slots, b->d_slot_cnt,
                        b->d_slot_off, b->d_slot_est, b->d_slot_vi, b->d_scan_tmp, b->d_units,
@@ -223,20 +251,16 @@ extern "C" int mk_batch_create(mk_ctx *ctx, const mk_graph *const *gs, int32_t n
     b->ng = ng;
     b->graphs.assign(gs, gs + ng);
     if (opts) b->opts = *opts;
-    if (b->opts.method < MK_METHOD_AUTO || b->opts.method > MK_METHOD_CORES) {
+    if (b->opts.method < MK_METHOD_AUTO || b->opts.method > MK_METHOD_CORES ||
+        b->opts.adjacency < MK_ADJ_AUTO || b->opts.adjacency > MK_ADJ_LISTS ||
+        b->opts.marks < MK_MARKS_AUTO || b->opts.marks > MK_MARKS_GLOBAL) {
         delete b;
-        return fail(MK_EINVAL, "mk_batch_create: unknown method %d", opts->method);
+        return fail(MK_EINVAL, "mk_batch_create: unknown method %d, adjacency %d or marks %d",
+                    b->opts.method, b->opts.adjacency, b->opts.marks);
     }
-    // the library's choice: counting from the (k-2)-sets is the faster on
-    // sparse graphs for k <= 5; for k = 6 the per-core work (up to 255 cells)
-    // costs more than enumerating the k-sets
-    b->method = b->opts.method != MK_METHOD_AUTO ? b->opts.method
-                                                 : (b->k <= 5 ? MK_METHOD_CORES : MK_METHOD_ESU);
-    b->plan_k = b->method == MK_METHOD_CORES ? (b->k == 3 ? 2 : b->k - 1) : b->k;
-    if (b->opts.split_threshold == 0) b->opts.split_threshold = kDefaultSplit[b->plan_k];
-    if (b->opts.use_graph == 0) b->opts.use_graph = 1;
 
-    // workspace layout: [bits of every graph][urow of every graph][uadj ...]
+    // workspace layout: [bit matrices of every graph, or the list-build
+    // arrays][urow of every graph][uadj ...]
     std::vector<DevGraph> hg(ng);
     uint64_t bits = 0, rows = 0, adj = 0, slots = 0;
     for (int i = 0; i < ng; ++i) {
@@ -250,18 +274,56 @@ extern "C" int mk_batch_create(mk_ctx *ctx, const mk_graph *const *gs, int32_t n
         b->seg_cap = std::max(b->seg_cap, g->max_udeg);
         b->max_nnz = std::max<int64_t>(b->max_nnz, g->nnz_u);
         b->max_m = std::max<int64_t>(b->max_m, g->m);
+        b->total_n += (uint64_t)g->n;
+        b->total_m += (uint64_t)g->m;
         slots += (uint64_t)g->nnz_u;
     }
-    if (slots >= 0xFFFFFFFFull) {
+    if (slots >= 0xFFFFFFFFull || 2 * b->total_m >= 0xFFFFFFFFull || b->total_n >= 0x7FFFFFFFull) {
         delete b;
-        return fail(MK_ERANGE, "batch too large: %llu adjacency entries", (unsigned long long)slots);
+        return fail(MK_ERANGE, "batch too large: %llu adjacency entries, %llu arcs",
+                    (unsigned long long)slots, (unsigned long long)b->total_m);
     }
-    b->bits_words = bits;
+
+    // where the marks live, how arcs are tested, the counting method
+    const bool big = b->max_n > MK_LDS_MARKS_MAX_VERTICES;
+    b->marks = b->opts.marks != MK_MARKS_AUTO ? b->opts.marks
+                                              : (big ? MK_MARKS_GLOBAL : MK_MARKS_LDS);
+    b->adjacency = b->opts.adjacency != MK_ADJ_AUTO
+                       ? b->opts.adjacency
+                       : (b->marks == MK_MARKS_GLOBAL ? MK_ADJ_LISTS : MK_ADJ_BITS);
+    // the library's choice of method: counting from the (k-2)-sets is the
+    // faster on sparse graphs for k <= 5; for k = 6 the per-core work (up to
+    // 255 cells) costs more than enumerating the k-sets
+    b->method = b->opts.method != MK_METHOD_AUTO
+                    ? b->opts.method
+                    : (b->k <= 5 && b->marks == MK_MARKS_LDS ? MK_METHOD_CORES : MK_METHOD_ESU);
+    if (b->marks == MK_MARKS_LDS && big) {
+        delete b;
+        return fail(MK_ERANGE, "n=%d exceeds MK_LDS_MARKS_MAX_VERTICES=%d for MK_MARKS_LDS",
+                    b->max_n, MK_LDS_MARKS_MAX_VERTICES);
+    }
+    if (b->marks == MK_MARKS_GLOBAL && b->adjacency != MK_ADJ_LISTS) {
+        delete b;
+        return fail(MK_EINVAL, "MK_MARKS_GLOBAL needs MK_ADJ_LISTS");
+    }
+    if (b->method == MK_METHOD_CORES && b->marks != MK_MARKS_LDS) {
+        delete b;
+        return fail(MK_ERANGE, "MK_METHOD_CORES needs LDS marks (n <= %d)",
+                    MK_LDS_MARKS_MAX_VERTICES);
+    }
+    b->variant = (b->adjacency == MK_ADJ_LISTS ? kVarSearch : 0) |
+                 (b->marks == MK_MARKS_GLOBAL ? kVarGlobal : 0);
+    b->plan_k = b->method == MK_METHOD_CORES ? (b->k == 3 ? 2 : b->k - 1) : b->k;
+    if (b->opts.split_threshold == 0) b->opts.split_threshold = kDefaultSplit[b->plan_k];
+    if (b->opts.use_graph == 0) b->opts.use_graph = 1;
+
+    b->bits_words = b->adjacency == MK_ADJ_BITS ? bits : 0;
+    const uint64_t region = b->adjacency == MK_ADJ_BITS ? bits : list_ws_words(b->total_n, b->total_m);
     b->total_slots = (uint32_t)slots;
     b->seg_cap = std::max(b->seg_cap, 1);
     b->lds_bytes = b->method == MK_METHOD_CORES
                        ? core_lds_bytes(b->k, std::max(b->max_n, 1), b->seg_cap)
-                       : enum_lds_bytes(b->k, std::max(b->max_n, 1), b->seg_cap);
+                       : enum_lds_bytes(b->k, std::max(b->max_n, 1), b->seg_cap, b->variant);
     if ((size_t)b->lds_bytes > ctx->max_lds) {
         delete b;
         return fail(MK_ERANGE, "graphs need %d bytes of LDS per wave (limit %zu)", b->lds_bytes,
@@ -281,19 +343,22 @@ extern "C" int mk_batch_create(mk_ctx *ctx, const mk_graph *const *gs, int32_t n
                              hipGetErrorString(e_)));                                          \
     } while (0)
 
-    BAIL_HIP(hipMalloc(&b->d_ws, sizeof(uint32_t) * std::max<uint64_t>(bits + rows + adj, 1)));
+    BAIL_HIP(hipMalloc(&b->d_ws, sizeof(uint32_t) * std::max<uint64_t>(region + rows + adj, 1)));
     {
-        uint64_t ob = 0, orow = bits, oadj = bits + rows, oslot = 0;
+        const bool with_bits = b->adjacency == MK_ADJ_BITS;
+        uint64_t ob = 0, orow = region, oadj = region + rows, oslot = 0, vbase = 0;
         for (int i = 0; i < ng; ++i) {
             const mk_graph *g = gs[i];
             DevGraph d;
             std::memset(&d, 0, sizeof(d));
             d.n = g->n;
-            d.words = (g->n + 31) / 32;
+            d.words = with_bits ? (g->n + 31) / 32 : 0;
             d.out_row = g->d_row;
             d.out_col = g->d_col;
-            d.bits_out = b->d_ws + ob;
-            d.bits_in = b->d_ws + ob + (uint64_t)g->n * d.words;
+            d.bits_out = with_bits ? b->d_ws + ob : nullptr;
+            d.bits_in = with_bits ? b->d_ws + ob + (uint64_t)g->n * d.words : nullptr;
+            d.vbase = (uint32_t)vbase;
+            vbase += (uint64_t)g->n;
             d.urow = reinterpret_cast<int32_t *>(b->d_ws + orow);
             d.uadj = b->d_ws + oadj;
             d.slot_base = (uint32_t)oslot;
@@ -319,17 +384,24 @@ extern "C" int mk_batch_create(mk_ctx *ctx, const mk_graph *const *gs, int32_t n
 
     int per_cu = 0;
     rc = b->method == MK_METHOD_CORES ? core_max_blocks_per_cu(b->k, b->lds_bytes, &per_cu)
-                                      : enum_max_blocks_per_cu(b->k, b->lds_bytes, &per_cu);
+                                      : enum_max_blocks_per_cu(b->k, b->variant, b->lds_bytes, &per_cu);
     if (rc) return bail(rc);
     if (b->opts.waves_per_cu > 0) per_cu = std::min(per_cu, b->opts.waves_per_cu);
     per_cu = std::max(per_cu, 1);
     b->max_grid = per_cu * ctx->num_cus;
+    if (b->marks == MK_MARKS_GLOBAL) {
+        // one private marks array per workgroup, rounded to 64 entries; all
+        // of them together within 1/16 of the device memory
+        b->mark_stride = ((size_t)std::max(b->max_n, 1) + 63) & ~(size_t)63;
+        const size_t per_wave = b->mark_stride * (b->k <= 5 ? 2 : 4);
+        const uint64_t budget = (uint64_t)ctx->hbm_bytes / 16;
+        const uint64_t fit = std::max<uint64_t>(budget / per_wave, 1);
+        b->max_grid = (int)std::min<uint64_t>((uint64_t)b->max_grid, fit);
+    }
 
     // sizing pass: typed adjacency + unit counts only
     rc = fill_u32(b->d_counters, 0, kNumCounters, ctx->stream);
-    if (!rc)
-        rc = launch_typed_csr(b->d_graphs, ng, b->max_n, b->max_m, bits, b->d_ws,
-                              b->d_counters, ctx->stream);
+    if (!rc) rc = batch_enqueue_typed(b, ctx->stream);
     if (!rc)
         rc = launch_plan(b->plan_k, b->d_graphs, ng, b->max_nnz, b->total_slots, b->d_slot_cnt,
                          b->d_slot_off, b->d_slot_est, b->d_slot_vi, b->d_scan_tmp, nullptr, 0,
@@ -349,6 +421,15 @@ extern "C" int mk_batch_create(mk_ctx *ctx, const mk_graph *const *gs, int32_t n
     b->grid = (int)std::min<uint64_t>((uint64_t)b->max_grid, std::max<uint64_t>(b->units, 1));
     if (b->method == MK_METHOD_CORES)
         BAIL_HIP(hipMalloc(&b->d_wave_scratch, sizeof(uint32_t) * kParentArcCap * (size_t)b->grid));
+    if (b->marks == MK_MARKS_GLOBAL) {
+        // zero once: every pop restores the marks it changed, so they are
+        // zero again whenever a workgroup finishes a unit
+        b->mark_bytes = b->mark_stride * (b->k <= 5 ? 2 : 4) * (size_t)b->grid;
+        BAIL_HIP(hipMalloc(&b->d_marks, b->mark_bytes));
+        rc = fill_u32(b->d_marks, 0, b->mark_bytes / 4, ctx->stream);
+        if (rc) return bail(rc);
+        BAIL_HIP(hipStreamSynchronize(ctx->stream));
+    }
 #undef BAIL_HIP
     *out = b;
     return MK_OK;
@@ -457,6 +538,8 @@ extern "C" int mk_batch_stats_get(const mk_batch *b, mk_batch_stats *out)
     out->k = b->k;
     out->ng = b->ng;
     out->method = b->method;
+    out->adjacency = b->adjacency;
+    out->marks = b->marks;
     return MK_OK;
 }
 
@@ -468,15 +551,13 @@ uint64_t batch_units(const mk_batch *b) { return b->units; }
 
 uint64_t batch_device_bytes(const mk_batch *b)
 {
-    uint64_t words = 0;
-    for (const mk_graph *g : b->graphs) {
-        const uint64_t n = (uint64_t)g->n, w = (n + 31) / 32;
-        words += 2 * n * w + n + 1 + (uint64_t)g->nnz_u;
-    }
+    uint64_t words = b->adjacency == MK_ADJ_BITS ? b->bits_words
+                                                 : list_ws_words(b->total_n, b->total_m);
+    for (const mk_graph *g : b->graphs) words += (uint64_t)g->n + 1 + (uint64_t)g->nnz_u;
     return 4 * words + 16ull * b->total_slots + 4 * scan_tmp_words(b->total_slots) +
            16ull * b->unit_cap + 8ull * b->ng * b->table->num_classes +
            sizeof(DevGraph) * b->graphs.size() + 4 * kNumCounters +
-           (b->d_wave_scratch ? 4ull * kParentArcCap * (uint64_t)b->grid : 0);
+           (b->d_wave_scratch ? 4ull * kParentArcCap * (uint64_t)b->grid : 0) + b->mark_bytes;
 }
 
 // typed adjacency + plan into the batch's own histogram buffer
@@ -600,6 +681,7 @@ extern "C" int mk_autotune(mk_ctx *ctx, const mk_graph *const *gs, int32_t ng, c
     auto trial = [&](mk_batch_opts o) -> int {
         double ms = 0;
         int r = time_candidate(ctx, gs, ng, t, o, trials, &ms, &h);
+        if (r == MK_ERANGE) return MK_OK;  // not applicable to these graphs
         if (r) return r;
         if (h != ref) return fail(MK_EDEVICE, "mk_autotune: a candidate changed the histograms");
         if (ms < cur_ms) {
@@ -608,11 +690,24 @@ extern "C" int mk_autotune(mk_ctx *ctx, const mk_graph *const *gs, int32_t ng, c
         }
         return MK_OK;
     };
-    // coordinate search: method, split floor, units per grab, waves per CU
+    // coordinate search: method, arc tests, split floor, units per grab,
+    // waves per CU
     {
         mk_batch_opts o = cur;
         o.method = MK_METHOD_CORES;
         if ((rc = trial(o))) return rc;
+    }
+    {
+        int max_n = 0;
+        for (int i = 0; i < ng; ++i) max_n = std::max(max_n, gs[i]->n);
+        if (max_n <= MK_LDS_MARKS_MAX_VERTICES) {
+            const mk_batch_opts base0 = cur;
+            for (int a : {MK_ADJ_BITS, MK_ADJ_LISTS}) {
+                mk_batch_opts o = base0;
+                o.adjacency = a;
+                if ((rc = trial(o))) return rc;
+            }
+        }
     }
     static const uint64_t floors[] = {1u << 10, 1u << 14, 1u << 18, 1u << 22};
     const mk_batch_opts base1 = cur;

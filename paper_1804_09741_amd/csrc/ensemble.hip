@@ -327,6 +327,9 @@ extern "C" int mk_randomise(mk_ctx *ctx, const mk_graph *g, int32_t count, uint6
     if (count < 0) return fail(MK_EINVAL, "mk_randomise: count=%d < 0", count);
     if (g->ctx != ctx) return fail(MK_EINVAL, "mk_randomise: graph of another context");
     for (int i = 0; i < count; ++i) out[i] = nullptr;
+    // each chain keeps an n x n arc bit matrix
+    if (g->n > MK_LDS_MARKS_MAX_VERTICES)
+        return fail(MK_ERANGE, "mk_randomise: n=%d exceeds %d", g->n, MK_LDS_MARKS_MAX_VERTICES);
     if (count == 0) return MK_OK;
     std::lock_guard<std::recursive_mutex> lock(ctx->mu);
     MK_HIP(hipSetDevice(ctx->device));

@@ -47,8 +47,8 @@
 namespace mk {
 
 // last level: members s_0..s_{K-2}; every extension vertex closes a k-set
-template <int K>
-__device__ __forceinline__ void leaf(EnumState<K> &s, const int (&st)[K - 1], uint32_t code)
+template <int K, int V>
+__device__ __forceinline__ void leaf(EnumState<K, V> &s, const int (&st)[K - 1], uint32_t code)
 {
     const int lane = lane_id();
     int rem[K - 1];
@@ -86,8 +86,8 @@ __device__ __forceinline__ void leaf(EnumState<K> &s, const int (&st)[K - 1], ui
 
 // Position in seg storage of element a of an extension list made of the
 // tails seg[q][st[q]:] (rem[q] elements each), q < NQ.
-template <int K, int NQ>
-__device__ __forceinline__ int ext_addr(const EnumState<K> &s, const int (&st)[K - 1],
+template <int K, int NQ, int V>
+__device__ __forceinline__ int ext_addr(const EnumState<K, V> &s, const int (&st)[K - 1],
                                         const int (&rem)[NQ], int a)
 {
     int addr = 0;
@@ -107,12 +107,16 @@ __device__ __forceinline__ int ext_addr(const EnumState<K> &s, const int (&st)[K
 }
 
 // two-bit relation of w to u: bit0 arc w -> u, bit1 arc u -> w
-template <int K>
-__device__ __forceinline__ uint32_t pair_type(const EnumState<K> &s, uint32_t w, uint32_t u)
+template <int K, int V>
+__device__ __forceinline__ uint32_t pair_type(const EnumState<K, V> &s, uint32_t w, uint32_t u)
 {
-    const size_t word = (size_t)w * s.words + (u >> 5);
-    const uint32_t sh = u & 31u;
-    return ((s.bits_out[word] >> sh) & 1u) | (((s.bits_in[word] >> sh) & 1u) << 1);
+    if constexpr ((V & kVarSearch) != 0) {
+        return list_relation(s.urow, s.uadj, w, u);
+    } else {
+        const size_t word = (size_t)w * s.words + (u >> 5);
+        const uint32_t sh = u & 31u;
+        return ((s.bits_out[word] >> sh) & 1u) | (((s.bits_in[word] >> sh) & 1u) << 1);
+    }
 }
 
 
@@ -127,8 +131,8 @@ __device__ __forceinline__ uint32_t from_lane(uint32_t v, int l)
 // jlo..e-1: lane l holds E[l] with its code bits for positions k-2 and k-1
 // and its list row, so pair and neighbour items fetch them with one lane
 // permute each; pairs and neighbours share wave iterations.
-template <int K>
-__device__ void last_two_small(EnumState<K> &s, const int (&st)[K - 1],
+template <int K, int V>
+__device__ void last_two_small(EnumState<K, V> &s, const int (&st)[K - 1],
                                const int (&rem)[K - 2], int e, uint32_t code, int jlo)
 {
     constexpr int NQ = K - 2;
@@ -241,8 +245,8 @@ __device__ void last_two_small(EnumState<K> &s, const int (&st)[K - 1],
 // Part B is counted as in last_two_small.
 constexpr uint32_t kETag = 1u << 30;  // mark bits 24..29: the vertex's lane
 
-template <int K>
-__device__ void last_two_cells(EnumState<K> &s, const int (&st)[K - 1],
+template <int K, int V>
+__device__ void last_two_cells(EnumState<K, V> &s, const int (&st)[K - 1],
                                const int (&rem)[K - 2], int e, uint32_t code, int jlo)
 {
     static_assert(K == 6, "E tags need the 32-bit marks of k = 6");
@@ -416,8 +420,8 @@ __device__ void last_two_cells(EnumState<K> &s, const int (&st)[K - 1],
 //       to X, its relation to w is the type of the entry in w's list (the
 //       neighbour-list scan of Algorithm 3).
 // (A) and (B) together are exactly ESU's extension list of the child w.
-template <int K>
-__device__ void last_two(EnumState<K> &s, const int (&st)[K - 1], uint32_t code, int jlo, int jhi)
+template <int K, int V>
+__device__ void last_two(EnumState<K, V> &s, const int (&st)[K - 1], uint32_t code, int jlo, int jhi)
 {
     constexpr int NQ = K - 2;
     constexpr int P1 = K - 2, P2 = K - 1;
@@ -445,16 +449,21 @@ __device__ void last_two(EnumState<K> &s, const int (&st)[K - 1], uint32_t code,
     for (; i0 < hi && e - 1 - i0 >= kRowMin; ++i0) {
         const uint32_t w = (uint32_t)uniform((int)s.seg[ext_addr<K, NQ>(s, st, rem, i0)]);
         const uint32_t cw = code | code_bits<K>((uint32_t)uniform((int)s.mark[w]), P1);
-        const uint32_t *bo = s.bits_out + (size_t)w * s.words;
-        const uint32_t *bi = s.bits_in + (size_t)w * s.words;
+        const size_t wrow = (V & kVarSearch) != 0 ? 0 : (size_t)w * s.words;
         for (int jb = i0 + 1; jb < e; jb += kWave) {
             const int j = jb + lane;
             const bool valid = j < e;
             uint32_t c = 0;
             if (valid) {
                 const uint32_t u = s.seg[ext_addr<K, NQ>(s, st, rem, j)];
-                const uint32_t sh = u & 31u;
-                const uint32_t t = ((bo[u >> 5] >> sh) & 1u) | (((bi[u >> 5] >> sh) & 1u) << 1);
+                uint32_t t;
+                if constexpr ((V & kVarSearch) != 0) {
+                    t = list_relation(s.urow, s.uadj, w, u);
+                } else {
+                    const uint32_t sh = u & 31u;
+                    t = ((s.bits_out[wrow + (u >> 5)] >> sh) & 1u) |
+                        (((s.bits_in[wrow + (u >> 5)] >> sh) & 1u) << 1);
+                }
                 c = cw | code_bits<K>(s.mark[u], P2) | ((t & 1u) << B_WU) | ((t >> 1) << B_UW);
             }
             count_codes<K>(s, valid, c);
@@ -583,8 +592,8 @@ __device__ void last_two(EnumState<K> &s, const int (&st)[K - 1], uint32_t code,
 
 // node with members s_0..s_D: visit children jlo..jhi-1 of its extension
 // list (the tails seg[q][st[q]:] for q <= D, in order)
-template <int K, int D>
-__device__ void visit(EnumState<K> &s, const int (&st)[K - 1], uint32_t code, int jlo, int jhi)
+template <int K, int D, int V>
+__device__ void visit(EnumState<K, V> &s, const int (&st)[K - 1], uint32_t code, int jlo, int jhi)
 {
     if constexpr (K == 3 && D == 1) {
         leaf<K>(s, st, code);
@@ -628,8 +637,8 @@ __device__ void visit(EnumState<K> &s, const int (&st)[K - 1], uint32_t code, in
     }
 }
 
-template <int K>
-__device__ void run_unit(EnumState<K> &s, int v, int i, uint32_t range)
+template <int K, int V>
+__device__ void run_unit(EnumState<K, V> &s, int v, int i, uint32_t range)
 {
     s.root = v;
     const Held held0 = push_held<K, 0>(s, v);
@@ -650,6 +659,21 @@ __device__ void run_unit(EnumState<K> &s, int v, int i, uint32_t range)
     pop_held<K, 0>(s, v, held0);
 }
 
+template <int K, int V>
+__device__ __forceinline__ void enum_body(const DevGraph *graphs, const int4 *units,
+                                          uint32_t unit_cap, uint32_t unit_end, uint32_t *counters,
+                                          const uint32_t *table, uint32_t num_classes,
+                                          unsigned long long *hist_base, const EnumConfig &cfg)
+{
+    extern __shared__ uint32_t lds[];
+    EnumState<K, V> s;
+    const LdsLayout lay = lds_layout(K, cfg.max_n, cfg.seg_cap, cfg.hash_bits, (V & kVarGlobal) != 0);
+    init_state(s, reinterpret_cast<char *>(lds), lay, cfg, counters, table, num_classes);
+    for_each_unit<K>(s, graphs, units, unit_cap, unit_end, counters, hist_base, cfg,
+                     [&](int v, int i, uint32_t range) { run_unit<K>(s, v, i, range); });
+}
+
+// bit-matrix arc tests, LDS marks
 template <int K>
 __global__ __launch_bounds__(kWave) void enum_kernel(const DevGraph *graphs, const int4 *units,
                                                      uint32_t unit_cap, uint32_t unit_end,
@@ -658,37 +682,57 @@ __global__ __launch_bounds__(kWave) void enum_kernel(const DevGraph *graphs, con
                                                      unsigned long long *hist_base,
                                                      EnumConfig cfg)
 {
-    extern __shared__ uint32_t lds[];
-    EnumState<K> s;
-    const LdsLayout lay = lds_layout(K, cfg.max_n, cfg.seg_cap, cfg.hash_bits);
-    init_state<K>(s, reinterpret_cast<char *>(lds), lay, cfg, counters, table, num_classes);
-    for_each_unit<K>(s, graphs, units, unit_cap, unit_end, counters, hist_base, cfg,
-                     [&](int v, int i, uint32_t range) { run_unit<K>(s, v, i, range); });
+    enum_body<K, 0>(graphs, units, unit_cap, unit_end, counters, table, num_classes, hist_base, cfg);
+}
+
+// arc tests by list search (V = kVarSearch, optionally | kVarGlobal)
+template <int K, int V>
+__global__ __launch_bounds__(kWave) void enum_lists_kernel(const DevGraph *graphs, const int4 *units,
+                                                           uint32_t unit_cap, uint32_t unit_end,
+                                                           uint32_t *counters,
+                                                           const uint32_t *table, uint32_t num_classes,
+                                                           unsigned long long *hist_base,
+                                                           EnumConfig cfg)
+{
+    enum_body<K, V>(graphs, units, unit_cap, unit_end, counters, table, num_classes, hist_base, cfg);
 }
 
 int enum_hash_bits(int) { return kHashBits; }
 
-int enum_lds_bytes(int k, int max_n, int seg_cap)
+int enum_lds_bytes(int k, int max_n, int seg_cap, int variant)
 {
-    return lds_layout(k, max_n, seg_cap, enum_hash_bits(k)).total;
+    return lds_layout(k, max_n, seg_cap, enum_hash_bits(k), (variant & kVarGlobal) != 0).total;
 }
 
+// the instantiated variants: bit matrices, list search, list search with
+// global marks
 template <int K>
-static const void *enum_fn()
+static const void *enum_fn(int variant)
 {
-    return reinterpret_cast<const void *>(&enum_kernel<K>);
+    switch (variant) {
+    case 0: return reinterpret_cast<const void *>(&enum_kernel<K>);
+    case kVarSearch: return reinterpret_cast<const void *>(&enum_lists_kernel<K, kVarSearch>);
+    case kVarSearch | kVarGlobal:
+        return reinterpret_cast<const void *>(&enum_lists_kernel<K, kVarSearch | kVarGlobal>);
+    default: return nullptr;
+    }
 }
 
-int enum_max_blocks_per_cu(int k, int lds_bytes, int *blocks)
+static const void *enum_fn(int k, int variant)
 {
-    const void *fn = nullptr;
     switch (k) {
-    case 3: fn = enum_fn<3>(); break;
-    case 4: fn = enum_fn<4>(); break;
-    case 5: fn = enum_fn<5>(); break;
-    case 6: fn = enum_fn<6>(); break;
-    default: return fail(MK_ERANGE, "k=%d outside 3..6", k);
+    case 3: return enum_fn<3>(variant);
+    case 4: return enum_fn<4>(variant);
+    case 5: return enum_fn<5>(variant);
+    case 6: return enum_fn<6>(variant);
+    default: return nullptr;
     }
+}
+
+int enum_max_blocks_per_cu(int k, int variant, int lds_bytes, int *blocks)
+{
+    const void *fn = enum_fn(k, variant);
+    if (!fn) return fail(MK_ERANGE, "no enumeration kernel for k=%d, variant %d", k, variant);
     MK_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, fn, kWave, (size_t)lds_bytes));
     return MK_OK;
 }
@@ -699,26 +743,15 @@ int launch_enum(int k, const DevGraph *d_graphs, const int4 *units, uint32_t uni
                 hipStream_t stream)
 {
     if (grid <= 0) return MK_OK;
-    switch (k) {
-    case 3:
-        hipLaunchKernelGGL(enum_kernel<3>, dim3(grid), dim3(kWave), lds_bytes, stream, d_graphs,
-                           units, unit_cap, unit_end, counters, table, num_classes, hist_base, cfg);
-        break;
-    case 4:
-        hipLaunchKernelGGL(enum_kernel<4>, dim3(grid), dim3(kWave), lds_bytes, stream, d_graphs,
-                           units, unit_cap, unit_end, counters, table, num_classes, hist_base, cfg);
-        break;
-    case 5:
-        hipLaunchKernelGGL(enum_kernel<5>, dim3(grid), dim3(kWave), lds_bytes, stream, d_graphs,
-                           units, unit_cap, unit_end, counters, table, num_classes, hist_base, cfg);
-        break;
-    case 6:
-        hipLaunchKernelGGL(enum_kernel<6>, dim3(grid), dim3(kWave), lds_bytes, stream, d_graphs,
-                           units, unit_cap, unit_end, counters, table, num_classes, hist_base, cfg);
-        break;
-    default: return fail(MK_ERANGE, "k=%d outside 3..6", k);
-    }
-    MK_HIP(hipGetLastError());
+    const void *fn = enum_fn(k, cfg.variant);
+    if (!fn) return fail(MK_ERANGE, "no enumeration kernel for k=%d, variant %d", k, cfg.variant);
+    if ((cfg.variant & kVarGlobal) != 0 && !cfg.marks)
+        return fail(MK_EINVAL, "launch_enum: global marks variant without a marks array");
+    EnumConfig c = cfg;
+    void *args[] = {(void *)&d_graphs, (void *)&units, (void *)&unit_cap, (void *)&unit_end,
+                    (void *)&counters, (void *)&table, (void *)&num_classes, (void *)&hist_base,
+                    (void *)&c};
+    MK_HIP(hipLaunchKernel(fn, dim3(grid), dim3(kWave), args, (size_t)lds_bytes, stream));
     return MK_OK;
 }
 

@@ -80,17 +80,23 @@ constexpr uint32_t kPendingMax = 1u << 30;
 // long are processed one at a time with their first vertex wave-uniform.
 constexpr int kRowMin = MK_ROW_MIN;
 
-// Byte offsets of one wave's LDS: marks (n x 2 or 4 bytes), extension
-// segments (u16), scratch, hash keys and counts; each part 4-byte aligned.
+// extension segment entries: u16 vertex ids, u32 with global marks
+template <int V>
+using SegT = typename std::conditional<(V & kVarGlobal) != 0, uint32_t, uint16_t>::type;
+
+// Byte offsets of one wave's LDS: marks (n x 2 or 4 bytes; none when they
+// are in global memory), extension segments (u16, or u32 with global
+// marks), scratch, hash keys and counts; each part 4-byte aligned.
 struct LdsLayout {
     int seg, scratch, total;
 };
 
-__host__ __device__ inline LdsLayout lds_layout(int k, int max_n, int seg_cap, int hash_bits)
+__host__ __device__ inline LdsLayout lds_layout(int k, int max_n, int seg_cap, int hash_bits,
+                                                bool global_marks = false)
 {
     const int segs = k == 3 ? 2 : k - 2;
-    const int mark_bytes = ((k <= 5 ? 2 : 4) * max_n + 3) & ~3;
-    const int seg_bytes = (2 * segs * seg_cap + 3) & ~3;
+    const int mark_bytes = global_marks ? 0 : (((k <= 5 ? 2 : 4) * max_n + 3) & ~3);
+    const int seg_bytes = ((global_marks ? 4 : 2) * segs * seg_cap + 3) & ~3;
     LdsLayout l;
     l.seg = mark_bytes;
     l.scratch = l.seg + seg_bytes;
@@ -105,13 +111,13 @@ __host__ __device__ inline LdsLayout lds_layout(int k, int max_n, int seg_cap, i
 template <int K>
 using MarkT = typename std::conditional<K <= 5, uint16_t, uint32_t>::type;
 
-template <int K>
+template <int K, int V = 0>
 struct EnumState {
     static constexpr int OUTB = (kSegments<K> - 1) * (K - 1) + 1;
     static constexpr uint32_t INMASK = (1u << OUTB) - 1u;
     static_assert(OUTB + kSegments<K> <= 8 * (int)sizeof(MarkT<K>), "mark bits do not fit");
-    MarkT<K> *mark;
-    uint16_t *seg;              // vertex ids (n <= MK_MAX_VERTICES < 65536)
+    MarkT<K> *mark;             // LDS, or this wave's global array (kVarGlobal)
+    SegT<V> *seg;               // vertex ids
     int seg_cap;
     int root;
     const int32_t *urow;
@@ -161,13 +167,13 @@ __device__ __forceinline__ uint32_t code_bits(uint32_t m, int p)
 
 // s_D := x.  Builds seg[D] (new exclusive extension vertices, ascending) and
 // ORs position D's bits into the marks of x's neighbours.
-template <int K, int D>
-__device__ __forceinline__ void push(EnumState<K> &s, int x)
+template <int K, int D, int V>
+__device__ __forceinline__ void push(EnumState<K, V> &s, int x)
 {
     const int lane = lane_id();
     const int r0 = uniform(s.urow[x]);
     const int r1 = uniform(s.urow[x + 1]);
-    uint16_t *seg = s.seg + D * s.seg_cap;
+    SegT<V> *seg = s.seg + D * s.seg_cap;
     int cnt = 0;
     for (int base = r0; base < r1; base += kWave) {
         const int e = base + lane;
@@ -177,7 +183,7 @@ __device__ __forceinline__ void push(EnumState<K> &s, int x)
         const uint32_t m = valid ? s.mark[y] : 1u;
         const bool fresh = valid && y > s.root && m == 0u;
         const unsigned long long bal = __ballot(fresh);
-        if (fresh) seg[cnt + (int)lanes_below(bal)] = (uint16_t)y;
+        if (fresh) seg[cnt + (int)lanes_below(bal)] = (SegT<V>)y;
         cnt += __popcll(bal);
         if (valid) s.mark[y] = (MarkT<K>)(m | mark_bits<K>(D, ent & 3u));
     }
@@ -186,8 +192,8 @@ __device__ __forceinline__ void push(EnumState<K> &s, int x)
 }
 
 // undo push<D>(x)
-template <int K, int D>
-__device__ __forceinline__ void pop(EnumState<K> &s, int x)
+template <int K, int D, int V>
+__device__ __forceinline__ void pop(EnumState<K, V> &s, int x)
 {
     const int lane = lane_id();
     const int r0 = uniform(s.urow[x]);
@@ -214,8 +220,8 @@ struct Held {
 };
 
 // push<D>(x), keeping the list for pop_held
-template <int K, int D>
-__device__ __forceinline__ Held push_held(EnumState<K> &s, int x)
+template <int K, int D, int V>
+__device__ __forceinline__ Held push_held(EnumState<K, V> &s, int x)
 {
     const int lane = lane_id();
     const int r0 = uniform(s.urow[x]);
@@ -228,14 +234,14 @@ __device__ __forceinline__ Held push_held(EnumState<K> &s, int x)
         push<K, D>(s, x);
         return h;
     }
-    uint16_t *seg = s.seg + D * s.seg_cap;
+    SegT<V> *seg = s.seg + D * s.seg_cap;
     const bool valid = lane < h.n;
     if (valid) h.ent = s.uadj[r0 + lane];
     const int y = (int)(h.ent >> 2);
     if (valid) h.m = s.mark[y];
     const bool fresh = valid && y > s.root && h.m == 0u;
     const unsigned long long bal = __ballot(fresh);
-    if (fresh) seg[(int)lanes_below(bal)] = (uint16_t)y;
+    if (fresh) seg[(int)lanes_below(bal)] = (SegT<V>)y;
     if (valid) s.mark[y] = (MarkT<K>)(h.m | mark_bits<K>(D, h.ent & 3u));
     s.len[D] = __popcll(bal);
     __syncthreads();
@@ -243,8 +249,8 @@ __device__ __forceinline__ Held push_held(EnumState<K> &s, int x)
 }
 
 // undo push_held<D>(x)
-template <int K, int D>
-__device__ __forceinline__ void pop_held(EnumState<K> &s, int x, const Held &h)
+template <int K, int D, int V>
+__device__ __forceinline__ void pop_held(EnumState<K, V> &s, int x, const Held &h)
 {
     if (h.n > kWave) {
         pop<K, D>(s, x);
@@ -255,8 +261,8 @@ __device__ __forceinline__ void pop_held(EnumState<K> &s, int x, const Held &h)
 }
 
 // add n to the histogram bin of code (table lookup + global 64-bit atomic)
-template <int K>
-__device__ __forceinline__ void add_global(EnumState<K> &s, uint32_t code, uint32_t n)
+template <int K, int V>
+__device__ __forceinline__ void add_global(EnumState<K, V> &s, uint32_t code, uint32_t n)
 {
     const uint32_t id = s.class_keys ? code : s.table[code];
     // n is a 32-bit two's complement count (negative only in the (k-2)-set
@@ -266,8 +272,8 @@ __device__ __forceinline__ void add_global(EnumState<K> &s, uint32_t code, uint3
 }
 
 // move the wave's pending counts to the histogram and empty the hash
-template <int K>
-__device__ __forceinline__ void flush_hash(EnumState<K> &s)
+template <int K, int V>
+__device__ __forceinline__ void flush_hash(EnumState<K, V> &s)
 {
     __syncthreads();
     for (int i = lane_id(); i <= (int)s.hmask; i += kWave) {
@@ -286,8 +292,8 @@ __device__ __forceinline__ void flush_hash(EnumState<K> &s)
 // Add n to the pending count of code for every lane with `mine` set: the
 // wave's LDS hash (linear probing); a lane that finds no slot within
 // kHashProbes goes straight to the histogram.  Flushes when half full.
-template <int K>
-__device__ __forceinline__ void hash_insert(EnumState<K> &s, bool mine, uint32_t code, uint32_t n)
+template <int K, int V>
+__device__ __forceinline__ void hash_insert(EnumState<K, V> &s, bool mine, uint32_t code, uint32_t n)
 {
     bool fresh = false;
     if (s.flags & kDebugNoHash) {
@@ -321,8 +327,8 @@ __device__ __forceinline__ void hash_insert(EnumState<K> &s, bool mine, uint32_t
 // count one code per valid lane.  MK_MERGE_ROUNDS ballot rounds merge the
 // lanes that share the first remaining lane's code; every code left goes
 // into the hash.
-template <int K>
-__device__ __forceinline__ void count_codes(EnumState<K> &s, bool valid, uint32_t code)
+template <int K, int V>
+__device__ __forceinline__ void count_codes(EnumState<K, V> &s, bool valid, uint32_t code)
 {
     const int lane = lane_id();
     unsigned long long act = __ballot(valid);
@@ -344,8 +350,8 @@ __device__ __forceinline__ void count_codes(EnumState<K> &s, bool valid, uint32_
 
 
 // count codes with weight -1 (merged like count_codes)
-template <int K>
-__device__ __forceinline__ void uncount_codes(EnumState<K> &s, bool valid, uint32_t code)
+template <int K, int V>
+__device__ __forceinline__ void uncount_codes(EnumState<K, V> &s, bool valid, uint32_t code)
 {
     const int lane = lane_id();
     unsigned long long act = __ballot(valid);
@@ -361,13 +367,16 @@ __device__ __forceinline__ void uncount_codes(EnumState<K> &s, bool valid, uint3
 }
 
 // Set up a wave's state on its LDS (marks zero, hash empty).
-template <int K>
-__device__ __forceinline__ void init_state(EnumState<K> &s, char *base, const LdsLayout &lay,
+template <int K, int V>
+__device__ __forceinline__ void init_state(EnumState<K, V> &s, char *base, const LdsLayout &lay,
                                            const EnumConfig &cfg, uint32_t *counters,
                                            const uint32_t *table, uint32_t num_classes)
 {
-    s.mark = reinterpret_cast<MarkT<K> *>(base);
-    s.seg = reinterpret_cast<uint16_t *>(base + lay.seg);
+    if constexpr ((V & kVarGlobal) != 0)
+        s.mark = reinterpret_cast<MarkT<K> *>(cfg.marks) + (size_t)blockIdx.x * cfg.mark_stride;
+    else
+        s.mark = reinterpret_cast<MarkT<K> *>(base);
+    s.seg = reinterpret_cast<SegT<V> *>(base + lay.seg);
     s.seg_cap = cfg.seg_cap;
     s.flags = cfg.flags;
     s.scratch = reinterpret_cast<uint32_t *>(base + lay.scratch);
@@ -392,7 +401,9 @@ __device__ __forceinline__ void init_state(EnumState<K> &s, char *base, const Ld
     s.urow = nullptr;
     s.uadj = nullptr;
     s.hist = nullptr;
-    for (int i = lane_id(); i < cfg.max_n; i += kWave) s.mark[i] = 0;
+    // global marks are zeroed when allocated and every pop restores them
+    if constexpr ((V & kVarGlobal) == 0)
+        for (int i = lane_id(); i < cfg.max_n; i += kWave) s.mark[i] = 0;
     __syncthreads();
 }
 
@@ -400,8 +411,8 @@ __device__ __forceinline__ void init_state(EnumState<K> &s, char *base, const Ld
 // first) and call run(v, i, range) for each, switching the graph (and
 // flushing the hash) when the unit's graph changes.  The hash is flushed at
 // the end.
-template <int K, typename Run>
-__device__ __forceinline__ void for_each_unit(EnumState<K> &s, const DevGraph *graphs,
+template <int K, int V, typename Run>
+__device__ __forceinline__ void for_each_unit(EnumState<K, V> &s, const DevGraph *graphs,
                                               const int4 *units, uint32_t unit_cap,
                                               uint32_t unit_end, uint32_t *counters,
                                               unsigned long long *hist_base, const EnumConfig &cfg,

@@ -129,6 +129,179 @@ int launch_typed_csr(const DevGraph *d_graphs, int ng, int max_n, int64_t max_m,
     return MK_OK;
 }
 
+// ------------------------------------------------ typed lists, no matrices
+//
+// For graphs whose n x n bit matrices would be too large (and as a variant
+// for any graph): every arc u -> v gives a raw entry (v << 2 | 1) to u and
+// (u << 2 | 2) to v; each vertex's raw entries are sorted (then the two
+// entries of a bidirected pair are adjacent) and merged into one typed entry
+// per neighbour.  Per-vertex arrays of the whole batch are indexed by
+// vbase + v:
+//   cnt[N]      raw counts, then merged degrees
+//   roff[N+1]   exclusive scan of the raw counts
+//   raw[2M]     raw entries, merged lists at the front of each vertex's range
+//   uoff[N+1]   exclusive scan of the merged degrees
+//   tmp         scan workspace
+
+static uint64_t list_tmp_words(uint64_t total_n) { return scan_tmp_words(total_n + 1); }
+
+uint64_t list_ws_words(uint64_t total_n, uint64_t total_m)
+{
+    return total_n + 2 * (total_n + 1) + 2 * total_m + list_tmp_words(total_n);
+}
+
+// arc e of the out-CSR: tail by binary search
+__device__ __forceinline__ int arc_tail(const DevGraph &g, int e)
+{
+    int lo = 0, hi = g.n;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (g.out_row[mid] <= e) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+__global__ void rawcount_kernel(const DevGraph *graphs, uint32_t *cnt)
+{
+    const DevGraph &g = graphs[blockIdx.y];
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g.n == 0 || e >= g.out_row[g.n]) return;
+    const int u = arc_tail(g, e), v = g.out_col[e];
+    atomicAdd(&cnt[g.vbase + u], 1u);
+    atomicAdd(&cnt[g.vbase + v], 1u);
+}
+
+// each end takes a slot counting down from the end of its range; cnt ends at 0
+__global__ void rawfill_kernel(const DevGraph *graphs, uint32_t *cnt, const uint32_t *roff,
+                               uint32_t *raw)
+{
+    const DevGraph &g = graphs[blockIdx.y];
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g.n == 0 || e >= g.out_row[g.n]) return;
+    const int u = arc_tail(g, e), v = g.out_col[e];
+    const uint32_t xu = g.vbase + (uint32_t)u, xv = g.vbase + (uint32_t)v;
+    raw[roff[xu] + atomicSub(&cnt[xu], 1u) - 1u] = ((uint32_t)v << 2) | 1u;
+    raw[roff[xv] + atomicSub(&cnt[xv], 1u) - 1u] = ((uint32_t)u << 2) | 2u;
+}
+
+// One wave per vertex: bitonic sort of its raw entries in LDS (padded to a
+// power of two with all-ones), then one typed entry per neighbour written
+// to the front of its raw range; cnt receives the merged degree.
+__global__ __launch_bounds__(kWave) void merge_kernel(const DevGraph *graphs, uint32_t *cnt,
+                                                      const uint32_t *roff, uint32_t *raw)
+{
+    extern __shared__ uint32_t buf[];
+    const DevGraph &g = graphs[blockIdx.y];
+    const int v = blockIdx.x;
+    if (v >= g.n) return;
+    const int lane = threadIdx.x;
+    const uint32_t x = g.vbase + (uint32_t)v;
+    const uint32_t r0 = roff[x];
+    const int len = (int)(roff[x + 1] - r0);
+    int p = kWave;
+    while (p < len) p <<= 1;
+    for (int i = lane; i < p; i += kWave) buf[i] = i < len ? raw[r0 + i] : 0xFFFFFFFFu;
+    __syncthreads();
+    for (int size = 2; size <= p; size <<= 1) {
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            for (int t = lane; t < p / 2; t += kWave) {
+                const int i = 2 * t - (t & (stride - 1));
+                const int j = i + stride;
+                const uint32_t a = buf[i], b = buf[j];
+                const bool up = (i & size) == 0;
+                if ((a > b) == up) {
+                    buf[i] = b;
+                    buf[j] = a;
+                }
+            }
+            __syncthreads();
+        }
+    }
+    int out = 0;
+    for (int base = 0; base < len; base += kWave) {
+        const int i = base + lane;
+        uint32_t key = 0, t = 0;
+        bool head = false;
+        if (i < len) {
+            key = buf[i];
+            head = i == 0 || (buf[i - 1] >> 2) != (key >> 2);
+            t = key & 3u;
+            if (head && i + 1 < len && (buf[i + 1] >> 2) == (key >> 2)) t |= buf[i + 1] & 3u;
+        }
+        const unsigned long long bal = __ballot(head);
+        if (head)
+            raw[r0 + out + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32),
+                                                         __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u))] =
+                (key & ~3u) | t;
+        out += __popcll(bal);
+    }
+    if (lane == 0) cnt[x] = (uint32_t)out;
+}
+
+// One wave per vertex: its merged list to the graph's uadj, its offset to
+// urow (positions from the batch-wide scan, less the graph's first).
+__global__ __launch_bounds__(kWave) void place_kernel(const DevGraph *graphs, const uint32_t *cnt,
+                                                      const uint32_t *roff, const uint32_t *uoff,
+                                                      const uint32_t *raw, uint32_t *counters)
+{
+    const DevGraph &g = graphs[blockIdx.y];
+    const int v = blockIdx.x;
+    const int lane = threadIdx.x;
+    if (g.n == 0) {
+        if (v == 0 && lane == 0) g.urow[0] = 0;
+        return;
+    }
+    if (v >= g.n) return;
+    const uint32_t x = g.vbase + (uint32_t)v;
+    const uint32_t d = cnt[x];
+    const uint32_t pos = uoff[x] - uoff[g.vbase];
+    if ((uint64_t)pos + d > g.nnz_cap) {
+        if (lane == 0) atomicAdd(&counters[kAdjOverflow], 1u);
+        return;
+    }
+    for (uint32_t i = lane; i < d; i += kWave) g.uadj[pos + i] = raw[roff[x] + i];
+    if (lane == 0) {
+        g.urow[v] = (int32_t)pos;
+        if (v == g.n - 1) g.urow[g.n] = (int32_t)(pos + d);
+    }
+}
+
+int launch_typed_lists(const DevGraph *d_graphs, int ng, int max_n, int64_t max_m,
+                       uint64_t total_n, uint64_t total_m, int max_raw, uint32_t *lists,
+                       uint32_t *counters, hipStream_t stream)
+{
+    if (ng <= 0) return MK_OK;
+    uint32_t *cnt = lists;
+    uint32_t *roff = cnt + total_n;
+    uint32_t *raw = roff + total_n + 1;
+    uint32_t *uoff = raw + 2 * total_m;
+    uint32_t *tmp = uoff + total_n + 1;
+    int rc = fill_u32(cnt, 0, std::max<uint64_t>(total_n, 1), stream);
+    if (rc != MK_OK) return rc;
+    const dim3 agrid((unsigned)std::max<int64_t>((max_m + kRowThreads - 1) / kRowThreads, 1),
+                     (unsigned)ng);
+    hipLaunchKernelGGL(rawcount_kernel, agrid, dim3(kRowThreads), 0, stream, d_graphs, cnt);
+    MK_HIP(hipGetLastError());
+    rc = scan_u32(cnt, roff, total_n, 0, roff + total_n, tmp, stream);
+    if (rc != MK_OK) return rc;
+    hipLaunchKernelGGL(rawfill_kernel, agrid, dim3(kRowThreads), 0, stream, d_graphs, cnt, roff,
+                       raw);
+    MK_HIP(hipGetLastError());
+    int p = kWave;
+    while (p < max_raw) p <<= 1;
+    const dim3 vgrid((unsigned)std::max(max_n, 1), (unsigned)ng);
+    hipLaunchKernelGGL(merge_kernel, vgrid, dim3(kWave), sizeof(uint32_t) * (size_t)p, stream,
+                       d_graphs, cnt, roff, raw);
+    MK_HIP(hipGetLastError());
+    rc = scan_u32(cnt, uoff, total_n, 0, uoff + total_n, tmp, stream);
+    if (rc != MK_OK) return rc;
+    hipLaunchKernelGGL(place_kernel, vgrid, dim3(kWave), 0, stream, d_graphs, cnt, roff, uoff,
+                       raw, counters);
+    MK_HIP(hipGetLastError());
+    return MK_OK;
+}
+
 }  // namespace mk
 
 using namespace mk;

@@ -67,7 +67,30 @@ struct DevGraph {
     uint32_t *uadj;           // (u << 2) | type; type bit0: v -> u, bit1: u -> v
     uint32_t slot_base;       // first planner slot of this graph
     uint32_t nnz_cap;         // entries reserved for uadj (host-computed sum of |delta(v)|)
+    uint32_t vbase;           // index of vertex 0 in the batch's per-vertex arrays
+                              // (list-built adjacency); bits_* are null then
 };
+
+// Two-bit relation of w to u read from the sorted typed lists (bit0: arc
+// w -> u, bit1: arc u -> w; 0 when not adjacent): a binary search for u in
+// w's list or for w in u's, whichever list is shorter.
+__device__ __forceinline__ uint32_t list_relation(const int32_t *urow, const uint32_t *uadj,
+                                                  uint32_t w, uint32_t u)
+{
+    const int a0 = urow[w], a1 = urow[w + 1], b0 = urow[u], b1 = urow[u + 1];
+    const bool sw = b1 - b0 < a1 - a0;
+    int lo = sw ? b0 : a0;
+    const int end = sw ? b1 : a1;
+    const uint32_t key = sw ? w : u;
+    int hi = end;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if ((uadj[mid] >> 2) < key) lo = mid + 1;
+        else hi = mid;
+    }
+    const uint32_t t = (lo < end && (uadj[lo] >> 2) == key) ? (uadj[lo] & 3u) : 0u;
+    return sw ? (((t & 1u) << 1) | (t >> 1)) : t;
+}
 
 // Work unit of the enumeration queue.
 //   x: graph index in the batch, y: root vertex v,
@@ -121,6 +144,12 @@ int build_table(Table *t, hipStream_t stream);
 
 // Typed symmetric adjacency of every graph of a batch (bit matrices
 // zeroed, arcs set, degrees counted and scanned, lists written).
+// Typed adjacency without bit matrices: raw out/in entries per vertex,
+// sorted and merged per vertex.  `lists` holds list_ws_words() words.
+uint64_t list_ws_words(uint64_t total_n, uint64_t total_m);
+int launch_typed_lists(const DevGraph *d_graphs, int ng, int max_n, int64_t max_m,
+                       uint64_t total_n, uint64_t total_m, int max_raw, uint32_t *lists,
+                       uint32_t *counters, hipStream_t stream);
 int launch_typed_csr(const DevGraph *d_graphs, int ng, int max_n, int64_t max_m,
                      uint64_t bits_words_total, uint32_t *bits_base, uint32_t *counters,
                      hipStream_t stream);
@@ -134,11 +163,22 @@ int launch_plan(int k, const DevGraph *d_graphs, int ng, int64_t max_nnz, uint32
                 uint32_t waves, uint32_t *counters, hipStream_t stream);
 
 // Enumeration + code + lookup + histogram over the queued units.
-int enum_lds_bytes(int k, int max_n, int seg_cap);
-int enum_max_blocks_per_cu(int k, int lds_bytes, int *blocks);
+int enum_lds_bytes(int k, int max_n, int seg_cap, int variant);
+int enum_max_blocks_per_cu(int k, int variant, int lds_bytes, int *blocks);
 constexpr uint32_t kAllUnits = 0xFFFFFFFFu;
 
 // Launch configuration of the enumeration kernel.
+// Variants of the enumeration walk (template parameter V of its state and
+// kernels):
+//   kVarSearch  arc tests between extension vertices search the sorted typed
+//               lists (the shorter of the two) instead of reading n x n bit
+//               matrices, so no bit matrix is built;
+//   kVarGlobal  every wave's marks live in a private n-entry array in global
+//               memory instead of LDS, and extension segments hold u32 ids:
+//               graphs with more vertices than LDS marks can hold.
+constexpr int kVarSearch = 1;
+constexpr int kVarGlobal = 2;
+
 struct EnumConfig {
     int max_n;       // largest n of the batch (LDS marks)
     int seg_cap;     // largest undirected degree (LDS extension segments)
@@ -146,6 +186,9 @@ struct EnumConfig {
     uint32_t chunk;  // units per queue grab; 0 = about 1/16 of a wave's share
     uint32_t *wave_scratch;  // core kernel: kParentArcCap words per workgroup
     int hash_bits;           // log2 of the per-wave hash slots (enum_/core_hash_bits)
+    int variant;             // kVar* bits of the enumeration kernel (esu.h)
+    void *marks;             // kVarGlobal: grid x mark_stride marks, all zero
+    size_t mark_stride;      //   marks per workgroup (>= max_n)
 };
 int enum_hash_bits(int k);
 int core_hash_bits(int k);

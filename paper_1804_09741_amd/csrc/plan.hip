@@ -59,8 +59,10 @@ __device__ __forceinline__ int first_above(const uint32_t *uadj, int r0, int r1,
     return lo;
 }
 
+// bit matrices when the batch has them, else a search of the sorted lists
 __device__ __forceinline__ bool adjacent(const DevGraph &g, int v, int x)
 {
+    if (!g.bits_out) return list_relation(g.urow, g.uadj, (uint32_t)v, (uint32_t)x) != 0u;
     const size_t w = (size_t)v * g.words + (x >> 5);
     return ((g.bits_out[w] | g.bits_in[w]) >> (x & 31)) & 1u;
 }
@@ -82,8 +84,11 @@ __device__ __forceinline__ uint64_t effective_threshold(const uint32_t *counters
 }
 
 // Per-slot record of the estimate pass: (v, i) of a first-level node packed
-// as v | i << 13 (n <= 8192, degrees <= 4096), or kNoNode for a slot whose
-// neighbour is not above its owner.
+// as v | i << 20 (n <= 2^20, degrees <= 4096), or kNoNode for a slot whose
+// neighbour is not above its owner (no node has v = 2^20 - 1, i = 4095: the
+// largest vertex has no neighbour above it).
+constexpr int kViShift = 20;
+constexpr uint32_t kViMask = (1u << kViShift) - 1u;
 constexpr uint32_t kNoNode = 0xFFFFFFFFu;
 
 // greedy ranges over the children of (v, w_i): calls put(r, j0 | j1 << 16)
@@ -168,7 +173,7 @@ __global__ __launch_bounds__(kPlanThreads) void plan_kernel(const DevGraph *grap
                 if constexpr (K == 3) est = (uint64_t)L2 + 1;
                 else split_children<K, false>(g, v, first, r1, i, y, L2, ~0ull, &est,
                                               [](uint32_t, uint32_t) {});
-                vi = (uint32_t)v | ((uint32_t)i << 13);
+                vi = (uint32_t)v | ((uint32_t)i << kViShift);
             }
             slot_vi[slot] = vi;
             slot_est[slot] = est > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)est;
@@ -177,7 +182,7 @@ __global__ __launch_bounds__(kPlanThreads) void plan_kernel(const DevGraph *grap
             const uint32_t sest = slot_est[slot];
             uint32_t cnt = 0;
             if (vi != kNoNode) {
-                const int v = (int)(vi & 0x1FFFu), i = (int)(vi >> 13);
+                const int v = (int)(vi & kViMask), i = (int)(vi >> kViShift);
                 const bool split = K > 3 && sest != 0xFFFFFFFFu && sest > threshold
                                        ? true : (K > 3 && sest == 0xFFFFFFFFu);
                 if (K <= 3) {

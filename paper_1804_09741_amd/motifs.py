@@ -32,8 +32,9 @@ MK_EBUSY = -6
 MK_ETIMEDOUT = -7
 MK_ENOTFOUND = -8
 MK_INVALID_CLASS = 0xFFFFFFFF
-MK_MAX_VERTICES = 8192
+MK_MAX_VERTICES = 1 << 20
 MK_MAX_DEGREE = 4096
+MK_LDS_MARKS_MAX_VERTICES = 8192
 
 NUM_CLASSES = {3: 13, 4: 199, 5: 9364, 6: 1530843}
 
@@ -47,16 +48,20 @@ class MotifsError(RuntimeError):
 class BatchOpts(ctypes.Structure):
     _fields_ = [("split_threshold", ctypes.c_uint64), ("waves_per_cu", ctypes.c_int32),
                 ("use_graph", ctypes.c_int32), ("units_per_grab", ctypes.c_int32),
-                ("debug_flags", ctypes.c_int32), ("method", ctypes.c_int32)]
+                ("debug_flags", ctypes.c_int32), ("method", ctypes.c_int32),
+                ("adjacency", ctypes.c_int32), ("marks", ctypes.c_int32)]
 
 
 METHOD_AUTO, METHOD_ESU, METHOD_CORES = 0, 1, 2
+ADJ_AUTO, ADJ_BITS, ADJ_LISTS = 0, 1, 2
+MARKS_AUTO, MARKS_LDS, MARKS_GLOBAL = 0, 1, 2
 
 
 class BatchStats(ctypes.Structure):
     _fields_ = [("units", ctypes.c_uint64), ("split_pairs", ctypes.c_uint64),
                 ("grid", ctypes.c_int32), ("lds_bytes", ctypes.c_int32),
-                ("k", ctypes.c_int32), ("ng", ctypes.c_int32), ("method", ctypes.c_int32)]
+                ("k", ctypes.c_int32), ("ng", ctypes.c_int32), ("method", ctypes.c_int32),
+                ("adjacency", ctypes.c_int32), ("marks", ctypes.c_int32)]
 
 
 class ServerOpts(ctypes.Structure):
@@ -317,9 +322,10 @@ def mk_count_batch(ctx: int, gs: Sequence[int], t: int) -> Tuple[np.ndarray, np.
 
 def mk_batch_create(ctx: int, gs: Sequence[int], t: int, split_threshold: int = 0,
                     waves_per_cu: int = 0, use_graph: int = 0, units_per_grab: int = 0,
-                    debug_flags: int = 0, method: int = 0) -> int:
+                    debug_flags: int = 0, method: int = 0, adjacency: int = 0,
+                    marks: int = 0) -> int:
     opts = BatchOpts(split_threshold, waves_per_cu, use_graph, units_per_grab, debug_flags,
-                     method)
+                     method, adjacency, marks)
     h = _P()
     _check(library().mk_batch_create(ctx, _handles(gs), len(gs), t, ctypes.byref(opts),
                                      ctypes.byref(h)))

@@ -60,6 +60,16 @@ def test_constants_match_header():
     with open(os.path.join(ROOT, "include", "motifs.h")) as f:
         hdr = f.read()
     for name in ("MK_OK", "MK_EINVAL", "MK_ERANGE", "MK_EGRAPH", "MK_ENOMEM", "MK_EDEVICE",
-                 "MK_EBUSY", "MK_ETIMEDOUT", "MK_ENOTFOUND", "MK_MAX_VERTICES", "MK_MAX_DEGREE"):
-        m = re.search(r"#define %s \(?(-?\d+)\)?" % name, hdr)
-        assert m and int(m.group(1)) == getattr(M, name), name
+                 "MK_EBUSY", "MK_ETIMEDOUT", "MK_ENOTFOUND", "MK_MAX_VERTICES", "MK_MAX_DEGREE",
+                 "MK_LDS_MARKS_MAX_VERTICES"):
+        m = re.search(r"#define %s (\(?-?\d+(?: << \d+)?\)?)\s" % name, hdr)
+        assert m, name
+        expr = m.group(1).strip("()")
+        value = (int(expr.split("<<")[0]) << int(expr.split("<<")[1])) if "<<" in expr else int(expr)
+        assert value == getattr(M, name), name
+    for prefix, names in (("MK_METHOD_", ("AUTO", "ESU", "CORES")),
+                          ("MK_ADJ_", ("AUTO", "BITS", "LISTS")),
+                          ("MK_MARKS_", ("AUTO", "LDS", "GLOBAL"))):
+        for name in names:
+            m = re.search(r"#define %s%s (\d+)" % (prefix, name), hdr)
+            assert m and int(m.group(1)) == getattr(M, prefix[3:] + name), prefix + name

@@ -1,6 +1,8 @@
-"""Both counting methods at the library's size limits: MK_MAX_VERTICES
+"""Both counting methods at the limits of LDS marks: MK_LDS_MARKS_MAX_VERTICES
 vertices and a hub of degree up to MK_MAX_DEGREE, against the oracle where
-it finishes in seconds and against closed forms where it would not."""
+it finishes in seconds and against closed forms where it would not.  (Larger
+graphs, up to MK_MAX_VERTICES, are covered with the variants that keep the
+marks in device memory.)"""
 
 import math
 
@@ -41,9 +43,9 @@ def _count(ctx, g, k, method):
 
 
 def _max_n_with_hub(seed, hub_degree, extra_arcs):
-    """MK_MAX_VERTICES vertices: vertex 0 points at hub_degree others, plus
-    random arcs among the rest."""
-    n = M.MK_MAX_VERTICES
+    """MK_LDS_MARKS_MAX_VERTICES vertices: vertex 0 points at hub_degree
+    others, plus random arcs among the rest."""
+    n = M.MK_LDS_MARKS_MAX_VERTICES
     rng = np.random.default_rng(seed)
     src = [0] * hub_degree
     dst = list(range(1, hub_degree + 1))
@@ -67,7 +69,7 @@ def test_k3_max_vertices_and_hub(ctx, method):
 @pytest.mark.parametrize("method", METHODS)
 def test_max_vertices_sparse(ctx, k, method):
     rng = np.random.default_rng([91, k])
-    g = I.er_digraph(M.MK_MAX_VERTICES, 12000, rng)
+    g = I.er_digraph(M.MK_LDS_MARKS_MAX_VERTICES, 12000, rng)
     hist, _ = _count(ctx, g, k, method)
     assert as_code_dict(hist, ctx.table(k).class_codes()) == _oracle(("er", k), g, k)
 
