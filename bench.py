@@ -17,7 +17,10 @@ kernel (algorithmic HBM bytes: a 4-byte table entry and an 8-byte counter
 read + write per subgraph, over the kernel's HIP-event duration), the CPU
 oracle timed on a bounded sample, the plain one-graph-per-launch form on
 the same graphs, table build times, and the k = 5 batch (1 + 100
-randomisations of n = 1000, m = 3000) as a second reading.
+randomisations of n = 1000, m = 3000) as a second reading; then both
+counting methods, the code-formation variants (arc tests on bit matrices or
+sorted lists, marks in LDS or device memory) with a k = 6 graph of 2^20
+vertices, and the ensemble pipeline.
 """
 
 from __future__ import annotations
@@ -88,6 +91,8 @@ def _parse():
                         "known traffic, to scale hardware byte counters)")
     p.add_argument("--no-methods", action="store_true",
                    help="skip timing both counting methods on the k=6 and k=5 batches")
+    p.add_argument("--no-variants", action="store_true",
+                   help="skip the code-formation variants and the 2^20-vertex graph")
     p.add_argument("--no-ensemble", action="store_true",
                    help="skip the ensemble pipeline (random graphs, counts, z-scores)")
     p.add_argument("--serve", type=int, default=0, metavar="R",
@@ -164,6 +169,58 @@ def _methods(ctx, M, I, torch):
         res["k%d" % k] = row
         for g in gs:
             g.free()
+    return res
+
+
+def _variants(ctx, M, I, torch):
+    """Code-formation variants of the enumeration: the k=6 and k=5 batches
+    with arc tests on bit matrices or on sorted lists and marks in LDS or in
+    device memory (kernel and pass ms, histograms equal to the first), then
+    one k=6 graph of 2^20 vertices, past the LDS marks limit (the library
+    picks lists and device-memory marks by itself)."""
+    import numpy as np
+    res = {}
+    combos = (("bits_lds", M.ADJ_BITS, M.MARKS_LDS), ("lists_lds", M.ADJ_LISTS, M.MARKS_LDS),
+              ("lists_global", M.ADJ_LISTS, M.MARKS_GLOBAL))
+    for k, w, steps in ((6, I.workload_k6_batch(), 4), (5, I.workload_k5_batch(), 2)):
+        t = ctx.table(k)
+        gs = [ctx.load_graph(*g) for g in w.graphs]
+        row, ref = {}, None
+        for name, adj, marks in combos:
+            r = _timed_batch(ctx, M, gs, t, steps, 1, torch, method=M.METHOD_ESU, adjacency=adj,
+                             marks=marks)
+            if ref is None:
+                ref = r["hist"]
+            row[name] = {"pass_ms": float(np.mean(r["pass_ms"])),
+                         "kernel_ms": float(np.mean(r["enum_ms"])),
+                         "equal": bool(np.array_equal(ref, r["hist"]))}
+        _log("variants k=%d: %s" % (k, ", ".join("%s %.3f ms" % (n, row[n]["kernel_ms"])
+                                                  for n, _, _ in combos)))
+        res["k%d" % k] = row
+        for g in gs:
+            g.free()
+    w = I.workload_k6_large()
+    t = ctx.table(6)
+    g = ctx.load_graph(*w.graphs[0])
+    try:
+        r = _timed_batch(ctx, M, [g], t, 2, 1, torch)
+    finally:
+        g.free()
+    sub = int(r["totals"][0])
+    kern = float(np.mean(r["enum_ms"]))
+    st = r["stats"]
+    res["large"] = {"workload": w.name, "subgraphs": sub, "kernel_ms": kern,
+                    "pass_ms": float(np.mean(r["pass_ms"])),
+                    "value": sub / (float(np.mean(r["pass_ms"])) / 1e3),
+                    "unit": "subgraphs/s", "adjacency": st["adjacency"], "marks": st["marks"],
+                    "grid": st["grid"], "units": st["units"],
+                    "roofline": {"bound": "hbm", "kernel": "enum_lists_kernel<6, 3>",
+                                 "achieved": BYTES_PER_SUBGRAPH * sub / (kern / 1e3) / 1e9,
+                                 "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                 "frac": BYTES_PER_SUBGRAPH * sub / (kern / 1e3) / 1e9 / HBM_PEAK_GBS,
+                                 "bytes_per_subgraph": BYTES_PER_SUBGRAPH}}
+    _log("variants: %s, %d subgraphs, pass %.1f ms (kernel %.1f ms), %.3g subgraphs/s" % (
+        w.name, sub, res["large"]["pass_ms"], kern, res["large"]["value"]))
     return res
 
 
@@ -400,6 +457,8 @@ def main():
             g.free()
     if not args.no_methods:
         out["methods"] = _methods(ctx, M, I, torch)
+    if not args.no_variants:
+        out["variants"] = _variants(ctx, M, I, torch)
     if not args.no_ensemble:
         out["ensemble"] = _ensemble(ctx, M, I, torch, cpu=not args.no_cpu_baseline)
     if args.serve:

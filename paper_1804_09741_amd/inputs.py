@@ -263,6 +263,23 @@ def powerlaw_out_digraph(n: int, m: int, exponent: float, dmax: int,
     return csr_from_arcs(n, np.concatenate(src), np.concatenate(dst))
 
 
+def sparse_powerlaw_digraph(n: int, exponent: float, dmax: int, rng) -> Csr:
+    """Large sparse graphs drawn in vectorised form: out-degrees i.i.d.
+    P(d) ~ d^-exponent on [1, dmax]; targets uniform over the other vertices,
+    a repeated target dropped (so m is about n times the mean out-degree);
+    in-degrees close to Poisson."""
+    ds = np.arange(1, dmax + 1, dtype=np.float64)
+    p = ds ** (-exponent)
+    p /= p.sum()
+    deg = rng.choice(np.arange(1, dmax + 1), size=n, p=p).astype(np.int64)
+    deg = np.minimum(deg, n - 1)
+    src = np.repeat(np.arange(n, dtype=np.int64), deg)
+    t = rng.integers(0, n - 1, size=len(src))
+    dst = t + (t >= src)
+    keep = _first_occurrence(src * n + dst)
+    return csr_from_arcs(n, src[keep], dst[keep])
+
+
 def switch_randomise(row_ptr, col, accepted: int, rng) -> Csr:
     """Degree-preserving randomisation by directed arc switches.
 
@@ -372,6 +389,14 @@ def workload_k6_batch(count: int = 31) -> Workload:
     out-degree <= 60, in-degree ~Poisson) plus 30 randomisations."""
     gs = tuple(k6_batch_graph(i) for i in range(count))
     return Workload("k6_batch%d_powerlaw_n700_m1500" % count, 6, gs)
+
+
+def workload_k6_large(n: int = 1 << 20) -> Workload:
+    """k=6 on one graph past the LDS marks limit: the k=6 batch's degree
+    recipe (out-degree P(d) ~ d^-2.5 on [1, 60], uniform targets) at
+    n = 2^20 vertices (m ~ 2.2 n)."""
+    g = sparse_powerlaw_digraph(n, 2.5, 60, _rng(6, 0))
+    return Workload("k6_large_powerlaw_n%d_m%d" % (n, len(g[1])), 6, (g,))
 
 
 @dataclasses.dataclass(frozen=True)
