@@ -42,6 +42,12 @@
 // nodes, so the hash absorbs most of them, and only its flush looks codes up
 // in the code -> class table and adds to the graph's histogram with 64-bit
 // atomics.
+//
+// Two variants of the walk are separate kernels (enum_lists_kernel<k, V>):
+// arcs between two extension vertices tested by a binary search in the
+// shorter sorted list instead of a bit-matrix read, and, for graphs whose
+// marks do not fit LDS, each wave's marks kept in its own array in device
+// memory (the kVar* bits).
 #include "esu.h"
 
 namespace mk {

@@ -11,6 +11,8 @@
 // bit matrices (out-rows and in-rows), each vertex counts the union of its two
 // rows, a per-graph scan turns counts into offsets, and each vertex writes its
 // list by scanning its rows in ascending order (which sorts it for free).
+// Where n x n matrices are too large (or not wanted), the lists are built
+// by sorting each vertex's out- and in-arcs instead (launch_typed_lists).
 #include <algorithm>
 
 #include "internal.h"
