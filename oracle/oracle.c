@@ -25,6 +25,9 @@
  *      all k! relabelings of the vertices, found by trying every one;
  *   4. the count of that canonical code is incremented (exact 64-bit).
  *
+ * k = 7 (oracle_count7) follows the same steps with 42-bit codes and reports
+ * the histogram by canonical code (no table of all 2^42 codes is made).
+ *
  * Arc tests use an n x n bit matrix; neighbour lists delta(v) are built by
  * testing every pair.  Canonical forms are tabulated for every code when
  * k <= 5 and memoised per labeled code when k = 6 (a cache only: each entry
@@ -521,4 +524,267 @@ int64_t oracle_switch_chain(int n, const int32_t *row_ptr, const int32_t *col, u
     free(src);
     free(arc);
     return (int64_t)accepted;
+}
+
+/* ------------------------------------------------------------------------
+ * k = 7.  Section 1 gives the number of 7-vertex classes (880,471,142); a
+ * table over all 2^42 codes is out of reach, so the histogram is keyed by
+ * canonical code.  Same definition as above with 42-bit codes: ESU lists
+ * every connected 7-set once, its code has bit i*6 + j - [j > i] set iff
+ * arc s_i -> s_j, and its class is the minimum code over all 5040
+ * relabelings, found by trying every one (memoised per labeled code).
+ */
+
+typedef struct {
+    uint64_t *keys;
+    uint64_t *vals;
+    uint8_t *used;
+    size_t cap, size;
+} u64map;
+
+static int map64_init(u64map *m, size_t cap)
+{
+    m->cap = cap;
+    m->size = 0;
+    m->keys = (uint64_t *)malloc(cap * sizeof(uint64_t));
+    m->vals = (uint64_t *)malloc(cap * sizeof(uint64_t));
+    m->used = (uint8_t *)calloc(cap, 1);
+    return (m->keys && m->vals && m->used) ? OR_OK : OR_ENOMEM;
+}
+
+static void map64_free(u64map *m)
+{
+    free(m->keys);
+    free(m->vals);
+    free(m->used);
+    m->keys = NULL; m->vals = NULL; m->used = NULL;
+}
+
+static size_t map64_slot(const u64map *m, uint64_t key)
+{
+    size_t h = (size_t)((key * 0x9E3779B97F4A7C15ull) >> 20) & (m->cap - 1);
+    while (m->used[h] && m->keys[h] != key) h = (h + 1) & (m->cap - 1);
+    return h;
+}
+
+/* pointer to the value of key, inserting 0 if absent (NULL: out of memory) */
+static uint64_t *map64_get(u64map *m, uint64_t key, int *inserted)
+{
+    if (2 * (m->size + 1) > m->cap) {
+        u64map bigger;
+        if (map64_init(&bigger, m->cap * 2) != OR_OK) { map64_free(&bigger); return NULL; }
+        for (size_t i = 0; i < m->cap; ++i)
+            if (m->used[i]) {
+                size_t s = map64_slot(&bigger, m->keys[i]);
+                bigger.used[s] = 1;
+                bigger.keys[s] = m->keys[i];
+                bigger.vals[s] = m->vals[i];
+                bigger.size++;
+            }
+        map64_free(m);
+        *m = bigger;
+    }
+    size_t s = map64_slot(m, key);
+    *inserted = !m->used[s];
+    if (!m->used[s]) {
+        m->used[s] = 1;
+        m->keys[s] = key;
+        m->vals[s] = 0;
+        m->size++;
+    }
+    return &m->vals[s];
+}
+
+/* canonical form of a 7-vertex code: min over all relabelings pi of the
+   code with arc pi(i) -> pi(j) for every arc i -> j */
+uint64_t oracle_canon7(uint64_t code)
+{
+    int ai[42], aj[42], na = 0;  /* the arcs i -> j of the code */
+    for (int i = 0; i < 7; ++i)
+        for (int j = 0; j < 7; ++j)
+            if (i != j && ((code >> bit_of(7, i, j)) & 1u)) {
+                ai[na] = i;
+                aj[na] = j;
+                ++na;
+            }
+    int p[7];
+    for (int i = 0; i < 7; ++i) p[i] = i;
+    uint64_t best = ~0ull;
+    do {
+        uint64_t c = 0;
+        for (int t = 0; t < na; ++t) c |= 1ull << bit_of(7, p[ai[t]], p[aj[t]]);
+        best = c < best ? c : best;
+    } while (next_perm(p, 7));
+    return best;
+}
+
+typedef struct {
+    int n;
+    const uint64_t *arcbits; /* n*n bits, bit u*n+v set iff arc u -> v */
+    const int32_t *nb_ptr;   /* delta(v) = nb[nb_ptr[v] .. nb_ptr[v+1]) */
+    const int32_t *nb;
+    u64map *memo;            /* labeled code -> canonical code */
+    u64map *hist;            /* canonical code -> count */
+    int *buf[7];
+    int sub[7];
+    int failed;
+} esu7_ctx;
+
+static int arc7(const esu7_ctx *e, int u, int v)
+{
+    size_t bit = (size_t)u * e->n + v;
+    return (int)((e->arcbits[bit >> 6] >> (bit & 63)) & 1u);
+}
+
+static void record7(esu7_ctx *e)
+{
+    uint64_t code = 0;
+    for (int i = 0; i < 7; ++i)
+        for (int j = 0; j < 7; ++j)
+            if (i != j && arc7(e, e->sub[i], e->sub[j])) code |= 1ull << bit_of(7, i, j);
+    int ins = 0;
+    uint64_t *cv = map64_get(e->memo, code, &ins);
+    if (!cv) { e->failed = 1; return; }
+    if (ins) *cv = oracle_canon7(code);
+    const uint64_t canon = *cv;
+    uint64_t *hv = map64_get(e->hist, canon, &ins);
+    if (!hv) { e->failed = 1; return; }
+    *hv += 1;
+}
+
+static int in_closed_nbhd7(const esu7_ctx *e, int depth, int u)
+{
+    for (int i = 0; i < depth; ++i) {
+        int s = e->sub[i];
+        if (s == u || arc7(e, s, u) || arc7(e, u, s)) return 1;
+    }
+    return 0;
+}
+
+/* ESU extension step: V_sub = sub[0..depth), ext[0..next) is V_ext */
+static void extend7(esu7_ctx *e, int depth, const int *ext, int next, int root)
+{
+    if (e->failed) return;
+    if (depth == 7) {
+        record7(e);
+        return;
+    }
+    int *child = e->buf[depth];
+    for (int i = 0; i < next; ++i) {
+        int w = ext[i];
+        int cn = 0;
+        for (int j = i + 1; j < next; ++j) child[cn++] = ext[j];
+        for (int t = e->nb_ptr[w]; t < e->nb_ptr[w + 1]; ++t) {
+            int u = e->nb[t];
+            if (u > root && !in_closed_nbhd7(e, depth, u)) child[cn++] = u;
+        }
+        e->sub[depth] = w;
+        extend7(e, depth + 1, child, cn, root);
+    }
+}
+
+typedef struct { uint64_t code; uint64_t count; } pair64_t;
+
+static int pair64_cmp(const void *a, const void *b)
+{
+    uint64_t x = ((const pair64_t *)a)->code, y = ((const pair64_t *)b)->code;
+    return (x > y) - (x < y);
+}
+
+/*
+ * H_7 of the digraph (n, row_ptr, col) given as out-adjacency CSR: the
+ * distinct canonical codes that occur, ascending, in out_codes, their counts
+ * in out_counts; returns how many there are (OR_ESMALL when more than
+ * capacity) and stores the number of listed subgraphs in *total.
+ */
+int64_t oracle_count7(int n, const int32_t *row_ptr, const int32_t *col, uint64_t *out_codes,
+                      uint64_t *out_counts, int64_t capacity, uint64_t *total)
+{
+    int rc = check_graph(n, row_ptr, col);
+    if (rc != OR_OK) return rc;
+    if (total) *total = 0;
+    size_t words = ((size_t)n * n + 63) / 64;
+    uint64_t *bits = (uint64_t *)calloc(words + 1, sizeof(uint64_t));
+    if (!bits) return OR_ENOMEM;
+    for (int u = 0; u < n; ++u)
+        for (int32_t t = row_ptr[u]; t < row_ptr[u + 1]; ++t) {
+            int v = col[t];
+            size_t bit = (size_t)u * n + v;
+            if (u == v || ((bits[bit >> 6] >> (bit & 63)) & 1u)) { free(bits); return OR_EGRAPH; }
+            bits[bit >> 6] |= 1ull << (bit & 63);
+        }
+    if (n < 7) { free(bits); return 0; }
+
+    esu7_ctx e;
+    memset(&e, 0, sizeof(e));
+    e.n = n;
+    e.arcbits = bits;
+    int32_t *nb_ptr = (int32_t *)malloc(sizeof(int32_t) * ((size_t)n + 1));
+    int32_t *nb = (int32_t *)malloc(sizeof(int32_t) * (2 * (size_t)row_ptr[n] + 1));
+    int *ext = (int *)malloc(sizeof(int) * ((size_t)n + 1) * 8);
+    u64map memo, hist;
+    memset(&memo, 0, sizeof(memo));
+    memset(&hist, 0, sizeof(hist));
+    int64_t result = 0;
+    if (!nb_ptr || !nb || !ext || map64_init(&memo, 1 << 16) != OR_OK ||
+        map64_init(&hist, 1 << 16) != OR_OK) {
+        result = OR_ENOMEM;
+        goto done;
+    }
+    e.nb_ptr = nb_ptr;
+    e.nb = nb;
+    e.memo = &memo;
+    e.hist = &hist;
+    /* delta(v): every u with an arc either way, ascending */
+    int32_t cnt = 0;
+    for (int v = 0; v < n; ++v) {
+        nb_ptr[v] = cnt;
+        for (int u = 0; u < n; ++u)
+            if (u != v && (arc7(&e, v, u) || arc7(&e, u, v))) nb[cnt++] = u;
+    }
+    nb_ptr[n] = cnt;
+    for (int d = 0; d < 7; ++d) e.buf[d] = ext + (size_t)(d + 1) * ((size_t)n + 1);
+    for (int v = 0; v < n && !e.failed; ++v) {
+        int en = 0;
+        for (int t = nb_ptr[v]; t < nb_ptr[v + 1]; ++t)
+            if (nb[t] > v) ext[en++] = nb[t];
+        e.sub[0] = v;
+        extend7(&e, 1, ext, en, v);
+    }
+    if (e.failed) {
+        result = OR_ENOMEM;
+        goto done;
+    }
+    {
+        pair64_t *pairs = (pair64_t *)malloc(sizeof(pair64_t) * (hist.size + 1));
+        if (!pairs) {
+            result = OR_ENOMEM;
+            goto done;
+        }
+        int64_t nout = 0;
+        uint64_t sum = 0;
+        for (size_t s = 0; s < hist.cap; ++s)
+            if (hist.used[s]) {
+                pairs[nout].code = hist.keys[s];
+                pairs[nout].count = hist.vals[s];
+                sum += hist.vals[s];
+                ++nout;
+            }
+        qsort(pairs, (size_t)nout, sizeof(pair64_t), pair64_cmp);
+        for (int64_t i = 0; i < nout && i < capacity; ++i) {
+            out_codes[i] = pairs[i].code;
+            out_counts[i] = pairs[i].count;
+        }
+        free(pairs);
+        if (total) *total = sum;
+        result = nout > capacity ? OR_ESMALL : nout;
+    }
+done:
+    map64_free(&memo);
+    map64_free(&hist);
+    free(ext);
+    free(nb_ptr);
+    free(nb);
+    free(bits);
+    return result;
 }

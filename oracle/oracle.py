@@ -62,6 +62,12 @@ def load_library(path: str):
     lib.oracle_count.argtypes = [ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
                                  ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
                                  ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]
+    lib.oracle_canon7.restype = ctypes.c_uint64
+    lib.oracle_canon7.argtypes = [ctypes.c_uint64]
+    lib.oracle_count7.restype = ctypes.c_int64
+    lib.oracle_count7.argtypes = [ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
+                                  ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                  ctypes.c_void_p]
     return lib
 
 
@@ -119,8 +125,35 @@ def class_codes(k: int) -> np.ndarray:
 
 
 def count(row_ptr, col, k: int) -> Dict[int, int]:
-    """H_k as {canonical code: count} (zero classes omitted)."""
+    """H_k as {canonical code: count} (zero classes omitted); k = 3..7."""
+    if k == 7:
+        return count7_with(_lib(), row_ptr, col)
     return count_with(_lib(), row_ptr, col, k, canon_table(k)[0] if 3 <= k <= 5 else None)
+
+
+def canon7(code: int) -> int:
+    """Canonical form of a 7-vertex code (minimum over the 5040 relabelings)."""
+    return int(_lib().oracle_canon7(code))
+
+
+def count7_with(lib, row_ptr, col) -> Dict[int, int]:
+    """H_7 as {canonical code: count} from a given oracle library."""
+    row_ptr = np.ascontiguousarray(row_ptr, dtype=np.int32)
+    col = np.ascontiguousarray(col, dtype=np.int32)
+    n = len(row_ptr) - 1
+    cap = 1 << 14
+    while True:
+        codes = np.zeros(cap, dtype=np.uint64)
+        counts = np.zeros(cap, dtype=np.uint64)
+        total = ctypes.c_uint64(0)
+        rc = lib.oracle_count7(n, row_ptr.ctypes.data, col.ctypes.data if len(col) else None,
+                               codes.ctypes.data, counts.ctypes.data, cap, ctypes.byref(total))
+        if rc == -5:
+            cap *= 4
+            continue
+        if rc < 0:
+            raise OracleError(int(rc))
+        return {int(c): int(v) for c, v in zip(codes[:rc], counts[:rc])}
 
 
 def count_with(lib, row_ptr, col, k: int, table=None) -> Dict[int, int]:

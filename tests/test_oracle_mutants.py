@@ -55,6 +55,17 @@ MUTANTS = {
     "child extension keeps the chosen vertex": (
         "for (int j = i + 1; j < next; ++j) child[cn++] = ext[j];",
         "for (int j = i; j < next; ++j) child[cn++] = ext[j];"),
+    "k7 canonical form is the first relabeling": (
+        "best = c < best ? c : best;", "best = best == ~0ull ? c : best;"),
+    "k7 code operands transposed": (
+        "if (i != j && arc7(e, e->sub[i], e->sub[j])) code |= 1ull << bit_of(7, i, j);",
+        "if (i != j && arc7(e, e->sub[j], e->sub[i])) code |= 1ull << bit_of(7, i, j);"),
+    "k7 exclusive test drops one arc direction": (
+        "if (s == u || arc7(e, s, u) || arc7(e, u, s)) return 1;",
+        "if (s == u || arc7(e, s, u)) return 1;"),
+    "k7 extension ignores the root bound": (
+        "if (u > root && !in_closed_nbhd7(e, depth, u)) child[cn++] = u;",
+        "if (u != root && !in_closed_nbhd7(e, depth, u)) child[cn++] = u;"),
 }
 
 
@@ -139,6 +150,17 @@ def _failed_pins(lib):
                 failed.append("core raw sums k=%d" % k)
     except O.OracleError:
         failed.append("core error")
+    # k = 7: closed forms and the brute force on a tiny graph
+    try:
+        if O.count7_with(lib, *I.out_star(7)) != {63: 7}:
+            failed.append("out-star k=7")
+        if O.count7_with(lib, *I.complete_digraph(8)) != {(1 << 42) - 1: 8}:
+            failed.append("complete digraph k=7")
+        g = I.er_digraph(8, 16, np.random.default_rng(58))
+        if O.count7_with(lib, *g) != O.brute_force_count(*g, 7):
+            failed.append("brute force k=7")
+    except O.OracleError:
+        failed.append("error k=7")
     # ensemble: the generator's published values; switches keep the graph simple
     if [lib.oracle_splitmix64(0, i) for i in range(3)] != [
             0xe220a8397b1dcdaf, 0x6e789e6aa1b965f4, 0x06c45d188009454f]:
@@ -164,6 +186,7 @@ def test_unmutated_oracle_passes(tmp_path):
 def test_mutant_is_caught(tmp_path, name):
     before, after = MUTANTS[name]
     text = open(SRC).read()
-    assert text.count(before) == 1, "mutation site not found: %s" % before
-    lib = _build(tmp_path, "mutant", text.replace(before, after))
+    # the first site: a k = 7 copy of a line further down keeps its own mutant
+    assert text.count(before) >= 1, "mutation site not found: %s" % before
+    lib = _build(tmp_path, "mutant", text.replace(before, after, 1))
     assert _failed_pins_in_child(lib), "no pin catches: %s" % name
