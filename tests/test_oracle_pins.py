@@ -240,4 +240,4 @@ def test_bad_graphs_rejected():
     with pytest.raises(O.OracleError):
         O.count(np.array([0, 1, 1], np.int32), np.array([5], np.int32), 3)  # range
     with pytest.raises(O.OracleError):
-        O.count(*I.complete_digraph(4), 7)
+        O.count(*I.complete_digraph(4), 8)
