@@ -93,6 +93,7 @@ def _parse():
                    help="skip timing both counting methods on the k=6 and k=5 batches")
     p.add_argument("--no-variants", action="store_true",
                    help="skip the code-formation variants and the 2^20-vertex graph")
+    p.add_argument("--no-k7", action="store_true", help="skip the k=7 reading")
     p.add_argument("--no-ensemble", action="store_true",
                    help="skip the ensemble pipeline (random graphs, counts, z-scores)")
     p.add_argument("--serve", type=int, default=0, metavar="R",
@@ -221,6 +222,31 @@ def _variants(ctx, M, I, torch):
                                  "bytes_per_subgraph": BYTES_PER_SUBGRAPH}}
     _log("variants: %s, %d subgraphs, pass %.1f ms (kernel %.1f ms), %.3g subgraphs/s" % (
         w.name, sub, res["large"]["pass_ms"], kern, res["large"]["value"]))
+    return res
+
+
+def _k7(ctx, M, I, torch):
+    """k = 7 on the 31 graphs of the k = 6 batch (classes by canonical code,
+    canonicalised on the device): two calls, the second timed."""
+    import numpy as np
+    w = I.workload_k6_batch()
+    gs = [ctx.load_graph(*g) for g in w.graphs]
+    try:
+        ctx.count7(gs)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out, totals, kern = ctx.count7(gs)
+        wall = time.perf_counter() - t0
+    finally:
+        for g in gs:
+            g.free()
+    sub = int(np.sum(totals))
+    classes = [len(c) for c, _ in out]
+    res = {"workload": w.name.replace("k6_", "k7_"), "subgraphs": sub, "kernel_ms": kern,
+           "call_ms": wall * 1e3, "value": sub / (kern / 1e3), "unit": "subgraphs/s (kernel)",
+           "classes_mean": float(np.mean(classes)), "classes_max": int(max(classes))}
+    _log("k=7 on the k=6 batch: %d subgraphs, kernel %.1f ms (%.3g/s), call %.1f ms, "
+         "%.0f classes per graph" % (sub, kern, res["value"], res["call_ms"], res["classes_mean"]))
     return res
 
 
@@ -459,6 +485,8 @@ def main():
         out["methods"] = _methods(ctx, M, I, torch)
     if not args.no_variants:
         out["variants"] = _variants(ctx, M, I, torch)
+    if not args.no_k7:
+        out["k7"] = _k7(ctx, M, I, torch)
     if not args.no_ensemble:
         out["ensemble"] = _ensemble(ctx, M, I, torch, cpu=not args.no_cpu_baseline)
     if args.serve:

@@ -14,6 +14,7 @@
  *                  (its adjacency code, the table lookup) or by Section 3's
  *                  counting from the connected (k-2)-sets (MK_METHOD_*);
  *   - mk_server_*  a continuous-batching request server over the same path;
+ *   - mk_count7    H_7 (k = 7), classes reported by canonical code;
  *   - mk_randomise,
  *     mk_significance  the ensemble of random graphs and the z-score of each
  *                  class against it (Section 1's steps (a) and (c)).
@@ -330,6 +331,21 @@ int mk_batch_stats_get(const mk_batch *b, mk_batch_stats *out);
 int mk_batch_timing(mk_batch *b, double *pass_ms, double *enum_ms);
 
 void mk_batch_free(mk_batch *b);
+
+/* H_7 of ng graphs (each with n <= MK_LDS_MARKS_MAX_VERTICES).  Section 1
+   counts 880,471,142 classes of 7-vertex digraphs, too many for a table of
+   all 2^42 codes, so classes are reported by canonical code: the minimum
+   adjacency code over the 5040 relabelings (the rule behind the k <= 6 class
+   ids).  The subgraphs are enumerated as for k <= 6 and canonicalised on the
+   device.  For graph g, n_classes[g] receives the number of distinct classes;
+   the first min(n_classes[g], cap) of them, ascending, go to
+   codes[g * cap + i] with their counts in counts[g * cap + i].  totals[g]
+   (may be NULL) receives the number of connected 7-sets; kernel_ms (may be
+   NULL) the counting kernel's time.  MK_ERANGE when a graph is too large or
+   has more than cap classes (n_classes is still filled).  Blocks. */
+int mk_count7(mk_ctx *ctx, const mk_graph *const *gs, int32_t ng, int64_t cap,
+              uint64_t *codes, uint64_t *counts, int64_t *n_classes, uint64_t *totals,
+              double *kernel_ms);
 
 /* Autotuner: time the batch path on these graphs (best of `trials` runs
    each) under candidate settings -- counting method, split-threshold floor,

@@ -63,7 +63,8 @@ struct mk_batch {
     hipStream_t last_stream = nullptr;
 };
 
-static constexpr uint64_t kDefaultSplit[7] = {0, 0, 1u << 30, 1u << 30, 1u << 12, 1u << 12, 1u << 12};
+static constexpr uint64_t kDefaultSplit[8] = {0,       0,       1u << 30, 1u << 30,
+                                              1u << 12, 1u << 12, 1u << 12, 1u << 12};
 
 // ----------------------------------------------------------------- context
 
@@ -187,8 +188,10 @@ static int batch_enqueue_prep(mk_batch *b, unsigned long long *hist, hipStream_t
 {
     int rc = fill_u32(b->d_counters, 0, kNumCounters, stream);
     if (rc) return rc;
-    rc = fill_u32(hist, 0, (size_t)b->ng * b->table->num_classes * 2, stream);
-    if (rc) return rc;
+    if (hist) {
+        rc = fill_u32(hist, 0, (size_t)b->ng * b->table->num_classes * 2, stream);
+        if (rc) return rc;
+    }
     rc = batch_enqueue_typed(b, stream);
     if (rc) return rc;
     return launch_plan(b->plan_k, b->d_graphs, b->ng, b->max_nnz, b->total_slots, b->d_slot_cnt,
@@ -231,12 +234,11 @@ static int batch_enqueue_enum(mk_batch *b, unsigned long long *hist, hipStream_t
     return MK_OK;
 }
 
-extern "C" int mk_batch_create(mk_ctx *ctx, const mk_graph *const *gs, int32_t ng,
-                               const mk_table *t, const mk_batch_opts *opts, mk_batch **out)
+// A batch of ng graphs for subgraph size k: counted with table t (k <= 6),
+// or with the k = 7 kernel and no table (t null).
+static int batch_create(mk_ctx *ctx, const mk_graph *const *gs, int32_t ng, int k,
+                        const mk_table *t, const mk_batch_opts *opts, mk_batch **out)
 {
-    if (!ctx || !t || !out || (ng > 0 && !gs)) return fail(MK_EINVAL, "mk_batch_create: NULL argument");
-    if (ng < 0) return fail(MK_EINVAL, "mk_batch_create: ng=%d < 0", ng);
-    if (t->ctx != ctx || !t->d_table) return fail(MK_EINVAL, "mk_batch_create: table of another context");
     *out = nullptr;
     for (int i = 0; i < ng; ++i)
         if (!gs[i] || gs[i]->ctx != ctx)
@@ -247,7 +249,7 @@ extern "C" int mk_batch_create(mk_ctx *ctx, const mk_graph *const *gs, int32_t n
     mk_batch *b = new mk_batch();
     b->ctx = ctx;
     b->table = t;
-    b->k = t->k;
+    b->k = k;
     b->ng = ng;
     b->graphs.assign(gs, gs + ng);
     if (opts) b->opts = *opts;
@@ -321,7 +323,8 @@ extern "C" int mk_batch_create(mk_ctx *ctx, const mk_graph *const *gs, int32_t n
     const uint64_t region = b->adjacency == MK_ADJ_BITS ? bits : list_ws_words(b->total_n, b->total_m);
     b->total_slots = (uint32_t)slots;
     b->seg_cap = std::max(b->seg_cap, 1);
-    b->lds_bytes = b->method == MK_METHOD_CORES
+    b->lds_bytes = b->k == 7 ? k7_lds_bytes(std::max(b->max_n, 1), b->seg_cap)
+                   : b->method == MK_METHOD_CORES
                        ? core_lds_bytes(b->k, std::max(b->max_n, 1), b->seg_cap)
                        : enum_lds_bytes(b->k, std::max(b->max_n, 1), b->seg_cap, b->variant);
     if ((size_t)b->lds_bytes > ctx->max_lds) {
@@ -383,8 +386,10 @@ extern "C" int mk_batch_create(mk_ctx *ctx, const mk_graph *const *gs, int32_t n
     for (hipEvent_t &e : b->ev) BAIL_HIP(hipEventCreate(&e));
 
     int per_cu = 0;
-    rc = b->method == MK_METHOD_CORES ? core_max_blocks_per_cu(b->k, b->lds_bytes, &per_cu)
-                                      : enum_max_blocks_per_cu(b->k, b->variant, b->lds_bytes, &per_cu);
+    rc = b->k == 7 ? k7_max_blocks_per_cu(b->lds_bytes, &per_cu)
+         : b->method == MK_METHOD_CORES
+             ? core_max_blocks_per_cu(b->k, b->lds_bytes, &per_cu)
+             : enum_max_blocks_per_cu(b->k, b->variant, b->lds_bytes, &per_cu);
     if (rc) return bail(rc);
     if (b->opts.waves_per_cu > 0) per_cu = std::min(per_cu, b->opts.waves_per_cu);
     per_cu = std::max(per_cu, 1);
@@ -433,6 +438,15 @@ extern "C" int mk_batch_create(mk_ctx *ctx, const mk_graph *const *gs, int32_t n
 #undef BAIL_HIP
     *out = b;
     return MK_OK;
+}
+
+extern "C" int mk_batch_create(mk_ctx *ctx, const mk_graph *const *gs, int32_t ng,
+                               const mk_table *t, const mk_batch_opts *opts, mk_batch **out)
+{
+    if (!ctx || !t || !out || (ng > 0 && !gs)) return fail(MK_EINVAL, "mk_batch_create: NULL argument");
+    if (ng < 0) return fail(MK_EINVAL, "mk_batch_create: ng=%d < 0", ng);
+    if (t->ctx != ctx || !t->d_table) return fail(MK_EINVAL, "mk_batch_create: table of another context");
+    return batch_create(ctx, gs, ng, t->k, t, opts, out);
 }
 
 extern "C" int mk_batch_run(mk_batch *b, uint64_t *d_hist, void *stream)
@@ -759,4 +773,147 @@ extern "C" int mk_count(mk_ctx *ctx, const mk_graph *g, const mk_table *t, uint6
 {
     if (!g) return fail(MK_EINVAL, "mk_count: NULL graph");
     return mk_count_batch(ctx, &g, 1, t, hist, total);
+}
+
+// ------------------------------------------------------------------ k = 7
+
+// one k = 7 pass over a prepared batch with class tables of 2^class_log2
+// slots per graph; *overflow tells whether a table was too small
+static int count7_once(mk_batch *b, int class_log2, int cache_log2, int64_t cap, uint64_t *codes,
+                       uint64_t *counts, int64_t *n_classes, uint64_t *totals, double *kernel_ms,
+                       bool *overflow)
+{
+    mk_ctx *ctx = b->ctx;
+    hipStream_t st = ctx->stream;
+    const int ng = b->ng;
+    const size_t cache_slots = (size_t)1 << cache_log2;
+    const size_t class_slots = ((size_t)1 << class_log2) * (size_t)ng;
+    K7Launch a{};
+    a.cache_log2 = cache_log2;
+    a.class_log2 = class_log2;
+    unsigned long long *d_out = nullptr, *d_n = nullptr;
+    std::vector<void *> bufs;
+    auto alloc = [&](void **p, size_t bytes) {
+        hipError_t e = hipMalloc(p, std::max<size_t>(bytes, 8));
+        if (e == hipSuccess) bufs.push_back(*p);
+        return e;
+    };
+    auto release = [&]() {
+        for (void *p : bufs) (void)hipFree(p);
+    };
+    hipError_t e = alloc((void **)&a.cache_key, 8 * cache_slots);
+    if (e == hipSuccess) e = alloc((void **)&a.cache_val, 8 * cache_slots);
+    if (e == hipSuccess) e = alloc((void **)&a.class_key, 8 * class_slots);
+    if (e == hipSuccess) e = alloc((void **)&a.class_cnt, 8 * class_slots);
+    if (e == hipSuccess) e = alloc((void **)&a.totals, 8 * (size_t)ng);
+    if (e == hipSuccess) e = alloc((void **)&a.overflow, 4);
+    if (e == hipSuccess) e = alloc((void **)&d_n, 8 * (size_t)ng);
+    if (e == hipSuccess) e = alloc((void **)&d_out, 16 * (size_t)ng * (size_t)cap);
+    if (e != hipSuccess) {
+        release();
+        return fail(e == hipErrorOutOfMemory ? MK_ENOMEM : MK_EDEVICE, "mk_count7: allocation: %s",
+                    hipGetErrorString(e));
+    }
+    unsigned long long *d_codes = d_out, *d_counts = d_out + (size_t)ng * (size_t)cap;
+    int rc = fill_u32(a.cache_key, 0xFFFFFFFFu, 2 * cache_slots, st);
+    if (!rc) rc = fill_u32(a.cache_val, 0xFFFFFFFFu, 2 * cache_slots, st);
+    if (!rc) rc = fill_u32(a.class_key, 0xFFFFFFFFu, 2 * class_slots, st);
+    if (!rc) rc = fill_u32(a.class_cnt, 0u, 2 * class_slots, st);
+    if (!rc) rc = fill_u32(a.totals, 0u, 2 * (size_t)ng, st);
+    if (!rc) rc = fill_u32(a.overflow, 0u, 1, st);
+    if (!rc) rc = fill_u32(d_n, 0u, 2 * (size_t)ng, st);
+    if (!rc) rc = batch_enqueue_prep(b, nullptr, st);
+    EnumConfig cfg = enum_config(b);
+    cfg.hash_bits = 0;  // the k = 7 kernel keeps its own hash of 64-bit codes
+    if (!rc && hipEventRecord(b->ev[1], st) != hipSuccess) rc = fail(MK_EDEVICE, "event record");
+    if (!rc) rc = launch_k7(b->d_graphs, b->d_units, b->unit_cap, b->d_counters, a, cfg, b->grid,
+                            b->lds_bytes, st);
+    if (!rc && hipEventRecord(b->ev[2], st) != hipSuccess) rc = fail(MK_EDEVICE, "event record");
+    if (!rc) rc = launch_k7_collect(a, ng, cap, d_codes, d_counts, d_n, st);
+    std::vector<unsigned long long> hn(ng), ht(ng), hc((size_t)ng * cap), hv((size_t)ng * cap);
+    uint32_t cnt[kNumCounters], ovf = 0;
+    auto copy = [&](void *dst, const void *src, size_t bytes) {
+        if (!rc && bytes) {
+            hipError_t ce = hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, st);
+            if (ce != hipSuccess) rc = fail(MK_EDEVICE, "mk_count7: copy: %s", hipGetErrorString(ce));
+        }
+    };
+    copy(hn.data(), d_n, 8 * (size_t)ng);
+    copy(ht.data(), a.totals, 8 * (size_t)ng);
+    copy(hc.data(), d_codes, 8 * (size_t)ng * cap);
+    copy(hv.data(), d_counts, 8 * (size_t)ng * cap);
+    copy(cnt, b->d_counters, sizeof(cnt));
+    copy(&ovf, a.overflow, 4);
+    if (!rc && hipStreamSynchronize(st) != hipSuccess) rc = fail(MK_EDEVICE, "mk_count7: sync");
+    float ms = 0.f;
+    if (!rc) (void)hipEventElapsedTime(&ms, b->ev[1], b->ev[2]);
+    release();
+    if (rc) return rc;
+    if (cnt[kErrors] != 0 || cnt[kAdjOverflow] != 0)
+        return fail(MK_EDEVICE, "device-side check failed (%u errors, %u adjacency overflows)",
+                    cnt[kErrors], cnt[kAdjOverflow]);
+    *overflow = ovf != 0;
+    if (*overflow) return MK_OK;
+    if (kernel_ms) *kernel_ms = ms;
+    bool small = false;
+    for (int g = 0; g < ng; ++g) {
+        n_classes[g] = (int64_t)hn[g];
+        if (totals) totals[g] = ht[g];
+        const int64_t m = std::min<int64_t>((int64_t)hn[g], cap);
+        small |= (int64_t)hn[g] > cap;
+        std::vector<std::pair<uint64_t, uint64_t>> pr((size_t)m);
+        for (int64_t i = 0; i < m; ++i) pr[i] = {hc[(size_t)g * cap + i], hv[(size_t)g * cap + i]};
+        std::sort(pr.begin(), pr.end());
+        for (int64_t i = 0; i < m; ++i) {
+            codes[(size_t)g * cap + i] = pr[i].first;
+            counts[(size_t)g * cap + i] = pr[i].second;
+        }
+    }
+    if (small) return fail(MK_ERANGE, "mk_count7: a graph has more classes than cap=%lld", (long long)cap);
+    return MK_OK;
+}
+
+extern "C" int mk_count7(mk_ctx *ctx, const mk_graph *const *gs, int32_t ng, int64_t cap,
+                         uint64_t *codes, uint64_t *counts, int64_t *n_classes, uint64_t *totals,
+                         double *kernel_ms)
+{
+    if (!ctx || (ng > 0 && (!gs || !n_classes)) || (cap > 0 && ng > 0 && (!codes || !counts)))
+        return fail(MK_EINVAL, "mk_count7: NULL argument");
+    if (ng < 0 || cap < 0) return fail(MK_EINVAL, "mk_count7: negative ng or cap");
+    for (int i = 0; i < ng; ++i) {
+        if (!gs[i] || gs[i]->ctx != ctx)
+            return fail(MK_EINVAL, "mk_count7: graph %d missing or of another context", i);
+        if (gs[i]->n > MK_LDS_MARKS_MAX_VERTICES)
+            return fail(MK_ERANGE, "mk_count7: graph %d has n=%d > %d", i, gs[i]->n,
+                        MK_LDS_MARKS_MAX_VERTICES);
+    }
+    if (kernel_ms) *kernel_ms = 0.0;
+    if (ng == 0) return MK_OK;
+    std::lock_guard<std::recursive_mutex> lock(ctx->mu);
+    MK_HIP(hipSetDevice(ctx->device));
+    mk_batch_opts o{};
+    o.use_graph = -1;
+    o.method = MK_METHOD_ESU;
+    o.adjacency = MK_ADJ_BITS;
+    o.marks = MK_MARKS_LDS;
+    mk_batch *b = nullptr;
+    int rc = batch_create(ctx, gs, ng, 7, nullptr, &o, &b);
+    if (rc) return rc;
+    // class tables of the size the last count needed (2^10 slots per graph
+    // at first), 4x larger after an overflow
+    for (int class_log2 = ctx->k7_class_log2;; class_log2 += 2) {
+        bool overflow = false;
+        rc = count7_once(b, class_log2, 22, cap, codes, counts, n_classes, totals, kernel_ms,
+                         &overflow);
+        if (rc || !overflow) {
+            if (!rc) ctx->k7_class_log2 = class_log2;
+            break;
+        }
+        if (class_log2 >= 24) {
+            rc = fail(MK_ERANGE, "mk_count7: more distinct classes than 2^%d slots hold", class_log2);
+            break;
+        }
+    }
+    mk_batch_free(b);
+    return rc;
 }

@@ -122,6 +122,7 @@ struct Ctx {
     int64_t hbm_bytes = 0;
     size_t max_lds = 0;
     Table *tables[7] = {};
+    int k7_class_log2 = 10;  // class-table size of the last k = 7 count (grows as needed)
     std::recursive_mutex mu;
 };
 
@@ -163,6 +164,22 @@ int launch_plan(int k, const DevGraph *d_graphs, int ng, int64_t max_nnz, uint32
                 uint32_t waves, uint32_t *counters, hipStream_t stream);
 
 // Enumeration + code + lookup + histogram over the queued units.
+// k = 7 (k7.hip): device tables of one count
+struct K7Launch {
+    unsigned long long *cache_key, *cache_val;  // labeled -> canonical code
+    int cache_log2;                              // log2 of the cache slots
+    unsigned long long *class_key, *class_cnt;  // per graph: canonical code -> count
+    int class_log2;                              // log2 of the class slots per graph
+    unsigned long long *totals;                  // per graph: subgraphs
+    uint32_t *overflow;                          // class inserts that found no slot
+};
+int k7_lds_bytes(int max_n, int seg_cap);
+int k7_max_blocks_per_cu(int lds_bytes, int *blocks);
+int launch_k7(const DevGraph *d_graphs, const int4 *units, uint32_t unit_cap, uint32_t *counters,
+              const K7Launch &a, const struct EnumConfig &cfg, int grid, int lds_bytes,
+              hipStream_t stream);
+int launch_k7_collect(const K7Launch &a, int ng, int64_t cap, unsigned long long *out_codes,
+                      unsigned long long *out_counts, unsigned long long *n_out, hipStream_t stream);
 int enum_lds_bytes(int k, int max_n, int seg_cap, int variant);
 int enum_max_blocks_per_cu(int k, int variant, int lds_bytes, int *blocks);
 constexpr uint32_t kAllUnits = 0xFFFFFFFFu;

@@ -1,0 +1,559 @@
+// k = 7.  Section 1 counts 880,471,142 classes of 7-vertex digraphs; a code
+// -> class table would need 2^42 entries, so here the class of a subgraph is
+// its canonical code (the minimum adjacency code over the 5040 relabelings,
+// the rule the k <= 6 tables are built by), and H_7 of a graph is a set of
+// (canonical code, count) pairs.
+//
+// The walk is the enumeration kernel's (ESU with per-wave LDS marks, the
+// last two levels flat: pairs inside the extension list by bit-matrix test,
+// exclusive neighbours by list scan), with 42-bit codes.  Codes go into a
+// per-wave LDS hash of pending counts; at its flush each distinct labeled
+// code gets its canonical code from a device-wide cache (labeled ->
+// canonical, open addressing); a code not in the cache is canonicalised by
+// the whole wave -- each lane tries 79 of the 5040 relabelings, then a
+// minimum over the wave -- and entered.  Counts are added to the graph's
+// class table (canonical code -> u64 count, open addressing).
+#include "esu.h"
+
+namespace mk {
+
+using Code7 = unsigned long long;
+constexpr Code7 kNoCode = ~0ull;       // free slot / value not written yet
+constexpr int kHash7Slots = 256;       // per-wave LDS hash
+constexpr int kHash7Probes = 8;
+constexpr int kCacheProbes = 32;
+constexpr int kClassProbes = 64;
+
+struct K7Tables {
+    Code7 *cache_key;              // labeled code (kNoCode: free)
+    Code7 *cache_val;              // its canonical code (kNoCode: not written yet)
+    int cache_shift;               // 64 - log2(cache slots)
+    uint32_t cache_mask;
+    Code7 *class_key;              // per graph class_mask + 1 canonical codes
+    unsigned long long *class_cnt; //   and their counts
+    int class_shift;               // 64 - log2(class slots)
+    uint32_t class_mask;
+    unsigned long long *totals;    // per graph: subgraphs counted
+    uint32_t *overflow;            // class-table inserts that found no slot
+};
+
+// per-wave hash of pending (labeled code, count) pairs in LDS
+struct K7Wave {
+    Code7 *hkey;
+    uint32_t *hcnt;
+    int hused;
+    uint32_t hpending;
+    int graph;
+};
+
+__device__ __forceinline__ uint32_t hash7(Code7 c, int shift)
+{
+    return (uint32_t)((c * 0x9E3779B97F4A7C15ull) >> shift);
+}
+
+__device__ __forceinline__ Code7 readlane64(Code7 v, int l)
+{
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, l);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), l);
+    return ((Code7)hi << 32) | lo;
+}
+
+// position of arc i -> j in a 7-vertex code
+__host__ __device__ constexpr int bit7(int i, int j) { return i * 6 + j - (j > i ? 1 : 0); }
+
+// code bits of a vertex with mark m joining at position p (1..6)
+__device__ __forceinline__ Code7 code_bits7(uint32_t m, int p)
+{
+    return ((Code7)(m >> EnumState<7>::OUTB) << (p * 6)) |
+           ((Code7)(m & EnumState<7>::INMASK) << (p - 1));
+}
+
+// Canonical code: every lane tries the relabelings l, l + 64, ... of the
+// 5040 (numbered in the factorial number system), the wave takes the
+// minimum.  Call with every lane active and the same code in all lanes.
+__device__ Code7 canon7_wave(Code7 code)
+{
+    constexpr int fact[7] = {720, 120, 24, 6, 2, 1, 1};
+    Code7 best = kNoCode;
+    for (int p = lane_id(); p < 5040; p += kWave) {
+        // relabeling p: position pos of the new order takes vertex perm(pos);
+        // perm is kept as 4-bit fields
+        int idx = p;
+        uint32_t avail = 0x7Fu, perm = 0;
+#pragma unroll
+        for (int pos = 0; pos < 7; ++pos) {
+            const int d = idx / fact[pos];
+            idx -= d * fact[pos];
+            uint32_t a = avail;
+            for (int t = 0; t < d; ++t) a &= a - 1u;
+            const uint32_t v = (uint32_t)__builtin_ctz(a);
+            perm |= v << (4 * pos);
+            avail &= ~(1u << v);
+        }
+        Code7 c = 0, rest = code;
+        while (rest) {
+            const int b = __builtin_ctzll(rest);
+            rest &= rest - 1;
+            const int i = b / 6, r = b - 6 * i;
+            const int j = r + (r >= i ? 1 : 0);
+            c |= 1ull << bit7((int)((perm >> (4 * i)) & 15u), (int)((perm >> (4 * j)) & 15u));
+        }
+        best = c < best ? c : best;
+    }
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) {
+        const Code7 o = __shfl_xor(best, off, kWave);
+        best = o < best ? o : best;
+    }
+    return best;
+}
+
+// Move the wave's pending counts to its graph's class table: canonical code
+// from the cache (or computed and entered), count added; hash emptied.
+__device__ void flush7(EnumState<7> &s, K7Wave &w, const K7Tables &t)
+{
+    __syncthreads();
+    const int lane = lane_id();
+    unsigned long long tot = 0;
+    Code7 *ckey = t.class_key + (size_t)w.graph * (t.class_mask + 1);
+    unsigned long long *ccnt = t.class_cnt + (size_t)w.graph * (t.class_mask + 1);
+    for (int base = 0; base < kHash7Slots; base += kWave) {
+        const int i = base + lane;
+        const Code7 key = w.hkey[i];
+        const uint32_t cnt = w.hcnt[i];
+        const bool live = key != kNoCode;
+        Code7 canon = kNoCode;
+        if (live) {
+            uint32_t h = hash7(key, t.cache_shift);
+            for (int p = 0; p < kCacheProbes; ++p) {
+                const Code7 k2 = t.cache_key[h];
+                if (k2 == key) {
+                    canon = t.cache_val[h];
+                    break;
+                }
+                if (k2 == kNoCode) break;
+                h = (h + 1) & t.cache_mask;
+            }
+        }
+        const bool missed = live && canon == kNoCode;
+        unsigned long long miss = __ballot(missed);
+        while (miss) {
+            const int l = __builtin_ctzll(miss);
+            miss &= miss - 1;
+            const Code7 m = canon7_wave(readlane64(key, l));
+            if (lane == l) canon = m;
+        }
+        if (missed) {
+            // enter it: the lane that claims the key writes the value; a
+            // reader that meets the key before the value computes it again
+            uint32_t h = hash7(key, t.cache_shift);
+            for (int p = 0; p < kCacheProbes; ++p) {
+                const Code7 old = atomicCAS(&t.cache_key[h], kNoCode, key);
+                if (old == kNoCode) {
+                    atomicExch(&t.cache_val[h], canon);
+                    break;
+                }
+                if (old == key) break;
+                h = (h + 1) & t.cache_mask;
+            }
+        }
+        if (live && cnt != 0u) {
+            uint32_t h = hash7(canon, t.class_shift);
+            bool done = false;
+            for (int p = 0; p < kClassProbes && !done; ++p) {
+                const Code7 old = atomicCAS(&ckey[h], kNoCode, canon);
+                if (old == kNoCode || old == canon) {
+                    atomicAdd(&ccnt[h], (unsigned long long)cnt);
+                    done = true;
+                }
+                h = (h + 1) & t.class_mask;
+            }
+            if (!done) atomicAdd(t.overflow, 1u);
+            tot += cnt;
+        }
+        if (live) {
+            w.hkey[i] = kNoCode;
+            w.hcnt[i] = 0u;
+        }
+    }
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) tot += __shfl_xor(tot, off, kWave);
+    if (lane == 0 && tot) atomicAdd(&t.totals[w.graph], tot);
+    w.hused = 0;
+    w.hpending = 0;
+    __syncthreads();
+}
+
+// add n to the pending count of code for every lane with `mine` set; a full
+// hash is flushed and the inserts that found no slot are tried again
+__device__ void hash7_insert(EnumState<7> &s, K7Wave &w, const K7Tables &t, bool mine, Code7 code,
+                             uint32_t n)
+{
+    bool pending = mine;
+    for (;;) {
+        bool fresh = false;
+        if (pending) {
+            uint32_t h = hash7(code, 64 - 8);
+            for (int p = 0; p < kHash7Probes; ++p) {
+                const Code7 old = atomicCAS(&w.hkey[h], kNoCode, code);
+                if (old == kNoCode || old == code) {
+                    fresh = old == kNoCode;
+                    atomicAdd(&w.hcnt[h], n);
+                    pending = false;
+                    break;
+                }
+                h = (h + 1) & (kHash7Slots - 1);
+            }
+        }
+        w.hused += __popcll(__ballot(fresh));
+        const bool retry = __ballot(pending) != 0ull;
+        if (retry || w.hused > kHash7Slots / 2 || w.hpending >= kPendingMax) flush7(s, w, t);
+        if (!retry) break;
+    }
+}
+
+// count one code per valid lane (lanes sharing the first lane's code merged)
+__device__ void count7(EnumState<7> &s, K7Wave &w, const K7Tables &t, bool valid, Code7 code)
+{
+    const int lane = lane_id();
+    const unsigned long long act = __ballot(valid);
+    if (!act) return;
+    w.hpending += (uint32_t)__popcll(act);
+    const int l = __builtin_ctzll(act);
+    const Code7 c0 = readlane64(code, l);
+    const unsigned long long eq = __ballot(valid && code == c0) & act;
+    uint32_t n = 1;
+    if (lane == l) n = (uint32_t)__popcll(eq);
+    else if ((eq >> lane) & 1ull) n = 0;
+    hash7_insert(s, w, t, valid && n > 0, code, n);
+}
+
+// position in seg storage of element a of the extension list made of the
+// tails seg[q][st[q]:], q < NQ
+template <int NQ>
+__device__ __forceinline__ int ext_addr7(const EnumState<7> &s, const int (&st)[6],
+                                         const int (&rem)[NQ], int a)
+{
+    int addr = 0;
+    bool found = false;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        if (!found) {
+            if (a < rem[q]) {
+                addr = q * s.seg_cap + st[q] + a;
+                found = true;
+            } else {
+                a -= rem[q];
+            }
+        }
+    }
+    return addr;
+}
+
+// The last two levels of a node X with members s_0..s_4 and extension list
+// E: child w = E[i] (i in [jlo, jhi)) closes X + {w, u} for (A) u = E[j],
+// j > i (arc w - u from the bit matrices) and (B) u an exclusive neighbour
+// of w (its list entry gives the arc).  Same split as the k <= 6 kernel.
+__device__ void last_two7(EnumState<7> &s, K7Wave &w7, const K7Tables &t, const int (&st)[6],
+                          Code7 code, int jlo, int jhi)
+{
+    constexpr int NQ = 5;
+    constexpr int B_WU = bit7(5, 6);  // arc s_5 -> s_6
+    constexpr int B_UW = bit7(6, 5);  // arc s_6 -> s_5
+    const int lane = lane_id();
+    int rem[NQ];
+    int e = 0;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        rem[q] = s.len[q] - st[q];
+        e += rem[q];
+    }
+    const int hi = e < jhi ? e : jhi;
+    if (jlo >= hi) return;
+
+    // (A) pairs (E[i], E[j]), jlo <= i < hi, i < j < e, row by row
+    const int rows = hi - jlo;
+    const int A = e - 1 - jlo;
+    const long long npairs = (long long)rows * A - (long long)rows * (rows - 1) / 2;
+    const float tA = 2.0f * (float)A + 1.0f;
+    for (long long base = 0; base < npairs; base += kWave) {
+        const long long p = base + lane;
+        const bool valid = p < npairs;
+        Code7 c = 0;
+        bool ok = false;
+        if (valid) {
+            float disc = tA * tA - 8.0f * (float)p;
+            disc = disc > 0.f ? disc : 0.f;
+            int r = (int)((tA - __builtin_amdgcn_sqrtf(disc)) * 0.5f);
+            r = r < 0 ? 0 : (r > rows - 1 ? rows - 1 : r);
+            while (r + 1 < rows && (long long)(r + 1) * A - (long long)(r + 1) * r / 2 <= p) ++r;
+            while (r > 0 && (long long)r * A - (long long)r * (r - 1) / 2 > p) --r;
+            const int i = jlo + r;
+            const int j = i + 1 + (int)(p - ((long long)r * A - (long long)r * (r - 1) / 2));
+            if (i < j && j < e) {
+                const uint32_t w = s.seg[ext_addr7<NQ>(s, st, rem, i)];
+                const uint32_t u = s.seg[ext_addr7<NQ>(s, st, rem, j)];
+                const size_t word = (size_t)w * s.words + (u >> 5);
+                const uint32_t sh = u & 31u;
+                const uint32_t tt = ((s.bits_out[word] >> sh) & 1u) | (((s.bits_in[word] >> sh) & 1u) << 1);
+                c = code | code_bits7(s.mark[w], 5) | code_bits7(s.mark[u], 6) |
+                    ((Code7)(tt & 1u) << B_WU) | ((Code7)(tt >> 1) << B_UW);
+                ok = true;
+            } else {
+                atomicAdd(s.errors, 1u);  // unreachable: the decode keeps i < j < e
+            }
+        }
+        count7(s, w7, t, ok, c);
+    }
+
+    // (B) exclusive neighbours, 64 children at a time: a lane-prefix sum of
+    // their degrees maps a flat index to (child, list position)
+    uint32_t *pre = s.scratch, *start = s.scratch + kWave;
+    for (int ib = jlo; ib < hi; ib += kWave) {
+        const int i = ib + lane;
+        int deg = 0, row = 0;
+        Code7 wcode = 0;
+        if (i < hi) {
+            const uint32_t w = s.seg[ext_addr7<NQ>(s, st, rem, i)];
+            row = s.urow[w];
+            deg = s.urow[w + 1] - row;
+            wcode = code_bits7(s.mark[w], 5);
+        }
+        int incl = deg;
+#pragma unroll
+        for (int d = 1; d < kWave; d <<= 1) {
+            const int o = __shfl_up(incl, d, kWave);
+            if (lane >= d) incl += o;
+        }
+        const int tot = uniform(__shfl(incl, kWave - 1, kWave));
+        pre[lane] = (uint32_t)incl;
+        start[lane] = (uint32_t)row;
+        __syncthreads();
+        for (int fb = 0; fb < tot; fb += kWave) {
+            const int f = fb + lane;
+            bool valid = f < tot;
+            int lo = 0;
+            if (valid) {
+#pragma unroll
+                for (int step = kWave / 2; step > 0; step >>= 1)
+                    lo += ((int)pre[lo + step - 1] <= f) ? step : 0;
+            }
+            // the child's code bits from its lane (every lane active here)
+            const Code7 cw = ((Code7)(uint32_t)__builtin_amdgcn_ds_bpermute(
+                                  lo << 2, (int)(uint32_t)(wcode >> 32)) << 32) |
+                             (uint32_t)__builtin_amdgcn_ds_bpermute(lo << 2, (int)(uint32_t)wcode);
+            Code7 c = 0;
+            if (valid) {
+                const int before = lo ? (int)pre[lo - 1] : 0;
+                const uint32_t ent = s.uadj[start[lo] + (uint32_t)(f - before)];
+                const int u = (int)(ent >> 2);
+                const uint32_t tt = ent & 3u;
+                valid = u > s.root && s.mark[u] == 0u;
+                c = code | cw | ((Code7)(tt & 1u) << B_WU) | ((Code7)(tt >> 1) << B_UW);
+            }
+            count7(s, w7, t, valid, c);
+        }
+        __syncthreads();
+    }
+}
+
+// node with members s_0..s_D: children jlo..jhi-1 of its extension list
+template <int D>
+__device__ void visit7(EnumState<7> &s, K7Wave &w7, const K7Tables &t, const int (&st)[6],
+                       Code7 code, int jlo, int jhi)
+{
+    if constexpr (D == 4) {
+        last_two7(s, w7, t, st, code, jlo, jhi);
+    } else {
+        int rem[D + 1];
+        int total = 0;
+#pragma unroll
+        for (int q = 0; q <= D; ++q) {
+            rem[q] = s.len[q] - st[q];
+            total += rem[q];
+        }
+        const int hi = total < jhi ? total : jhi;
+        for (int j = jlo; j < hi; ++j) {
+            int a = j, L = 0, o = 0;
+            bool found = false;
+#pragma unroll
+            for (int q = 0; q <= D; ++q) {
+                if (!found) {
+                    if (a < rem[q]) {
+                        L = q;
+                        o = st[q] + a;
+                        found = true;
+                    } else {
+                        a -= rem[q];
+                    }
+                }
+            }
+            const int x = uniform((int)s.seg[L * s.seg_cap + o]);
+            const uint32_t mx = (uint32_t)uniform((int)s.mark[x]);
+            const Code7 ccode = code | code_bits7(mx, D + 1);
+            const Held held = push_held<7, D + 1>(s, x);
+            int cst[6];
+#pragma unroll
+            for (int q = 0; q < 6; ++q)
+                cst[q] = q < L ? s.len[q] : (q == L ? o + 1 : (q <= D ? st[q] : 0));
+            visit7<D + 1>(s, w7, t, cst, ccode, 0, INT_MAX);
+            pop_held<7, D + 1>(s, x, held);
+        }
+    }
+}
+
+__device__ void run_unit7(EnumState<7> &s, K7Wave &w7, const K7Tables &t, int v, int i,
+                          uint32_t range)
+{
+    s.root = v;
+    const Held held0 = push_held<7, 0>(s, v);
+    if (i < s.len[0]) {
+        const int x = uniform((int)s.seg[i]);
+        const Code7 code = code_bits7((uint32_t)uniform((int)s.mark[x]), 1);
+        const Held held1 = push_held<7, 1>(s, x);
+        int st[6];
+#pragma unroll
+        for (int q = 0; q < 6; ++q) st[q] = 0;
+        st[0] = i + 1;
+        const bool full = range == kFullChild;
+        visit7<1>(s, w7, t, st, code, full ? 0 : (int)(range & 0xFFFFu),
+                  full ? INT_MAX : (int)(range >> 16));
+        pop_held<7, 1>(s, x, held1);
+    } else if (lane_id() == 0) {
+        atomicAdd(s.errors, 1u);
+    }
+    pop_held<7, 0>(s, v, held0);
+}
+
+static __host__ __device__ int k7_hash_offset(int max_n, int seg_cap)
+{
+    return (lds_layout(7, max_n, seg_cap, 0).total + 7) & ~7;
+}
+
+__global__ __launch_bounds__(kWave) void k7_kernel(const DevGraph *graphs, const int4 *units,
+                                                   uint32_t unit_cap, uint32_t unit_end,
+                                                   uint32_t *counters, K7Tables t, EnumConfig cfg)
+{
+    extern __shared__ uint32_t lds[];
+    char *base = reinterpret_cast<char *>(lds);
+    EnumState<7> s;
+    const LdsLayout lay = lds_layout(7, cfg.max_n, cfg.seg_cap, 0);
+    init_state(s, base, lay, cfg, counters, nullptr, 0u);
+    K7Wave w7;
+    w7.hkey = reinterpret_cast<Code7 *>(base + k7_hash_offset(cfg.max_n, cfg.seg_cap));
+    w7.hcnt = reinterpret_cast<uint32_t *>(w7.hkey + kHash7Slots);
+    w7.hused = 0;
+    w7.hpending = 0;
+    w7.graph = 0;
+    for (int i = lane_id(); i < kHash7Slots; i += kWave) {
+        w7.hkey[i] = kNoCode;
+        w7.hcnt[i] = 0u;
+    }
+    __syncthreads();
+
+    // the persistent queue loop of the enumeration kernel, flushing this
+    // kernel's hash when the graph changes
+    const uint32_t navail = counters[kNumUnits];
+    const uint32_t cap = unit_cap < unit_end ? unit_cap : unit_end;
+    const uint32_t end = navail < cap ? navail : cap;
+    const uint32_t begin = counters[kSliceBegin];
+    const uint32_t span = end > begin ? end - begin : 0u;
+    uint32_t chunk = cfg.chunk ? cfg.chunk : span / (gridDim.x * 16u);
+    chunk = chunk < 1u ? 1u : (chunk > 16u ? 16u : chunk);
+    int cur = -1;
+    const int home = (int)(blockIdx.x % kQueues);
+    for (int q = 0; q < kQueues; ++q) {
+        const int x = (home + q) % kQueues;
+        const uint32_t lo = begin + (uint32_t)((uint64_t)span * x / kQueues);
+        const uint32_t hi = begin + (uint32_t)((uint64_t)span * (x + 1) / kQueues);
+        for (;;) {
+            uint32_t idx = 0;
+            if (lane_id() == 0) idx = atomicAdd(&counters[kQueueHeads + x * kHeadStride], chunk);
+            idx = lo + (uint32_t)uniform((int)idx);
+            if (idx >= hi) break;
+            const uint32_t stop = idx + chunk < hi ? idx + chunk : hi;
+            for (; idx < stop; ++idx) {
+                const int4 u = units[idx];
+                const int gi = uniform(u.x);
+                if (gi != cur) {
+                    if (w7.hused) flush7(s, w7, t);
+                    s.urow = graphs[gi].urow;
+                    s.uadj = graphs[gi].uadj;
+                    s.bits_out = graphs[gi].bits_out;
+                    s.bits_in = graphs[gi].bits_in;
+                    s.words = graphs[gi].words;
+                    w7.graph = gi;
+                    cur = gi;
+                }
+                run_unit7(s, w7, t, uniform(u.y), uniform(u.z), (uint32_t)uniform(u.w));
+            }
+        }
+    }
+    if (w7.hused) flush7(s, w7, t);
+}
+
+// every used class slot of every graph to (code, count) lists; n_out[g]
+// counts them (entries past cap are counted, not written)
+__global__ void k7_collect_kernel(const Code7 *class_key, const unsigned long long *class_cnt,
+                                  uint32_t slots, int64_t cap, Code7 *out_codes,
+                                  unsigned long long *out_counts, unsigned long long *n_out)
+{
+    const int gi = blockIdx.y;
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= slots) return;
+    const size_t at = (size_t)gi * slots + i;
+    const Code7 key = class_key[at];
+    if (key == kNoCode) return;
+    const unsigned long long pos = atomicAdd(&n_out[gi], 1ull);
+    if ((long long)pos < cap) {
+        out_codes[(size_t)gi * cap + pos] = key;
+        out_counts[(size_t)gi * cap + pos] = class_cnt[at];
+    }
+}
+
+int k7_lds_bytes(int max_n, int seg_cap)
+{
+    return k7_hash_offset(max_n, seg_cap) + kHash7Slots * (int)(sizeof(Code7) + sizeof(uint32_t));
+}
+
+int k7_max_blocks_per_cu(int lds_bytes, int *blocks)
+{
+    MK_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        blocks, reinterpret_cast<const void *>(&k7_kernel), kWave, (size_t)lds_bytes));
+    return MK_OK;
+}
+
+int launch_k7(const DevGraph *d_graphs, const int4 *units, uint32_t unit_cap, uint32_t *counters,
+              const K7Launch &a, const EnumConfig &cfg, int grid, int lds_bytes, hipStream_t stream)
+{
+    if (grid <= 0) return MK_OK;
+    K7Tables t;
+    t.cache_key = a.cache_key;
+    t.cache_val = a.cache_val;
+    t.cache_shift = 64 - a.cache_log2;
+    t.cache_mask = (1u << a.cache_log2) - 1u;
+    t.class_key = a.class_key;
+    t.class_cnt = a.class_cnt;
+    t.class_shift = 64 - a.class_log2;
+    t.class_mask = (1u << a.class_log2) - 1u;
+    t.totals = a.totals;
+    t.overflow = a.overflow;
+    hipLaunchKernelGGL(k7_kernel, dim3(grid), dim3(kWave), lds_bytes, stream, d_graphs, units,
+                       unit_cap, kAllUnits, counters, t, cfg);
+    MK_HIP(hipGetLastError());
+    return MK_OK;
+}
+
+int launch_k7_collect(const K7Launch &a, int ng, int64_t cap, unsigned long long *out_codes,
+                      unsigned long long *out_counts, unsigned long long *n_out, hipStream_t stream)
+{
+    if (ng <= 0) return MK_OK;
+    const uint32_t slots = 1u << a.class_log2;
+    const dim3 grid((slots + 255) / 256, (unsigned)ng);
+    hipLaunchKernelGGL(k7_collect_kernel, grid, dim3(256), 0, stream, a.class_key, a.class_cnt,
+                       slots, cap, out_codes, out_counts, n_out);
+    MK_HIP(hipGetLastError());
+    return MK_OK;
+}
+
+}  // namespace mk

@@ -286,7 +286,10 @@ int launch_plan(int k, const DevGraph *d_graphs, int ng, int64_t max_nnz, uint32
     case 6:
         return plan_k<6>(d_graphs, ng, max_nnz, total_slots, slot_cnt, slot_off, slot_est, slot_vi, scan_tmp, units,
                          unit_cap, split_threshold, waves, counters, stream);
-    default: return fail(MK_ERANGE, "plan size k=%d outside 2..6", k);
+    case 7:
+        return plan_k<7>(d_graphs, ng, max_nnz, total_slots, slot_cnt, slot_off, slot_est, slot_vi, scan_tmp, units,
+                         unit_cap, split_threshold, waves, counters, stream);
+    default: return fail(MK_ERANGE, "plan size k=%d outside 2..7", k);
     }
 }
 

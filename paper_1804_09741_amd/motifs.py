@@ -104,6 +104,8 @@ SIGNATURES = {
     "mk_table_core_mult": (ctypes.c_int, [_P, _U32, _U32, _P]),
     "mk_count": (ctypes.c_int, [_P, _P, _P, _P, ctypes.POINTER(_U64)]),
     "mk_count_batch": (ctypes.c_int, [_P, _P, _I32, _P, _P, _P]),
+    "mk_count7": (ctypes.c_int, [_P, _P, _I32, _I64, _P, _P, _P, _P,
+                                 ctypes.POINTER(ctypes.c_double)]),
     "mk_batch_create": (ctypes.c_int, [_P, _P, _I32, _P, ctypes.POINTER(BatchOpts),
                                        ctypes.POINTER(_P)]),
     "mk_batch_run": (ctypes.c_int, [_P, _P, _P]),
@@ -320,6 +322,24 @@ def mk_count_batch(ctx: int, gs: Sequence[int], t: int) -> Tuple[np.ndarray, np.
     return hist, totals
 
 
+def mk_count7(ctx: int, gs: Sequence[int], cap: int = 1 << 16):
+    """H_7 of each graph as (codes, counts) arrays sorted by canonical code,
+    plus the per-graph totals and the counting kernel's milliseconds."""
+    ng = len(gs)
+    codes = np.zeros((ng, cap), dtype=np.uint64)
+    counts = np.zeros((ng, cap), dtype=np.uint64)
+    ncls = np.zeros(ng, dtype=np.int64)
+    totals = np.zeros(ng, dtype=np.uint64)
+    ms = ctypes.c_double()
+    _check(library().mk_count7(ctx, _handles(gs), ng, cap,
+                               codes.ctypes.data_as(_P) if codes.size else None,
+                               counts.ctypes.data_as(_P) if counts.size else None,
+                               ncls.ctypes.data_as(_P) if ng else None,
+                               totals.ctypes.data_as(_P) if ng else None, ctypes.byref(ms)))
+    out = [(codes[g, :ncls[g]].copy(), counts[g, :ncls[g]].copy()) for g in range(ng)]
+    return out, totals, ms.value
+
+
 def mk_batch_create(ctx: int, gs: Sequence[int], t: int, split_threshold: int = 0,
                     waves_per_cu: int = 0, use_graph: int = 0, units_per_grab: int = 0,
                     debug_flags: int = 0, method: int = 0, adjacency: int = 0,
@@ -521,6 +541,10 @@ class Context:
 
     def count_batch(self, graphs: Sequence[Graph], table: Table):
         return mk_count_batch(self.handle, [g.handle for g in graphs], table.handle)
+
+    def count7(self, graphs: Sequence[Graph], cap: int = 1 << 16):
+        """H_7: per graph (canonical codes, counts) ascending; totals; kernel ms."""
+        return mk_count7(self.handle, [g.handle for g in graphs], cap)
 
     def batch(self, graphs: Sequence[Graph], table: Table, **opts) -> Batch:
         return Batch(self, graphs, table, **opts)

@@ -1,0 +1,106 @@
+"""k = 7 on the GPU (classes reported by canonical code): parity with the
+oracle's k = 7 histograms bit for bit, closed forms, the growth of the
+device class tables, and the argument errors."""
+
+import math
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1804_09741_amd import inputs as I
+from paper_1804_09741_amd import motifs as M
+
+pytestmark = pytest.mark.gpu
+
+
+def _count7(ctx, graphs, cap=1 << 16):
+    loaded = [ctx.load_graph(*g) for g in graphs]
+    try:
+        out, totals, ms = ctx.count7(loaded, cap)
+        return [dict(zip(c.tolist(), v.tolist())) for c, v in out], totals, ms
+    finally:
+        for g in loaded:
+            g.free()
+
+
+def test_random_batch_matches_oracle(ctx):
+    rng = np.random.default_rng(8100)
+    graphs = [I.chung_lu_digraph(int(rng.integers(20, 50)), int(rng.integers(30, 75)),
+                                 float(rng.uniform(2.0, 2.6)), 8, 0.2, rng) for _ in range(6)]
+    graphs += [I.empty_graph(5), I.directed_path(6), I.complete_digraph(9)]
+    hists, totals, ms = _count7(ctx, graphs)
+    assert ms >= 0
+    for i, g in enumerate(graphs):
+        exp = O.count(*g, 7)
+        assert hists[i] == exp, i
+        assert int(totals[i]) == sum(exp.values())
+
+
+def test_closed_forms(ctx):
+    in_star = sum(1 << (6 * i + 5) for i in range(6))
+    graphs = [I.out_star(40), I.in_star(40), I.complete_digraph(10), I.directed_cycle(7),
+              I.directed_cycle(50)]
+    hists, _, _ = _count7(ctx, graphs)
+    assert hists[0] == {63: math.comb(40, 6)}
+    assert hists[1] == {in_star: math.comb(40, 6)}
+    assert hists[2] == {(1 << 42) - 1: math.comb(10, 7)}
+    assert len(hists[3]) == 1 and sum(hists[3].values()) == 1
+    assert len(hists[4]) == 1 and sum(hists[4].values()) == 50
+
+
+def test_hub_and_relabel(ctx):
+    """A hub of degree 30 inside a random graph, and a relabeled copy: the
+    same histogram, equal to the oracle's."""
+    rng = np.random.default_rng(8200)
+    n = 80
+    src = [0] * 30 + rng.integers(1, n, size=50).tolist()
+    dst = list(range(1, 31)) + rng.integers(1, n, size=50).tolist()
+    arcs = [(u, v) for u, v in dict.fromkeys(zip(src, dst)) if u != v]
+    g = I.csr_from_arcs(n, [u for u, _ in arcs], [v for _, v in arcs])
+    g2 = I.relabel(*g, rng.permutation(n))
+    hists, _, _ = _count7(ctx, [g, g2])
+    assert hists[0] == hists[1] == O.count(*g, 7)
+
+
+def test_class_tables_grow(tmp_path):
+    """A fresh context starts with small class tables; a graph with a few
+    thousand classes overflows them and the count is redone with larger
+    ones, with the oracle's result."""
+    rng = np.random.default_rng(8300)
+    g = I.chung_lu_digraph(50, 80, 2.2, 8, 0.2, rng)
+    exp = O.count(*g, 7)
+    assert len(exp) > 4096
+    c = M.Context(0)
+    try:
+        gr = c.load_graph(*g)
+        out, totals, _ = c.count7([gr])
+        gr.free()
+    finally:
+        c.close()
+    codes, counts = out[0]
+    assert dict(zip(codes.tolist(), counts.tolist())) == exp
+    assert int(totals[0]) == sum(exp.values())
+
+
+def test_errors(ctx):
+    g = ctx.load_graph(*I.complete_digraph(9))
+    big = ctx.load_graph(*I.er_digraph(M.MK_LDS_MARKS_MAX_VERTICES + 1, 100,
+                                       np.random.default_rng(8400)))
+    try:
+        with pytest.raises(M.MotifsError) as e:
+            ctx.count7([big])
+        assert e.value.status == M.MK_ERANGE
+        rng = np.random.default_rng(8401)
+        many = ctx.load_graph(*I.chung_lu_digraph(30, 50, 2.2, 8, 0.2, rng))
+        try:
+            with pytest.raises(M.MotifsError) as e:
+                ctx.count7([many], cap=2)
+            assert e.value.status == M.MK_ERANGE
+        finally:
+            many.free()
+        out, totals, _ = ctx.count7([g], cap=1)
+        assert out[0][0].tolist() == [(1 << 42) - 1] and int(totals[0]) == 36
+    finally:
+        g.free()
+        big.free()
