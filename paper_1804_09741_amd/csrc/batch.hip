@@ -133,7 +133,7 @@ extern "C" int mk_graph_footprint(const mk_graph *g, int k, uint64_t *bytes)
     const uint64_t scratch =
         k <= 5 && !big ? 4ull * kParentArcCap * std::min<uint64_t>(g->nnz_u + 1, 8192) : 0;
     // per-workgroup marks, at most 32 workgroups per CU and 1/16 of the memory
-    const uint64_t per_wave = ((n + 63) & ~63ull) * (k <= 5 ? 2 : 4);
+    const uint64_t per_wave = ((n + 63) & ~63ull) * 4;
     const uint64_t marks =
         big ? std::min<uint64_t>((uint64_t)g->ctx->hbm_bytes / 16,
                                  (uint64_t)g->ctx->num_cus * 32 * per_wave)
@@ -398,7 +398,7 @@ static int batch_create(mk_ctx *ctx, const mk_graph *const *gs, int32_t ng, int 
         // one private marks array per workgroup, rounded to 64 entries; all
         // of them together within 1/16 of the device memory
         b->mark_stride = ((size_t)std::max(b->max_n, 1) + 63) & ~(size_t)63;
-        const size_t per_wave = b->mark_stride * (b->k <= 5 ? 2 : 4);
+        const size_t per_wave = b->mark_stride * 4;  // 32-bit marks in device memory
         const uint64_t budget = (uint64_t)ctx->hbm_bytes / 16;
         const uint64_t fit = std::max<uint64_t>(budget / per_wave, 1);
         b->max_grid = (int)std::min<uint64_t>((uint64_t)b->max_grid, fit);
@@ -429,7 +429,7 @@ static int batch_create(mk_ctx *ctx, const mk_graph *const *gs, int32_t ng, int 
     if (b->marks == MK_MARKS_GLOBAL) {
         // zero once: every pop restores the marks it changed, so they are
         // zero again whenever a workgroup finishes a unit
-        b->mark_bytes = b->mark_stride * (b->k <= 5 ? 2 : 4) * (size_t)b->grid;
+        b->mark_bytes = b->mark_stride * 4 * (size_t)b->grid;
         BAIL_HIP(hipMalloc(&b->d_marks, b->mark_bytes));
         rc = fill_u32(b->d_marks, 0, b->mark_bytes / 4, ctx->stream);
         if (rc) return bail(rc);

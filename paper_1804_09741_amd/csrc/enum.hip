@@ -240,8 +240,10 @@ __device__ void last_two_small(EnumState<K, V> &s, const int (&st)[K - 1],
     __syncthreads();
 }
 
-// k = 6 nodes with at most one wave of extension vertices: the pairs inside
-// E are counted per pair of cells, as in Section 3's loop over L_{k-2}.  Two
+// Nodes with at most one wave of extension vertices, when marks are 32-bit
+// (k = 6, and every k with marks in device memory): the pairs inside E are
+// counted per pair of cells, as in Section 3's loop over L_{k-2}, with no
+// arc test between two extension vertices.  Two
 // vertices with equal marks relate alike to the members, so all pairs of E
 // from cells A and B without an arc between them have one code; there are
 // C(n_A, 2) or n_A n_B of them.  The arcs inside E are found while the
@@ -255,7 +257,7 @@ template <int K, int V>
 __device__ void last_two_cells(EnumState<K, V> &s, const int (&st)[K - 1],
                                const int (&rem)[K - 2], int e, uint32_t code, int jlo)
 {
-    static_assert(K == 6, "E tags need the 32-bit marks of k = 6");
+    static_assert(sizeof(MarkT<K, V>) == 4, "E tags need 32-bit marks");
     constexpr int NQ = K - 2;
     constexpr int P1 = K - 2, P2 = K - 1;
     constexpr int B_WU = (K - 2) * (K - 1) + (K - 2);
@@ -273,7 +275,7 @@ __device__ void last_two_cells(EnumState<K, V> &s, const int (&st)[K - 1],
         deg = s.urow[vtx + 1] - row;
     }
     if (!inE) deg = 0;
-    if (inE) s.mark[vtx] = (MarkT<K>)(m0 | kETag | ((uint32_t)lane << 24));
+    if (inE) s.mark[vtx] = (MarkT<K, V>)(m0 | kETag | ((uint32_t)lane << 24));
     __syncthreads();
     auto tbits = [](uint32_t t) { return ((t & 1u) << B_WU) | ((t >> 1) << B_UW); };
 
@@ -385,7 +387,7 @@ __device__ void last_two_cells(EnumState<K, V> &s, const int (&st)[K - 1],
     uint32_t *cc1 = s.scratch + kWave, *cc2 = s.scratch + 2 * kWave;
     if (leader) {
         const int rk = (int)lanes_below(leaders);
-        cc1[rk] = cb1 | (size << 24);  // cb1 < 2^24 for k = 6
+        cc1[rk] = cb1 | (size << 24);  // cb1 < 2^24 for k <= 6
         cc2[rk] = cb2;
     }
     __syncthreads();
@@ -412,7 +414,7 @@ __device__ void last_two_cells(EnumState<K, V> &s, const int (&st)[K - 1],
         }
         hash_insert<K>(s, valid, c, w);
     }
-    if (inE) s.mark[vtx] = (MarkT<K>)m0;
+    if (inE) s.mark[vtx] = (MarkT<K, V>)m0;
     __syncthreads();
 }
 
@@ -444,7 +446,7 @@ __device__ void last_two(EnumState<K, V> &s, const int (&st)[K - 1], uint32_t co
     const int hi = e < jhi ? e : jhi;
     if (jlo >= hi) return;
     if (e <= kWave && hi == e) {
-        if constexpr (K == 6) last_two_cells<K>(s, st, rem, e, code, jlo);
+        if constexpr (sizeof(MarkT<K, V>) == 4) last_two_cells<K>(s, st, rem, e, code, jlo);
         else last_two_small<K>(s, st, rem, e, code, jlo);
         return;
     }

@@ -107,16 +107,17 @@ __host__ __device__ inline LdsLayout lds_layout(int k, int max_n, int seg_cap, i
 // Marks hold, for members at positions 0..kSegments-1, the "in" bits spread
 // at stride k-1 (highest at (kSegments-1)(k-1)) and then one "out" bit per
 // position: 5 / 6 / 12 / 20 bits for k = 3 / 4 / 5 / 6, so 16-bit marks do
-// for k <= 5.
-template <int K>
-using MarkT = typename std::conditional<K <= 5, uint16_t, uint32_t>::type;
+// for k <= 5 in LDS.  Marks in device memory are 32-bit for every k (room
+// for the extension-list tags of last_two_cells).
+template <int K, int V = 0>
+using MarkT = typename std::conditional<K <= 5 && (V & kVarGlobal) == 0, uint16_t, uint32_t>::type;
 
 template <int K, int V = 0>
 struct EnumState {
     static constexpr int OUTB = (kSegments<K> - 1) * (K - 1) + 1;
     static constexpr uint32_t INMASK = (1u << OUTB) - 1u;
-    static_assert(OUTB + kSegments<K> <= 8 * (int)sizeof(MarkT<K>), "mark bits do not fit");
-    MarkT<K> *mark;             // LDS, or this wave's global array (kVarGlobal)
+    static_assert(OUTB + kSegments<K> <= 8 * (int)sizeof(MarkT<K, V>), "mark bits do not fit");
+    MarkT<K, V> *mark;          // LDS, or this wave's global array (kVarGlobal)
     SegT<V> *seg;               // vertex ids
     int seg_cap;
     int root;
@@ -185,7 +186,7 @@ __device__ __forceinline__ void push(EnumState<K, V> &s, int x)
         const unsigned long long bal = __ballot(fresh);
         if (fresh) seg[cnt + (int)lanes_below(bal)] = (SegT<V>)y;
         cnt += __popcll(bal);
-        if (valid) s.mark[y] = (MarkT<K>)(m | mark_bits<K>(D, ent & 3u));
+        if (valid) s.mark[y] = (MarkT<K, V>)(m | mark_bits<K>(D, ent & 3u));
     }
     s.len[D] = cnt;
     __syncthreads();
@@ -203,7 +204,7 @@ __device__ __forceinline__ void pop(EnumState<K, V> &s, int x)
         const int e = base + lane;
         if (e < r1) {
             const int y = (int)(s.uadj[e] >> 2);
-            s.mark[y] = (MarkT<K>)(s.mark[y] & keep);
+            s.mark[y] = (MarkT<K, V>)(s.mark[y] & keep);
         }
     }
     __syncthreads();
@@ -242,7 +243,7 @@ __device__ __forceinline__ Held push_held(EnumState<K, V> &s, int x)
     const bool fresh = valid && y > s.root && h.m == 0u;
     const unsigned long long bal = __ballot(fresh);
     if (fresh) seg[(int)lanes_below(bal)] = (SegT<V>)y;
-    if (valid) s.mark[y] = (MarkT<K>)(h.m | mark_bits<K>(D, h.ent & 3u));
+    if (valid) s.mark[y] = (MarkT<K, V>)(h.m | mark_bits<K>(D, h.ent & 3u));
     s.len[D] = __popcll(bal);
     __syncthreads();
     return h;
@@ -256,7 +257,7 @@ __device__ __forceinline__ void pop_held(EnumState<K, V> &s, int x, const Held &
         pop<K, D>(s, x);
         return;
     }
-    if (lane_id() < h.n) s.mark[h.ent >> 2] = (MarkT<K>)h.m;
+    if (lane_id() < h.n) s.mark[h.ent >> 2] = (MarkT<K, V>)h.m;
     __syncthreads();
 }
 
@@ -373,9 +374,9 @@ __device__ __forceinline__ void init_state(EnumState<K, V> &s, char *base, const
                                            const uint32_t *table, uint32_t num_classes)
 {
     if constexpr ((V & kVarGlobal) != 0)
-        s.mark = reinterpret_cast<MarkT<K> *>(cfg.marks) + (size_t)blockIdx.x * cfg.mark_stride;
+        s.mark = reinterpret_cast<MarkT<K, V> *>(cfg.marks) + (size_t)blockIdx.x * cfg.mark_stride;
     else
-        s.mark = reinterpret_cast<MarkT<K> *>(base);
+        s.mark = reinterpret_cast<MarkT<K, V> *>(base);
     s.seg = reinterpret_cast<SegT<V> *>(base + lay.seg);
     s.seg_cap = cfg.seg_cap;
     s.flags = cfg.flags;
