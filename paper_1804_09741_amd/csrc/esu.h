@@ -409,15 +409,15 @@ __device__ __forceinline__ void init_state(EnumState<K, V> &s, char *base, const
 }
 
 // The persistent loop: take units from the kQueues queues (own XCD's range
-// first) and call run(v, i, range) for each, switching the graph (and
-// flushing the hash) when the unit's graph changes.  The hash is flushed at
-// the end.
-template <int K, int V, typename Run>
-__device__ __forceinline__ void for_each_unit(EnumState<K, V> &s, const DevGraph *graphs,
-                                              const int4 *units, uint32_t unit_cap,
-                                              uint32_t unit_end, uint32_t *counters,
-                                              unsigned long long *hist_base, const EnumConfig &cfg,
-                                              Run run)
+// first) and call run(v, i, range) for each.  When the unit's graph changes,
+// on_switch(gi) runs first (a kernel flushes what it holds for the previous
+// graph there) and the state is pointed at the new graph; after_unit() runs
+// after every unit.
+template <int K, int V, typename Run, typename Switch, typename After>
+__device__ __forceinline__ void unit_loop(EnumState<K, V> &s, const DevGraph *graphs,
+                                          const int4 *units, uint32_t unit_cap, uint32_t unit_end,
+                                          uint32_t *counters, const EnumConfig &cfg, Run run,
+                                          Switch on_switch, After after_unit)
 {
     const uint32_t navail = counters[kNumUnits];
     const uint32_t cap = unit_cap < unit_end ? unit_cap : unit_end;
@@ -444,20 +444,40 @@ __device__ __forceinline__ void for_each_unit(EnumState<K, V> &s, const DevGraph
                 const int4 u = units[idx];
                 const int gi = uniform(u.x);
                 if (gi != cur) {
-                    if (s.hused) flush_hash<K>(s);
+                    on_switch(gi);
                     s.urow = graphs[gi].urow;
                     s.uadj = graphs[gi].uadj;
                     s.bits_out = graphs[gi].bits_out;
                     s.bits_in = graphs[gi].bits_in;
                     s.words = graphs[gi].words;
-                    s.hist = hist_base + (size_t)gi * s.num_classes;
                     cur = gi;
                 }
                 run(uniform(u.y), uniform(u.z), (uint32_t)uniform(u.w));
-                if (s.hused > (int)((s.hmask + 1) >> 2)) flush_hash<K>(s);
+                after_unit();
             }
         }
     }
+}
+
+// unit_loop for the kernels that count into dense histograms through the
+// state's hash: flushed on a graph switch, once a quarter full after a
+// unit, and at the end
+template <int K, int V, typename Run>
+__device__ __forceinline__ void for_each_unit(EnumState<K, V> &s, const DevGraph *graphs,
+                                              const int4 *units, uint32_t unit_cap,
+                                              uint32_t unit_end, uint32_t *counters,
+                                              unsigned long long *hist_base, const EnumConfig &cfg,
+                                              Run run)
+{
+    unit_loop(
+        s, graphs, units, unit_cap, unit_end, counters, cfg, run,
+        [&](int gi) {
+            if (s.hused) flush_hash<K>(s);
+            s.hist = hist_base + (size_t)gi * s.num_classes;
+        },
+        [&] {
+            if (s.hused > (int)((s.hmask + 1) >> 2)) flush_hash<K>(s);
+        });
     if (s.hused) flush_hash<K>(s);
 }
 

@@ -19,7 +19,11 @@ namespace mk {
 
 using Code7 = unsigned long long;
 constexpr Code7 kNoCode = ~0ull;       // free slot / value not written yet
-constexpr int kHash7Slots = 256;       // per-wave LDS hash
+#ifndef MK_K7_HASH_BITS
+#define MK_K7_HASH_BITS 8
+#endif
+constexpr int kHash7Bits = MK_K7_HASH_BITS;    // per-wave LDS hash: 2^bits slots
+constexpr int kHash7Slots = 1 << kHash7Bits;
 constexpr int kHash7Probes = 8;
 constexpr int kCacheProbes = 32;
 constexpr int kClassProbes = 64;
@@ -193,7 +197,7 @@ __device__ void hash7_insert(EnumState<7> &s, K7Wave &w, const K7Tables &t, bool
     for (;;) {
         bool fresh = false;
         if (pending) {
-            uint32_t h = hash7(code, 64 - 8);
+            uint32_t h = hash7(code, 64 - kHash7Bits);
             for (int p = 0; p < kHash7Probes; ++p) {
                 const Code7 old = atomicCAS(&w.hkey[h], kNoCode, code);
                 if (old == kNoCode || old == code) {
@@ -451,44 +455,14 @@ __global__ __launch_bounds__(kWave) void k7_kernel(const DevGraph *graphs, const
     }
     __syncthreads();
 
-    // the persistent queue loop of the enumeration kernel, flushing this
-    // kernel's hash when the graph changes
-    const uint32_t navail = counters[kNumUnits];
-    const uint32_t cap = unit_cap < unit_end ? unit_cap : unit_end;
-    const uint32_t end = navail < cap ? navail : cap;
-    const uint32_t begin = counters[kSliceBegin];
-    const uint32_t span = end > begin ? end - begin : 0u;
-    uint32_t chunk = cfg.chunk ? cfg.chunk : span / (gridDim.x * 16u);
-    chunk = chunk < 1u ? 1u : (chunk > 16u ? 16u : chunk);
-    int cur = -1;
-    const int home = (int)(blockIdx.x % kQueues);
-    for (int q = 0; q < kQueues; ++q) {
-        const int x = (home + q) % kQueues;
-        const uint32_t lo = begin + (uint32_t)((uint64_t)span * x / kQueues);
-        const uint32_t hi = begin + (uint32_t)((uint64_t)span * (x + 1) / kQueues);
-        for (;;) {
-            uint32_t idx = 0;
-            if (lane_id() == 0) idx = atomicAdd(&counters[kQueueHeads + x * kHeadStride], chunk);
-            idx = lo + (uint32_t)uniform((int)idx);
-            if (idx >= hi) break;
-            const uint32_t stop = idx + chunk < hi ? idx + chunk : hi;
-            for (; idx < stop; ++idx) {
-                const int4 u = units[idx];
-                const int gi = uniform(u.x);
-                if (gi != cur) {
-                    if (w7.hused) flush7(s, w7, t);
-                    s.urow = graphs[gi].urow;
-                    s.uadj = graphs[gi].uadj;
-                    s.bits_out = graphs[gi].bits_out;
-                    s.bits_in = graphs[gi].bits_in;
-                    s.words = graphs[gi].words;
-                    w7.graph = gi;
-                    cur = gi;
-                }
-                run_unit7(s, w7, t, uniform(u.y), uniform(u.z), (uint32_t)uniform(u.w));
-            }
-        }
-    }
+    unit_loop(
+        s, graphs, units, unit_cap, unit_end, counters, cfg,
+        [&](int v, int i, uint32_t range) { run_unit7(s, w7, t, v, i, range); },
+        [&](int gi) {
+            if (w7.hused) flush7(s, w7, t);
+            w7.graph = gi;
+        },
+        [] {});
     if (w7.hused) flush7(s, w7, t);
 }
 
