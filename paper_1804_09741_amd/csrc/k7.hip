@@ -44,10 +44,13 @@ struct K7Tables {
 // per-wave hash of pending (labeled code, count) pairs in LDS
 struct K7Wave {
     Code7 *hkey;
-    uint32_t *hcnt;
+    uint32_t *hcnt;    // 32-bit two's complement counts (corrections are negative)
     int hused;
     uint32_t hpending;
     int graph;
+    uint8_t *etag;     // per vertex: 0x80 | lane while it is in a small node's E
+    Code7 *cc1, *cc2;  // per cell of E: code bits at positions 5 and 6
+    uint32_t *csz;     //   and its size
 };
 
 __device__ __forceinline__ uint32_t hash7(Code7 c, int shift)
@@ -162,18 +165,20 @@ __device__ void flush7(EnumState<7> &s, K7Wave &w, const K7Tables &t)
             }
         }
         if (live && cnt != 0u) {
+            // sign-extended: the 64-bit sums stay exact modulo 2^64
+            const unsigned long long add = (unsigned long long)(long long)(int32_t)cnt;
             uint32_t h = hash7(canon, t.class_shift);
             bool done = false;
             for (int p = 0; p < kClassProbes && !done; ++p) {
                 const Code7 old = atomicCAS(&ckey[h], kNoCode, canon);
                 if (old == kNoCode || old == canon) {
-                    atomicAdd(&ccnt[h], (unsigned long long)cnt);
+                    atomicAdd(&ccnt[h], add);
                     done = true;
                 }
                 h = (h + 1) & t.class_mask;
             }
             if (!done) atomicAdd(t.overflow, 1u);
-            tot += cnt;
+            tot += add;
         }
         if (live) {
             w.hkey[i] = kNoCode;
@@ -232,6 +237,22 @@ __device__ void count7(EnumState<7> &s, K7Wave &w, const K7Tables &t, bool valid
     hash7_insert(s, w, t, valid && n > 0, code, n);
 }
 
+// count each valid lane's code with weight -1 (merged like count7)
+__device__ void uncount7(EnumState<7> &s, K7Wave &w, const K7Tables &t, bool valid, Code7 code)
+{
+    const int lane = lane_id();
+    const unsigned long long act = __ballot(valid);
+    if (!act) return;
+    w.hpending += (uint32_t)__popcll(act);
+    const int l = __builtin_ctzll(act);
+    const Code7 c0 = readlane64(code, l);
+    const unsigned long long eq = __ballot(valid && code == c0) & act;
+    uint32_t n = 1;
+    if (lane == l) n = (uint32_t)__popcll(eq);
+    else if ((eq >> lane) & 1ull) n = 0;
+    hash7_insert(s, w, t, valid && n > 0, code, 0u - n);
+}
+
 // position in seg storage of element a of the extension list made of the
 // tails seg[q][st[q]:], q < NQ
 template <int NQ>
@@ -254,6 +275,189 @@ __device__ __forceinline__ int ext_addr7(const EnumState<7> &s, const int (&st)[
     return addr;
 }
 
+// lane l's value of v (every lane active: a permute reads 0 from an
+// inactive lane)
+__device__ __forceinline__ uint32_t from_lane7(uint32_t v, int l)
+{
+    return (uint32_t)__builtin_amdgcn_ds_bpermute(l << 2, (int)v);
+}
+
+__device__ __forceinline__ Code7 from_lane64(Code7 v, int l)
+{
+    return ((Code7)from_lane7((uint32_t)(v >> 32), l) << 32) | from_lane7((uint32_t)v, l);
+}
+
+// Nodes with at most one wave of extension vertices: the pairs inside E are
+// counted per pair of cells, as in Section 3's loop over L_{k-2}.  Vertices
+// of E with equal marks relate alike to the members, so all pairs from
+// cells A and B without an arc between them have one class; there are
+// C(n_A, 2) or n_A n_B of them.  The arcs inside E are found while the
+// children's lists are scanned for their exclusive neighbours: E's vertices
+// carry a tag with their lane meanwhile, and each arc (w, u), u after w,
+// adds one to its own code and takes one from its cell pair's.  Lane l holds
+// E[l], its code bits for positions 5 and 6 and its list row; a child of
+// degree >= kRowMin is scanned alone.
+__device__ void last_two7_cells(EnumState<7> &s, K7Wave &w7, const K7Tables &t, const int (&st)[6],
+                                const int (&rem)[5], int e, Code7 code, int jlo)
+{
+    constexpr int B_WU = bit7(5, 6), B_UW = bit7(6, 5);
+    const int lane = lane_id();
+    const bool inE = lane >= jlo && lane < e;
+    uint32_t vtx = 0;
+    Code7 cb1 = 0, cb2 = 0;
+    int row = 0, deg = 0;
+    if (lane < e) {
+        vtx = s.seg[ext_addr7<5>(s, st, rem, lane)];
+        const uint32_t m = s.mark[vtx];
+        cb1 = code_bits7(m, 5);
+        cb2 = code_bits7(m, 6);
+        row = s.urow[vtx];
+        deg = s.urow[vtx + 1] - row;
+    }
+    if (!inE) deg = 0;
+    if (inE) w7.etag[vtx] = (uint8_t)(0x80u | (uint32_t)lane);
+    __syncthreads();
+    auto tbits = [](uint32_t tt) { return ((Code7)(tt & 1u) << B_WU) | ((Code7)(tt >> 1) << B_UW); };
+
+    // children with long lists alone: exclusive neighbours by arc type, arcs
+    // to later vertices of E one by one
+    unsigned long long big = __ballot(deg >= kRowMin);
+    while (big) {
+        const int l = __builtin_ctzll(big);
+        big &= big - 1;
+        const int brow = __builtin_amdgcn_readlane(row, l);
+        const int bdeg = __builtin_amdgcn_readlane(deg, l);
+        const Code7 bcode = code | readlane64(cb1, l);
+        uint32_t n1 = 0, n2 = 0, n3 = 0;
+        for (int b = 0; b < bdeg; b += kWave) {
+            const int e2 = b + lane;
+            uint32_t tb = 0, tt = 0;
+            bool arc = false;
+            int q = 0;
+            if (e2 < bdeg) {
+                const uint32_t ent = s.uadj[brow + e2];
+                const int u = (int)(ent >> 2);
+                const uint32_t tg = w7.etag[u];
+                tt = ent & 3u;
+                if (tg & 0x80u) {
+                    q = (int)(tg & 63u);
+                    arc = q > l;
+                } else if (u > s.root && s.mark[u] == 0u) {
+                    tb = tt;
+                }
+            }
+            n1 += (uint32_t)__popcll(__ballot(tb == 1u));
+            n2 += (uint32_t)__popcll(__ballot(tb == 2u));
+            n3 += (uint32_t)__popcll(__ballot(tb == 3u));
+            const Code7 cm = bcode | from_lane64(cb2, q);
+            count7(s, w7, t, arc, cm | tbits(tt));
+            uncount7(s, w7, t, arc, cm);
+        }
+        const uint32_t tl = (uint32_t)lane + 1u;
+        const uint32_t nl = lane == 0 ? n1 : (lane == 1 ? n2 : n3);
+        w7.hpending += n1 + n2 + n3;
+        hash7_insert(s, w7, t, lane < 3 && nl > 0, bcode | tbits(tl), nl);
+    }
+    if (deg >= kRowMin) deg = 0;
+    int incl = deg;
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        const int o = __shfl_up(incl, d, kWave);
+        if (lane >= d) incl += o;
+    }
+    const int totB = uniform(__shfl(incl, kWave - 1, kWave));
+    uint32_t *pre = s.scratch;
+    pre[lane] = (uint32_t)incl;
+    __syncthreads();
+    // the short lists, flat: exclusive neighbours and arcs inside E
+    for (int base = 0; base < totB; base += kWave) {
+        const int f = base + lane;
+        const bool valid = f < totB;
+        int src1 = 0, off = 0;
+        if (valid) {
+            int lo = 0;
+#pragma unroll
+            for (int step = kWave / 2; step > 0; step >>= 1)
+                lo += ((int)pre[lo + step - 1] <= f) ? step : 0;
+            src1 = lo;
+            off = f - (lo ? (int)pre[lo - 1] : 0);
+        }
+        // the permutes run with every lane active
+        const int r1 = (int)from_lane7((uint32_t)row, src1);
+        const Code7 c1 = from_lane64(cb1, src1);
+        bool bv = false, arc = false;
+        uint32_t tt = 0;
+        int q = 0;
+        if (valid) {
+            const uint32_t ent = s.uadj[r1 + off];
+            const int u = (int)(ent >> 2);
+            const uint32_t tg = w7.etag[u];
+            tt = ent & 3u;
+            if (tg & 0x80u) {
+                q = (int)(tg & 63u);
+                arc = q > src1;
+            } else {
+                bv = u > s.root && s.mark[u] == 0u;
+            }
+        }
+        const Code7 cm = code | c1 | from_lane64(cb2, q);
+        count7(s, w7, t, bv, code | c1 | tbits(tt));
+        count7(s, w7, t, arc, cm | tbits(tt));
+        uncount7(s, w7, t, arc, cm);
+    }
+    __syncthreads();
+
+    // the cells of E (vertices with equal marks) and their pairs
+    const Code7 key = inE ? cb1 : kNoCode;
+    unsigned long long left = __ballot(inE);
+    bool leader = false;
+    uint32_t size = 0;
+    while (left) {
+        const int l = __builtin_ctzll(left);
+        const Code7 k0 = readlane64(key, l);
+        const unsigned long long eq = __ballot(key == k0) & left;
+        if (lane == l) {
+            leader = true;
+            size = (uint32_t)__popcll(eq);
+        }
+        left &= ~eq;
+    }
+    const unsigned long long leaders = __ballot(leader);
+    const int ncell = __popcll(leaders);
+    if (leader) {
+        const int rk = (int)lanes_below(leaders);
+        w7.cc1[rk] = cb1;
+        w7.cc2[rk] = cb2;
+        w7.csz[rk] = size;
+    }
+    __syncthreads();
+    const int mm = e - jlo;
+    const uint32_t all_pairs = (uint32_t)(mm * (mm - 1) / 2);
+    if (w7.hpending + all_pairs >= kPendingMax) flush7(s, w7, t);
+    w7.hpending += all_pairs;
+    const int ncp = ncell * (ncell + 1) / 2;
+    for (int pb = 0; pb < ncp; pb += kWave) {
+        const int p = pb + lane;
+        bool valid = p < ncp;
+        Code7 c = 0;
+        uint32_t w = 0;
+        if (valid) {
+            // p = z(z+1)/2 + y with y <= z
+            int z = (int)((__builtin_amdgcn_sqrtf(8.0f * (float)p + 1.0f) - 1.0f) * 0.5f);
+            if ((z + 1) * (z + 2) / 2 <= p) ++z;
+            if (z * (z + 1) / 2 > p) --z;
+            const int y = p - z * (z + 1) / 2;
+            const uint32_t ny = w7.csz[y], nz = w7.csz[z];
+            w = y == z ? ny * (ny - 1u) / 2u : ny * nz;
+            c = code | w7.cc1[y] | w7.cc2[z];
+            valid = w > 0u;
+        }
+        hash7_insert(s, w7, t, valid, c, w);
+    }
+    if (inE) w7.etag[vtx] = 0;
+    __syncthreads();
+}
+
 // The last two levels of a node X with members s_0..s_4 and extension list
 // E: child w = E[i] (i in [jlo, jhi)) closes X + {w, u} for (A) u = E[j],
 // j > i (arc w - u from the bit matrices) and (B) u an exclusive neighbour
@@ -274,6 +478,10 @@ __device__ void last_two7(EnumState<7> &s, K7Wave &w7, const K7Tables &t, const 
     }
     const int hi = e < jhi ? e : jhi;
     if (jlo >= hi) return;
+    if (e <= kWave && hi == e) {
+        last_two7_cells(s, w7, t, st, rem, e, code, jlo);
+        return;
+    }
 
     // (A) pairs (E[i], E[j]), jlo <= i < hi, i < j < e, row by row
     const int rows = hi - jlo;
@@ -429,9 +637,22 @@ __device__ void run_unit7(EnumState<7> &s, K7Wave &w7, const K7Tables &t, int v,
     pop_held<7, 0>(s, v, held0);
 }
 
+// this kernel's part of a wave's LDS, after the shared layout: the hash
+// (u64 keys, u32 counts), the cell table (2 x u64 + u32 per cell), the
+// extension tags (a byte per vertex)
 static __host__ __device__ int k7_hash_offset(int max_n, int seg_cap)
 {
     return (lds_layout(7, max_n, seg_cap, 0).total + 7) & ~7;
+}
+
+static __host__ __device__ int k7_cells_offset(int max_n, int seg_cap)
+{
+    return k7_hash_offset(max_n, seg_cap) + kHash7Slots * (int)(sizeof(Code7) + sizeof(uint32_t));
+}
+
+static __host__ __device__ int k7_tags_offset(int max_n, int seg_cap)
+{
+    return k7_cells_offset(max_n, seg_cap) + kWave * (int)(2 * sizeof(Code7) + sizeof(uint32_t));
 }
 
 __global__ __launch_bounds__(kWave) void k7_kernel(const DevGraph *graphs, const int4 *units,
@@ -446,6 +667,11 @@ __global__ __launch_bounds__(kWave) void k7_kernel(const DevGraph *graphs, const
     K7Wave w7;
     w7.hkey = reinterpret_cast<Code7 *>(base + k7_hash_offset(cfg.max_n, cfg.seg_cap));
     w7.hcnt = reinterpret_cast<uint32_t *>(w7.hkey + kHash7Slots);
+    w7.cc1 = reinterpret_cast<Code7 *>(base + k7_cells_offset(cfg.max_n, cfg.seg_cap));
+    w7.cc2 = w7.cc1 + kWave;
+    w7.csz = reinterpret_cast<uint32_t *>(w7.cc2 + kWave);
+    w7.etag = reinterpret_cast<uint8_t *>(base + k7_tags_offset(cfg.max_n, cfg.seg_cap));
+    for (int i = lane_id(); i < cfg.max_n; i += kWave) w7.etag[i] = 0;
     w7.hused = 0;
     w7.hpending = 0;
     w7.graph = 0;
@@ -466,8 +692,9 @@ __global__ __launch_bounds__(kWave) void k7_kernel(const DevGraph *graphs, const
     if (w7.hused) flush7(s, w7, t);
 }
 
-// every used class slot of every graph to (code, count) lists; n_out[g]
-// counts them (entries past cap are counted, not written)
+// every used class slot with a non-zero count of every graph to (code,
+// count) lists; n_out[g] counts them (entries past cap are counted, not
+// written)
 __global__ void k7_collect_kernel(const Code7 *class_key, const unsigned long long *class_cnt,
                                   uint32_t slots, int64_t cap, Code7 *out_codes,
                                   unsigned long long *out_counts, unsigned long long *n_out)
@@ -477,7 +704,8 @@ __global__ void k7_collect_kernel(const Code7 *class_key, const unsigned long lo
     if (i >= slots) return;
     const size_t at = (size_t)gi * slots + i;
     const Code7 key = class_key[at];
-    if (key == kNoCode) return;
+    // a class whose corrections cancel keeps a slot with count 0
+    if (key == kNoCode || class_cnt[at] == 0ull) return;
     const unsigned long long pos = atomicAdd(&n_out[gi], 1ull);
     if ((long long)pos < cap) {
         out_codes[(size_t)gi * cap + pos] = key;
@@ -487,7 +715,7 @@ __global__ void k7_collect_kernel(const Code7 *class_key, const unsigned long lo
 
 int k7_lds_bytes(int max_n, int seg_cap)
 {
-    return k7_hash_offset(max_n, seg_cap) + kHash7Slots * (int)(sizeof(Code7) + sizeof(uint32_t));
+    return k7_tags_offset(max_n, seg_cap) + ((max_n + 3) & ~3);
 }
 
 int k7_max_blocks_per_cu(int lds_bytes, int *blocks)
