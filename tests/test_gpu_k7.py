@@ -101,6 +101,16 @@ def test_errors(ctx):
             many.free()
         out, totals, _ = ctx.count7([g], cap=1)
         assert out[0][0].tolist() == [(1 << 42) - 1] and int(totals[0]) == 36
+        # cap 0: counts only; a graph without 7-sets fits, one with classes not
+        tiny = ctx.load_graph(*I.directed_path(5))
+        try:
+            out, totals, _ = ctx.count7([tiny], cap=0)
+            assert len(out[0][0]) == 0 and int(totals[0]) == 0
+            with pytest.raises(M.MotifsError) as e:
+                ctx.count7([g], cap=0)
+            assert e.value.status == M.MK_ERANGE
+        finally:
+            tiny.free()
     finally:
         g.free()
         big.free()

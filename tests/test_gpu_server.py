@@ -50,6 +50,31 @@ def test_served_equals_alone(ctx):
         g.free()
 
 
+def test_served_graph_past_lds_limit(ctx):
+    """A request whose graph is too large for LDS marks runs with marks in
+    device memory inside the server too, beside a small one."""
+    rng = np.random.default_rng(9100)
+    big = I.er_digraph(M.MK_LDS_MARKS_MAX_VERTICES + 5000, 30000, rng)
+    small = I.chung_lu_digraph(200, 600, 2.2, 30, 0.2, rng)
+    gb, gs = ctx.load_graph(*big), ctx.load_graph(*small)
+    try:
+        alone = ctx.count(gb, ctx.table(4))[0]
+        srv = ctx.server(tick_units=64)
+        try:
+            t1 = srv.submit(gb, 4)
+            t2 = srv.submit(gs, 5)
+            h1, _ = srv.wait(t1, 4)
+            h2, _ = srv.wait(t2, 5)
+        finally:
+            srv.stop()
+        assert np.array_equal(h1, alone)
+        assert_hist_equals_oracle(h1, ctx.table(4).class_codes(), *big, 4)
+        assert_hist_equals_oracle(h2, ctx.table(5).class_codes(), *small, 5)
+    finally:
+        gb.free()
+        gs.free()
+
+
 def test_admission_by_footprint(ctx):
     reqs = _requests(2, 6)
     graphs = [ctx.load_graph(*g) for _, g in reqs]
