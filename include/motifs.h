@@ -332,17 +332,18 @@ int mk_batch_timing(mk_batch *b, double *pass_ms, double *enum_ms);
 
 void mk_batch_free(mk_batch *b);
 
-/* H_7 of ng graphs (each with n <= MK_LDS_MARKS_MAX_VERTICES).  Section 1
-   counts 880,471,142 classes of 7-vertex digraphs, too many for a table of
-   all 2^42 codes, so classes are reported by canonical code: the minimum
-   adjacency code over the 5040 relabelings (the rule behind the k <= 6 class
-   ids).  The subgraphs are enumerated as for k <= 6 and canonicalised on the
-   device.  For graph g, n_classes[g] receives the number of distinct classes;
-   the first min(n_classes[g], cap) of them, ascending, go to
+/* H_7 of ng graphs.  Section 1 counts 880,471,142 classes of 7-vertex
+   digraphs, too many for a table of all 2^42 codes, so classes are reported
+   by canonical code: the minimum adjacency code over the 5040 relabelings
+   (the rule behind the k <= 6 class ids).  The subgraphs are enumerated as
+   for k <= 6 (graphs past MK_LDS_MARKS_MAX_VERTICES vertices with marks in
+   device memory and arc tests on the sorted lists) and canonicalised on the
+   device.  For graph g, n_classes[g] receives the number of distinct
+   classes; the first min(n_classes[g], cap) of them, ascending, go to
    codes[g * cap + i] with their counts in counts[g * cap + i].  totals[g]
    (may be NULL) receives the number of connected 7-sets; kernel_ms (may be
-   NULL) the counting kernel's time.  MK_ERANGE when a graph is too large or
-   has more than cap classes (n_classes is still filled).  Blocks. */
+   NULL) the counting kernel's time.  MK_ERANGE when a graph has more than
+   cap classes (n_classes is still filled).  Blocks. */
 int mk_count7(mk_ctx *ctx, const mk_graph *const *gs, int32_t ng, int64_t cap,
               uint64_t *codes, uint64_t *counts, int64_t *n_classes, uint64_t *totals,
               double *kernel_ms);

@@ -323,7 +323,7 @@ static int batch_create(mk_ctx *ctx, const mk_graph *const *gs, int32_t ng, int 
     const uint64_t region = b->adjacency == MK_ADJ_BITS ? bits : list_ws_words(b->total_n, b->total_m);
     b->total_slots = (uint32_t)slots;
     b->seg_cap = std::max(b->seg_cap, 1);
-    b->lds_bytes = b->k == 7 ? k7_lds_bytes(std::max(b->max_n, 1), b->seg_cap)
+    b->lds_bytes = b->k == 7 ? k7_lds_bytes(std::max(b->max_n, 1), b->seg_cap, b->variant)
                    : b->method == MK_METHOD_CORES
                        ? core_lds_bytes(b->k, std::max(b->max_n, 1), b->seg_cap)
                        : enum_lds_bytes(b->k, std::max(b->max_n, 1), b->seg_cap, b->variant);
@@ -386,7 +386,7 @@ static int batch_create(mk_ctx *ctx, const mk_graph *const *gs, int32_t ng, int 
     for (hipEvent_t &e : b->ev) BAIL_HIP(hipEventCreate(&e));
 
     int per_cu = 0;
-    rc = b->k == 7 ? k7_max_blocks_per_cu(b->lds_bytes, &per_cu)
+    rc = b->k == 7 ? k7_max_blocks_per_cu(b->variant, b->lds_bytes, &per_cu)
          : b->method == MK_METHOD_CORES
              ? core_max_blocks_per_cu(b->k, b->lds_bytes, &per_cu)
              : enum_max_blocks_per_cu(b->k, b->variant, b->lds_bytes, &per_cu);
@@ -398,7 +398,8 @@ static int batch_create(mk_ctx *ctx, const mk_graph *const *gs, int32_t ng, int 
         // one private marks array per workgroup, rounded to 64 entries; all
         // of them together within 1/16 of the device memory
         b->mark_stride = ((size_t)std::max(b->max_n, 1) + 63) & ~(size_t)63;
-        const size_t per_wave = b->mark_stride * 4;  // 32-bit marks in device memory
+        // 32-bit marks in device memory (k = 7: and a tag byte per vertex)
+        const size_t per_wave = b->mark_stride * (b->k == 7 ? 5 : 4);
         const uint64_t budget = (uint64_t)ctx->hbm_bytes / 16;
         const uint64_t fit = std::max<uint64_t>(budget / per_wave, 1);
         b->max_grid = (int)std::min<uint64_t>((uint64_t)b->max_grid, fit);
@@ -809,6 +810,10 @@ static int count7_once(mk_batch *b, int class_log2, int cache_log2, int64_t cap,
     if (e == hipSuccess) e = alloc((void **)&a.overflow, 4);
     if (e == hipSuccess) e = alloc((void **)&d_n, 8 * (size_t)ng);
     if (e == hipSuccess) e = alloc((void **)&d_out, 16 * (size_t)ng * (size_t)cap);
+    if (e == hipSuccess && b->marks == MK_MARKS_GLOBAL) {
+        a.etag_stride = b->mark_stride;
+        e = alloc((void **)&a.etag, a.etag_stride * (size_t)b->grid);
+    }
     if (e != hipSuccess) {
         release();
         return fail(e == hipErrorOutOfMemory ? MK_ENOMEM : MK_EDEVICE, "mk_count7: allocation: %s",
@@ -822,6 +827,7 @@ static int count7_once(mk_batch *b, int class_log2, int cache_log2, int64_t cap,
     if (!rc) rc = fill_u32(a.totals, 0u, 2 * (size_t)ng, st);
     if (!rc) rc = fill_u32(a.overflow, 0u, 1, st);
     if (!rc) rc = fill_u32(d_n, 0u, 2 * (size_t)ng, st);
+    if (!rc && a.etag) rc = fill_u32(a.etag, 0u, a.etag_stride * (size_t)b->grid / 4, st);
     if (!rc) rc = batch_enqueue_prep(b, nullptr, st);
     EnumConfig cfg = enum_config(b);
     cfg.hash_bits = 0;  // the k = 7 kernel keeps its own hash of 64-bit codes
@@ -883,19 +889,21 @@ extern "C" int mk_count7(mk_ctx *ctx, const mk_graph *const *gs, int32_t ng, int
     for (int i = 0; i < ng; ++i) {
         if (!gs[i] || gs[i]->ctx != ctx)
             return fail(MK_EINVAL, "mk_count7: graph %d missing or of another context", i);
-        if (gs[i]->n > MK_LDS_MARKS_MAX_VERTICES)
-            return fail(MK_ERANGE, "mk_count7: graph %d has n=%d > %d", i, gs[i]->n,
-                        MK_LDS_MARKS_MAX_VERTICES);
     }
     if (kernel_ms) *kernel_ms = 0.0;
     if (ng == 0) return MK_OK;
     std::lock_guard<std::recursive_mutex> lock(ctx->mu);
     MK_HIP(hipSetDevice(ctx->device));
+    // marks in LDS with bit-matrix arc tests while they fit, else marks and
+    // extension tags in device memory with arc tests on the lists
+    int max_n = 0;
+    for (int i = 0; i < ng; ++i) max_n = std::max(max_n, gs[i]->n);
+    const bool big = max_n > MK_LDS_MARKS_MAX_VERTICES;
     mk_batch_opts o{};
     o.use_graph = -1;
     o.method = MK_METHOD_ESU;
-    o.adjacency = MK_ADJ_BITS;
-    o.marks = MK_MARKS_LDS;
+    o.adjacency = big ? MK_ADJ_LISTS : MK_ADJ_BITS;
+    o.marks = big ? MK_MARKS_GLOBAL : MK_MARKS_LDS;
     mk_batch *b = nullptr;
     int rc = batch_create(ctx, gs, ng, 7, nullptr, &o, &b);
     if (rc) return rc;

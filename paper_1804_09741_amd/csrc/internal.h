@@ -172,9 +172,11 @@ struct K7Launch {
     int class_log2;                              // log2 of the class slots per graph
     unsigned long long *totals;                  // per graph: subgraphs
     uint32_t *overflow;                          // class inserts that found no slot
+    uint8_t *etag;                               // device-memory marks: tag bytes,
+    size_t etag_stride;                          //   per workgroup, all zero
 };
-int k7_lds_bytes(int max_n, int seg_cap);
-int k7_max_blocks_per_cu(int lds_bytes, int *blocks);
+int k7_lds_bytes(int max_n, int seg_cap, int variant);
+int k7_max_blocks_per_cu(int variant, int lds_bytes, int *blocks);
 int launch_k7(const DevGraph *d_graphs, const int4 *units, uint32_t unit_cap, uint32_t *counters,
               const K7Launch &a, const struct EnumConfig &cfg, int grid, int lds_bytes,
               hipStream_t stream);

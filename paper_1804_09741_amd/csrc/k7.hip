@@ -39,6 +39,8 @@ struct K7Tables {
     uint32_t class_mask;
     unsigned long long *totals;    // per graph: subgraphs counted
     uint32_t *overflow;            // class-table inserts that found no slot
+    uint8_t *etag;                 // marks in device memory: the tags too,
+    size_t etag_stride;            //   etag_stride bytes per workgroup, zero
 };
 
 // per-wave hash of pending (labeled code, count) pairs in LDS
@@ -49,6 +51,7 @@ struct K7Wave {
     uint32_t hpending;
     int graph;
     uint8_t *etag;     // per vertex: 0x80 | lane while it is in a small node's E
+                       // (LDS, or device memory with the marks)
     Code7 *cc1, *cc2;  // per cell of E: code bits at positions 5 and 6
     uint32_t *csz;     //   and its size
 };
@@ -117,7 +120,8 @@ __device__ Code7 canon7_wave(Code7 code)
 
 // Move the wave's pending counts to its graph's class table: canonical code
 // from the cache (or computed and entered), count added; hash emptied.
-__device__ void flush7(EnumState<7> &s, K7Wave &w, const K7Tables &t)
+template <int V>
+__device__ void flush7(EnumState<7, V> &s, K7Wave &w, const K7Tables &t)
 {
     __syncthreads();
     const int lane = lane_id();
@@ -195,7 +199,8 @@ __device__ void flush7(EnumState<7> &s, K7Wave &w, const K7Tables &t)
 
 // add n to the pending count of code for every lane with `mine` set; a full
 // hash is flushed and the inserts that found no slot are tried again
-__device__ void hash7_insert(EnumState<7> &s, K7Wave &w, const K7Tables &t, bool mine, Code7 code,
+template <int V>
+__device__ void hash7_insert(EnumState<7, V> &s, K7Wave &w, const K7Tables &t, bool mine, Code7 code,
                              uint32_t n)
 {
     bool pending = mine;
@@ -222,7 +227,8 @@ __device__ void hash7_insert(EnumState<7> &s, K7Wave &w, const K7Tables &t, bool
 }
 
 // count one code per valid lane (lanes sharing the first lane's code merged)
-__device__ void count7(EnumState<7> &s, K7Wave &w, const K7Tables &t, bool valid, Code7 code)
+template <int V>
+__device__ void count7(EnumState<7, V> &s, K7Wave &w, const K7Tables &t, bool valid, Code7 code)
 {
     const int lane = lane_id();
     const unsigned long long act = __ballot(valid);
@@ -238,7 +244,8 @@ __device__ void count7(EnumState<7> &s, K7Wave &w, const K7Tables &t, bool valid
 }
 
 // count each valid lane's code with weight -1 (merged like count7)
-__device__ void uncount7(EnumState<7> &s, K7Wave &w, const K7Tables &t, bool valid, Code7 code)
+template <int V>
+__device__ void uncount7(EnumState<7, V> &s, K7Wave &w, const K7Tables &t, bool valid, Code7 code)
 {
     const int lane = lane_id();
     const unsigned long long act = __ballot(valid);
@@ -255,8 +262,8 @@ __device__ void uncount7(EnumState<7> &s, K7Wave &w, const K7Tables &t, bool val
 
 // position in seg storage of element a of the extension list made of the
 // tails seg[q][st[q]:], q < NQ
-template <int NQ>
-__device__ __forceinline__ int ext_addr7(const EnumState<7> &s, const int (&st)[6],
+template <int NQ, int V>
+__device__ __forceinline__ int ext_addr7(const EnumState<7, V> &s, const int (&st)[6],
                                          const int (&rem)[NQ], int a)
 {
     int addr = 0;
@@ -297,7 +304,8 @@ __device__ __forceinline__ Code7 from_lane64(Code7 v, int l)
 // adds one to its own code and takes one from its cell pair's.  Lane l holds
 // E[l], its code bits for positions 5 and 6 and its list row; a child of
 // degree >= kRowMin is scanned alone.
-__device__ void last_two7_cells(EnumState<7> &s, K7Wave &w7, const K7Tables &t, const int (&st)[6],
+template <int V>
+__device__ void last_two7_cells(EnumState<7, V> &s, K7Wave &w7, const K7Tables &t, const int (&st)[6],
                                 const int (&rem)[5], int e, Code7 code, int jlo)
 {
     constexpr int B_WU = bit7(5, 6), B_UW = bit7(6, 5);
@@ -462,7 +470,8 @@ __device__ void last_two7_cells(EnumState<7> &s, K7Wave &w7, const K7Tables &t, 
 // E: child w = E[i] (i in [jlo, jhi)) closes X + {w, u} for (A) u = E[j],
 // j > i (arc w - u from the bit matrices) and (B) u an exclusive neighbour
 // of w (its list entry gives the arc).  Same split as the k <= 6 kernel.
-__device__ void last_two7(EnumState<7> &s, K7Wave &w7, const K7Tables &t, const int (&st)[6],
+template <int V>
+__device__ void last_two7(EnumState<7, V> &s, K7Wave &w7, const K7Tables &t, const int (&st)[6],
                           Code7 code, int jlo, int jhi)
 {
     constexpr int NQ = 5;
@@ -505,9 +514,14 @@ __device__ void last_two7(EnumState<7> &s, K7Wave &w7, const K7Tables &t, const 
             if (i < j && j < e) {
                 const uint32_t w = s.seg[ext_addr7<NQ>(s, st, rem, i)];
                 const uint32_t u = s.seg[ext_addr7<NQ>(s, st, rem, j)];
-                const size_t word = (size_t)w * s.words + (u >> 5);
-                const uint32_t sh = u & 31u;
-                const uint32_t tt = ((s.bits_out[word] >> sh) & 1u) | (((s.bits_in[word] >> sh) & 1u) << 1);
+                uint32_t tt;
+                if constexpr ((V & kVarSearch) != 0) {
+                    tt = list_relation(s.urow, s.uadj, w, u);
+                } else {
+                    const size_t word = (size_t)w * s.words + (u >> 5);
+                    const uint32_t sh = u & 31u;
+                    tt = ((s.bits_out[word] >> sh) & 1u) | (((s.bits_in[word] >> sh) & 1u) << 1);
+                }
                 c = code | code_bits7(s.mark[w], 5) | code_bits7(s.mark[u], 6) |
                     ((Code7)(tt & 1u) << B_WU) | ((Code7)(tt >> 1) << B_UW);
                 ok = true;
@@ -570,8 +584,8 @@ __device__ void last_two7(EnumState<7> &s, K7Wave &w7, const K7Tables &t, const 
 }
 
 // node with members s_0..s_D: children jlo..jhi-1 of its extension list
-template <int D>
-__device__ void visit7(EnumState<7> &s, K7Wave &w7, const K7Tables &t, const int (&st)[6],
+template <int D, int V>
+__device__ void visit7(EnumState<7, V> &s, K7Wave &w7, const K7Tables &t, const int (&st)[6],
                        Code7 code, int jlo, int jhi)
 {
     if constexpr (D == 4) {
@@ -614,7 +628,8 @@ __device__ void visit7(EnumState<7> &s, K7Wave &w7, const K7Tables &t, const int
     }
 }
 
-__device__ void run_unit7(EnumState<7> &s, K7Wave &w7, const K7Tables &t, int v, int i,
+template <int V>
+__device__ void run_unit7(EnumState<7, V> &s, K7Wave &w7, const K7Tables &t, int v, int i,
                           uint32_t range)
 {
     s.root = v;
@@ -640,38 +655,49 @@ __device__ void run_unit7(EnumState<7> &s, K7Wave &w7, const K7Tables &t, int v,
 // this kernel's part of a wave's LDS, after the shared layout: the hash
 // (u64 keys, u32 counts), the cell table (2 x u64 + u32 per cell), the
 // extension tags (a byte per vertex)
-static __host__ __device__ int k7_hash_offset(int max_n, int seg_cap)
+static __host__ __device__ int k7_hash_offset(int max_n, int seg_cap, bool global)
 {
-    return (lds_layout(7, max_n, seg_cap, 0).total + 7) & ~7;
+    return (lds_layout(7, max_n, seg_cap, 0, global).total + 7) & ~7;
 }
 
-static __host__ __device__ int k7_cells_offset(int max_n, int seg_cap)
+static __host__ __device__ int k7_cells_offset(int max_n, int seg_cap, bool global)
 {
-    return k7_hash_offset(max_n, seg_cap) + kHash7Slots * (int)(sizeof(Code7) + sizeof(uint32_t));
+    return k7_hash_offset(max_n, seg_cap, global) +
+           kHash7Slots * (int)(sizeof(Code7) + sizeof(uint32_t));
 }
 
-static __host__ __device__ int k7_tags_offset(int max_n, int seg_cap)
+static __host__ __device__ int k7_tags_offset(int max_n, int seg_cap, bool global)
 {
-    return k7_cells_offset(max_n, seg_cap) + kWave * (int)(2 * sizeof(Code7) + sizeof(uint32_t));
+    return k7_cells_offset(max_n, seg_cap, global) +
+           kWave * (int)(2 * sizeof(Code7) + sizeof(uint32_t));
 }
 
+// V = 0: LDS marks and tags, bit-matrix arc tests; V = kVarSearch |
+// kVarGlobal: marks and tags in device memory, arc tests on the lists
+template <int V>
 __global__ __launch_bounds__(kWave) void k7_kernel(const DevGraph *graphs, const int4 *units,
                                                    uint32_t unit_cap, uint32_t unit_end,
                                                    uint32_t *counters, K7Tables t, EnumConfig cfg)
 {
+    constexpr bool kGlobal = (V & kVarGlobal) != 0;
     extern __shared__ uint32_t lds[];
     char *base = reinterpret_cast<char *>(lds);
-    EnumState<7> s;
-    const LdsLayout lay = lds_layout(7, cfg.max_n, cfg.seg_cap, 0);
+    EnumState<7, V> s;
+    const LdsLayout lay = lds_layout(7, cfg.max_n, cfg.seg_cap, 0, kGlobal);
     init_state(s, base, lay, cfg, counters, nullptr, 0u);
     K7Wave w7;
-    w7.hkey = reinterpret_cast<Code7 *>(base + k7_hash_offset(cfg.max_n, cfg.seg_cap));
+    w7.hkey = reinterpret_cast<Code7 *>(base + k7_hash_offset(cfg.max_n, cfg.seg_cap, kGlobal));
     w7.hcnt = reinterpret_cast<uint32_t *>(w7.hkey + kHash7Slots);
-    w7.cc1 = reinterpret_cast<Code7 *>(base + k7_cells_offset(cfg.max_n, cfg.seg_cap));
+    w7.cc1 = reinterpret_cast<Code7 *>(base + k7_cells_offset(cfg.max_n, cfg.seg_cap, kGlobal));
     w7.cc2 = w7.cc1 + kWave;
     w7.csz = reinterpret_cast<uint32_t *>(w7.cc2 + kWave);
-    w7.etag = reinterpret_cast<uint8_t *>(base + k7_tags_offset(cfg.max_n, cfg.seg_cap));
-    for (int i = lane_id(); i < cfg.max_n; i += kWave) w7.etag[i] = 0;
+    if constexpr (kGlobal) {
+        // zeroed when allocated; every small node clears the tags it set
+        w7.etag = t.etag + (size_t)blockIdx.x * t.etag_stride;
+    } else {
+        w7.etag = reinterpret_cast<uint8_t *>(base + k7_tags_offset(cfg.max_n, cfg.seg_cap, false));
+        for (int i = lane_id(); i < cfg.max_n; i += kWave) w7.etag[i] = 0;
+    }
     w7.hused = 0;
     w7.hpending = 0;
     w7.graph = 0;
@@ -713,15 +739,27 @@ __global__ void k7_collect_kernel(const Code7 *class_key, const unsigned long lo
     }
 }
 
-int k7_lds_bytes(int max_n, int seg_cap)
+int k7_lds_bytes(int max_n, int seg_cap, int variant)
 {
-    return k7_tags_offset(max_n, seg_cap) + ((max_n + 3) & ~3);
+    const bool global = (variant & kVarGlobal) != 0;
+    return k7_tags_offset(max_n, seg_cap, global) + (global ? 0 : ((max_n + 3) & ~3));
 }
 
-int k7_max_blocks_per_cu(int lds_bytes, int *blocks)
+static const void *k7_fn(int variant)
 {
-    MK_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(
-        blocks, reinterpret_cast<const void *>(&k7_kernel), kWave, (size_t)lds_bytes));
+    switch (variant) {
+    case 0: return reinterpret_cast<const void *>(&k7_kernel<0>);
+    case kVarSearch | kVarGlobal:
+        return reinterpret_cast<const void *>(&k7_kernel<kVarSearch | kVarGlobal>);
+    default: return nullptr;
+    }
+}
+
+int k7_max_blocks_per_cu(int variant, int lds_bytes, int *blocks)
+{
+    const void *fn = k7_fn(variant);
+    if (!fn) return fail(MK_ERANGE, "no k = 7 kernel for variant %d", variant);
+    MK_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, fn, kWave, (size_t)lds_bytes));
     return MK_OK;
 }
 
@@ -740,9 +778,17 @@ int launch_k7(const DevGraph *d_graphs, const int4 *units, uint32_t unit_cap, ui
     t.class_mask = (1u << a.class_log2) - 1u;
     t.totals = a.totals;
     t.overflow = a.overflow;
-    hipLaunchKernelGGL(k7_kernel, dim3(grid), dim3(kWave), lds_bytes, stream, d_graphs, units,
-                       unit_cap, kAllUnits, counters, t, cfg);
-    MK_HIP(hipGetLastError());
+    t.etag = a.etag;
+    t.etag_stride = a.etag_stride;
+    const void *fn = k7_fn(cfg.variant);
+    if (!fn) return fail(MK_ERANGE, "no k = 7 kernel for variant %d", cfg.variant);
+    if ((cfg.variant & kVarGlobal) != 0 && (!cfg.marks || !a.etag))
+        return fail(MK_EINVAL, "launch_k7: device-memory variant without marks or tags");
+    const uint32_t end = kAllUnits;
+    EnumConfig c = cfg;
+    void *args[] = {(void *)&d_graphs, (void *)&units, (void *)&unit_cap, (void *)&end,
+                    (void *)&counters, (void *)&t, (void *)&c};
+    MK_HIP(hipLaunchKernel(fn, dim3(grid), dim3(kWave), args, (size_t)lds_bytes, stream));
     return MK_OK;
 }
 
