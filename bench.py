@@ -247,6 +247,22 @@ def _k7(ctx, M, I, torch):
            "classes_mean": float(np.mean(classes)), "classes_max": int(max(classes))}
     _log("k=7 on the k=6 batch: %d subgraphs, kernel %.1f ms (%.3g/s), call %.1f ms, "
          "%.0f classes per graph" % (sub, kern, res["value"], res["call_ms"], res["classes_mean"]))
+    # one graph past the LDS limit (marks and tags in device memory)
+    wl = I.workload_k6_large(1 << 17)
+    g = ctx.load_graph(*wl.graphs[0])
+    try:
+        ctx.count7([g])
+        t0 = time.perf_counter()
+        out, totals, kern = ctx.count7([g])
+        wall = time.perf_counter() - t0
+    finally:
+        g.free()
+    sub = int(totals[0])
+    res["large"] = {"workload": wl.name.replace("k6_", "k7_"), "subgraphs": sub, "kernel_ms": kern,
+                    "call_ms": wall * 1e3, "value": sub / (kern / 1e3),
+                    "unit": "subgraphs/s (kernel)", "classes": len(out[0][0])}
+    _log("k=7 on %s: %d subgraphs, kernel %.1f ms (%.3g/s), %d classes" % (
+        res["large"]["workload"], sub, kern, res["large"]["value"], res["large"]["classes"]))
     return res
 
 

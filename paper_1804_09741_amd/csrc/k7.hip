@@ -4,9 +4,12 @@
 // the rule the k <= 6 tables are built by), and H_7 of a graph is a set of
 // (canonical code, count) pairs.
 //
-// The walk is the enumeration kernel's (ESU with per-wave LDS marks, the
-// last two levels flat: pairs inside the extension list by bit-matrix test,
-// exclusive neighbours by list scan), with 42-bit codes.  Codes go into a
+// The walk is the enumeration kernel's (ESU with per-wave marks, the last
+// two levels flat: pairs inside a small extension list per pair of cells,
+// other pairs by arc test, exclusive neighbours by list scan), with 42-bit
+// codes; as there, graphs past the LDS limit keep their marks in device
+// memory and test arcs on the sorted lists (k7_kernel<kVarSearch |
+// kVarGlobal>).  Codes go into a
 // per-wave LDS hash of pending counts; at its flush each distinct labeled
 // code gets its canonical code from a device-wide cache (labeled ->
 // canonical, open addressing); a code not in the cache is canonicalised by

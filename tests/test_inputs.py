@@ -65,3 +65,21 @@ def test_serving_stream_small():
         I.check_simple(*r.graph)
         n = len(r.graph[0]) - 1
         assert 100 <= n <= 600
+
+
+def test_sparse_powerlaw_large_graph():
+    """The vectorised recipe of the large graphs: simple, out-degrees in
+    [0, 60] (repeated targets dropped), m about n times the mean out-degree
+    of P(d) ~ d^-2.5 on [1, 60], reproducible."""
+    n = 1 << 16
+    g = I.sparse_powerlaw_digraph(n, 2.5, 60, np.random.default_rng(5))
+    I.check_simple(*g)
+    out = np.diff(g[0])
+    assert out.max() <= 60 and out.min() >= 0
+    d = np.arange(1, 61, dtype=np.float64)
+    mean = float((d * d ** -2.5).sum() / (d ** -2.5).sum())
+    assert abs(len(g[1]) / n - mean) < 0.05 * mean
+    g2 = I.sparse_powerlaw_digraph(n, 2.5, 60, np.random.default_rng(5))
+    assert np.array_equal(g[0], g2[0]) and np.array_equal(g[1], g2[1])
+    w = I.workload_k6_large(1 << 14)
+    assert w.k == 6 and len(w.graphs) == 1 and len(w.graphs[0][0]) == (1 << 14) + 1
