@@ -28,13 +28,33 @@ __global__ void fill_kernel(uint32_t *dst, uint32_t value, size_t n)
     for (; i < n; i += stride) dst[i] = value;
 }
 
+// 16-byte stores for a 16-byte aligned dst; the last n % 4 words by the
+// first threads
+__global__ void fill4_kernel(uint32_t *dst, uint32_t value, size_t n)
+{
+    const size_t n4 = n >> 2;
+    uint4 *d4 = reinterpret_cast<uint4 *>(dst);
+    const uint4 v = make_uint4(value, value, value, value);
+    const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t i = t; i < n4; i += stride) d4[i] = v;
+    if (t < (n & 3)) dst[(n4 << 2) + t] = value;
+}
+
 int fill_u32(void *dst, uint32_t value, size_t n, hipStream_t stream)
 {
     if (n == 0) return MK_OK;
-    size_t blocks = (n + 255) / 256;
-    if (blocks > 16384) blocks = 16384;
-    hipLaunchKernelGGL(fill_kernel, dim3((unsigned)blocks), dim3(256), 0, stream,
-                       (uint32_t *)dst, value, n);
+    if (((uintptr_t)dst & 15) == 0 && n >= 4096) {
+        size_t blocks = (n / 4 + 255) / 256;
+        if (blocks > 8192) blocks = 8192;
+        hipLaunchKernelGGL(fill4_kernel, dim3((unsigned)blocks), dim3(256), 0, stream,
+                           (uint32_t *)dst, value, n);
+    } else {
+        size_t blocks = (n + 255) / 256;
+        if (blocks > 16384) blocks = 16384;
+        hipLaunchKernelGGL(fill_kernel, dim3((unsigned)blocks), dim3(256), 0, stream,
+                           (uint32_t *)dst, value, n);
+    }
     MK_HIP(hipGetLastError());
     return MK_OK;
 }
