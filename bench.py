@@ -129,6 +129,42 @@ def _timed_batch(ctx, M, graphs, table, steps, warmup, torch, **opts):
         b.free()
 
 
+def _oracle_total(args):
+    """Worker of the parallel CPU baseline: the oracle's count of one graph."""
+    rp, col, k = args
+    from oracle import oracle as O
+    h = O.count(rp, col, k)
+    return sum(h.values())
+
+
+def _oracle_ready(_):
+    """Worker warm-up: load the oracle library."""
+    import numpy as np
+    from oracle import oracle as O
+    O.count(np.zeros(4, np.int32), np.zeros(0, np.int32), 3)
+    return os.getpid()
+
+
+def _cpu_parallel(graphs, k, procs):
+    """The oracle over every graph of the workload, one graph per task, in
+    `procs` worker processes, timed from the first task to the last result
+    after the workers are up.  Called before this process touches the GPU,
+    so the workers start from a process without device state."""
+    import multiprocessing
+    from concurrent.futures import ProcessPoolExecutor
+    with ProcessPoolExecutor(max_workers=procs,
+                             mp_context=multiprocessing.get_context("spawn")) as pool:
+        list(pool.map(_oracle_ready, range(procs)))
+        t0 = time.perf_counter()
+        totals = list(pool.map(_oracle_total, [(rp, col, k) for rp, col in graphs]))
+        wall = time.perf_counter() - t0
+    counted = int(sum(totals))
+    return {"value": counted / wall, "unit": "subgraphs/s", "cores": procs, "kind": "oracle",
+            "sample": "all %d graphs of the batch (%d subgraphs), %d processes, %.1f s" % (
+                len(graphs), counted, procs, wall),
+            "totals": [int(x) for x in totals]}
+
+
 def _plain(ctx, graphs, table, steps, torch, **opts):
     """One prepared single-graph batch per graph, run one after another."""
     bs = [ctx.batch([g], table, **opts) for g in graphs]
@@ -383,9 +419,18 @@ def main():
               "use --gpus 1", file=sys.stderr)
         sys.exit(2)
     import numpy as np
-    import torch  # device buffers and the launch stream only
 
     from paper_1804_09741_amd import inputs as I
+
+    # the oracle on all host cores, before this process touches the GPU
+    cpu_par = None
+    if not args.no_cpu_baseline:
+        procs = max(1, min(16, os.cpu_count() or 1, 31))
+        cpu_par = _cpu_parallel(I.workload_k6_batch().graphs, 6, procs)
+        _log("cpu oracle, %d processes: %s" % (procs, cpu_par["sample"]))
+
+    import torch  # device buffers and the launch stream only
+
     from paper_1804_09741_amd import motifs as M
 
     ctx = M.Context(0)
@@ -472,6 +517,9 @@ def main():
                                "sample": "graphs 0..%d of the batch (%d subgraphs), single "
                                          "thread, %.1f s" % (ns - 1, counted, cpu_s),
                                "matches_gpu": bool(ok)}
+        totals = cpu_par.pop("totals")
+        cpu_par["totals_match_gpu"] = totals == [int(x) for x in r["totals"]]
+        out["cpu_baseline_parallel"] = cpu_par
     for g in graphs:
         g.free()
 
