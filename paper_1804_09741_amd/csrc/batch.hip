@@ -886,6 +886,9 @@ extern "C" int mk_count7(mk_ctx *ctx, const mk_graph *const *gs, int32_t ng, int
     if (!ctx || (ng > 0 && (!gs || !n_classes)) || (cap > 0 && ng > 0 && (!codes || !counts)))
         return fail(MK_EINVAL, "mk_count7: NULL argument");
     if (ng < 0 || cap < 0) return fail(MK_EINVAL, "mk_count7: negative ng or cap");
+    // the output lists (code and count, 16 bytes a class) must stay addressable
+    if (ng > 0 && (uint64_t)cap > (UINT64_MAX / 64) / (uint64_t)ng)
+        return fail(MK_ERANGE, "mk_count7: cap=%lld too large for %d graphs", (long long)cap, ng);
     for (int i = 0; i < ng; ++i) {
         if (!gs[i] || gs[i]->ctx != ctx)
             return fail(MK_EINVAL, "mk_count7: graph %d missing or of another context", i);

@@ -2,6 +2,7 @@
 oracle's k = 7 histograms bit for bit, closed forms, the growth of the
 device class tables, and the argument errors."""
 
+import ctypes
 import math
 
 import numpy as np
@@ -115,6 +116,13 @@ def test_errors(ctx):
             many.free()
         out, totals, _ = ctx.count7([g], cap=1)
         assert out[0][0].tolist() == [(1 << 42) - 1] and int(totals[0]) == 36
+        # a cap whose output lists would not be addressable is refused before use
+        dummy = np.zeros(1, dtype=np.uint64)
+        ncls = np.zeros(1, dtype=np.int64)
+        handles = (ctypes.c_void_p * 1)(g.handle)
+        rc = M.library().mk_count7(ctx.handle, handles, 1, 1 << 60, dummy.ctypes.data,
+                                   dummy.ctypes.data, ncls.ctypes.data, None, None)
+        assert rc == M.MK_ERANGE
         # cap 0: counts only; a graph without 7-sets fits, one with classes not
         tiny = ctx.load_graph(*I.directed_path(5))
         try:
