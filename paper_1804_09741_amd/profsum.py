@@ -3,6 +3,8 @@
     python -m paper_1804_09741_amd.profsum stats DIR --out FILE.md --command CMD
     python -m paper_1804_09741_amd.profsum counters DIR [DIR ...] --copy-mib MIB
         --bench-log LOG --out-md FILE.md --out-json FILE.json --command CMD [CMD ...]
+    python -m paper_1804_09741_amd.profsum pmc DIR [DIR ...] --kernels REGEX
+        --out FILE.md --command CMD [CMD ...] [--per NAME=COUNT ...]
 
 `stats` turns `run_kernel_stats.csv` of a `--kernel-trace --stats` run into a
 Markdown table.  `counters` averages every counter of every pass (one
@@ -10,6 +12,10 @@ Markdown table.  `counters` averages every counter of every pass (one
 
 * a Markdown table of all counters of the enumeration kernels and of the
   calibration copy;
+`pmc` averages every counter of the kernels whose names match REGEX, per
+dispatch, over one or more `--pmc` runs, optionally also per unit of work
+(`--per "k7_kernel<0>=2058308995"`: subgraphs of one dispatch).
+
 * the HBM traffic record that bench.py reports: FETCH_SIZE and WRITE_SIZE
   (KiB per dispatch) of each enumeration kernel, each scaled by what the
   same counter reads for the device-to-device copy of `--copy-mib` MiB
@@ -101,6 +107,26 @@ def counter_means(dirs, copy_bytes):
     return means, counts
 
 
+def kernel_counter_means(dirs, pattern):
+    """{kernel: {counter: mean per dispatch}}, {kernel: dispatches} for the
+    kernels whose short names match `pattern`."""
+    acc = defaultdict(lambda: defaultdict(list))
+    rx = re.compile(pattern)
+    for d in dirs:
+        per = defaultdict(float)
+        names = {}
+        for r in _csv(os.path.join(d, "run_counter_collection.csv")):
+            key = (int(r["Dispatch_Id"]), r["Counter_Name"])
+            per[key] += float(r["Counter_Value"])
+            names[int(r["Dispatch_Id"])] = short_name(r["Kernel_Name"])
+        for (disp, cname), v in per.items():
+            if rx.search(names[disp]):
+                acc[names[disp]][cname].append(v)
+    means = {k: {c: sum(v) / len(v) for c, v in cs.items()} for k, cs in acc.items()}
+    counts = {k: max(len(v) for v in cs.values()) for k, cs in acc.items()}
+    return means, counts
+
+
 def _bench_record(path):
     with open(path) as f:
         lines = [ln for ln in f.read().splitlines() if ln.startswith("{")]
@@ -124,7 +150,50 @@ def main(argv=None):
     c.add_argument("--out-json", required=True)
     c.add_argument("--title", default="enum_kernel hardware counters")
     c.add_argument("--command", nargs="+", required=True)
+    q = sub.add_parser("pmc")
+    q.add_argument("dirs", nargs="+")
+    q.add_argument("--kernels", required=True)
+    q.add_argument("--out", required=True)
+    q.add_argument("--title", default="hardware counters")
+    q.add_argument("--command", nargs="+", required=True)
+    q.add_argument("--per", nargs="*", default=[], metavar="KERNEL=UNITS")
+    q.add_argument("--note", default="")
     a = ap.parse_args(argv)
+
+    if a.cmd == "pmc":
+        means, counts = kernel_counter_means(a.dirs, a.kernels)
+        per = {}
+        for item in a.per:
+            name, units = item.rsplit("=", 1)
+            per[name] = float(units)
+        kerns = sorted(means)
+        lines = ["# " + a.title, "",
+                 "One rocprofv3 `--pmc` run per counter set, from /tmp with TMPDIR=/tmp; "
+                 "$R is the repository root:", "", "```"] + a.command + ["```", "",
+                 "Mean per dispatch over " + ", ".join(
+                     "%s: %d dispatches" % (k, counts[k]) for k in kerns) + ".", ""]
+        heads = []
+        for k in kerns:
+            heads.append(k)
+            if k in per:
+                heads.append("%s per unit" % k)
+        lines += ["| counter | " + " | ".join(heads) + " |", "|---|" + "---:|" * len(heads)]
+        for cname in sorted({c for k in kerns for c in means[k]}):
+            cells = []
+            for k in kerns:
+                v = means[k].get(cname, float("nan"))
+                cells.append("%.4g" % v)
+                if k in per:
+                    cells.append("%.4g" % (v / per[k]))
+            lines.append("| %s | " % cname + " | ".join(cells) + " |")
+        if per:
+            lines += ["", "Units per dispatch: " + ", ".join(
+                "%s %.6g" % (k, v) for k, v in sorted(per.items())) + "."]
+        if a.note:
+            lines += ["", a.note]
+        with open(a.out, "w") as f:
+            f.write("\n".join(lines) + "\n")
+        return
 
     if a.cmd == "stats":
         lines = ["# " + a.title, "",

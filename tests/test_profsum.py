@@ -57,3 +57,19 @@ def test_short_names():
         == "core_kernel<5>"
     assert P.short_name("mk::fill_kernel(unsigned int*, unsigned int, unsigned long)") == "fill_kernel"
     assert P.short_name("__amd_rocclr_copyBuffer") == "__amd_rocclr_copyBuffer"
+
+
+def test_pmc_means_per_dispatch_and_unit(tmp_path):
+    k7 = "void mk::k7_kernel<0>(mk::DevGraph const*, int)"
+    other = "mk::fill_kernel(unsigned int*, unsigned int, unsigned long)"
+    _pass(tmp_path / "p1", "SQ_INSTS_VALU", [(1, k7, 300.0), (1, k7, 100.0), (2, k7, 800.0),
+                                             (3, other, 5.0)])
+    _pass(tmp_path / "p2", "SQ_WAVES", [(1, k7, 64.0), (2, k7, 64.0), (3, other, 1.0)])
+    out = tmp_path / "pmc.md"
+    P.main(["pmc", str(tmp_path / "p1"), str(tmp_path / "p2"), "--kernels", "k7_kernel",
+            "--out", str(out), "--command", "cmd", "--per", "k7_kernel<0>=200"])
+    text = out.read_text()
+    assert "k7_kernel<0>: 2 dispatches" in text and "fill_kernel" not in text
+    # VALU: (400 + 800) / 2 = 600 per dispatch, 3 per unit of 200
+    assert "| SQ_INSTS_VALU | 600 | 3 |" in text
+    assert "| SQ_WAVES | 64 | 0.32 |" in text
