@@ -280,11 +280,13 @@ typedef struct mk_batch_opts {
 #define MK_ADJ_LISTS 2
 
 /* Per-vertex marks of each wave (every vertex's relation to the current
-   members; 2 bytes per vertex for k <= 5, 4 for k = 6).
-   MK_MARKS_LDS: in LDS; needs n <= MK_LDS_MARKS_MAX_VERTICES.
-   MK_MARKS_GLOBAL: a private n-entry array per wave in device memory (kept
-     zero between work units; fewer waves when they would take more than
-     1/16 of the device memory); needs MK_ADJ_LISTS and MK_METHOD_ESU.
+   members).
+   MK_MARKS_LDS: in LDS, 2 bytes per vertex for k <= 5 and 4 for k = 6;
+     needs n <= MK_LDS_MARKS_MAX_VERTICES.
+   MK_MARKS_GLOBAL: a private n-entry array per wave in device memory, 4
+     bytes per vertex (kept zero between work units; fewer waves when they
+     would take more than 1/16 of the device memory); needs MK_ADJ_LISTS and
+     MK_METHOD_ESU.
    MK_MARKS_AUTO: MK_MARKS_LDS when the graphs fit, else MK_MARKS_GLOBAL. */
 #define MK_MARKS_AUTO 0
 #define MK_MARKS_LDS 1
