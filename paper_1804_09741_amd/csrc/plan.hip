@@ -244,8 +244,9 @@ static int plan_k(const DevGraph *d_graphs, int ng, int64_t max_nnz, uint32_t to
                                    ? (max_nnz + kPlanThreads - 1) / kPlanThreads
                                    : 1),
                     (unsigned)ng);
-    int rc = fill_u32(counters + kEstTotal, 0, 2, stream);
-    if (rc != MK_OK) return rc;
+    // the estimate total (counters[kEstTotal]) starts at zero: the callers
+    // clear all counters before every plan
+    int rc = MK_OK;
     hipLaunchKernelGGL((plan_kernel<K, kEstimate>), grid, dim3(kPlanThreads), 0, stream, d_graphs,
                        slot_cnt, slot_off, slot_est, slot_vi, units, unit_cap, threshold, waves,
                        counters);
