@@ -71,15 +71,23 @@ __device__ __forceinline__ bool adjacent(const DevGraph &g, int v, int x)
 enum PlanPass : int { kEstimate = 0, kCount = 1, kEmit = 2 };
 
 // Split threshold of the count and emit passes: the floor, raised so that
-// the estimated total work makes about kUnitsPerWave units per enumeration
-// wave (large batches need little splitting, single graphs need more).
-constexpr uint64_t kUnitsPerWave = 16;
+// the estimated total work makes about kUnitsPerWave<K> units per
+// enumeration wave (large batches need little splitting, single graphs need
+// more).  The estimates are rough (a subtree's size is known only within a
+// factor of a few), so finer units even out the waves' loads: on MI355X, 64
+// instead of 16 takes 10% off a single graph of 2^20 vertices at k = 6 and
+// 1% off a batch of 101 graphs at k = 5; more than 64 gains little.  A k = 7
+// unit re-pushes its first members' marks into device memory on large
+// graphs, and 64 costs it 4% there, so k = 7 keeps 16.
+template <int K>
+constexpr uint64_t kUnitsPerWave = K == 7 ? 16 : 64;
 
+template <int K>
 __device__ __forceinline__ uint64_t effective_threshold(const uint32_t *counters, uint64_t floor_t,
                                                         uint32_t waves)
 {
     const uint64_t total = *reinterpret_cast<const unsigned long long *>(counters + kEstTotal);
-    const uint64_t adaptive = total / ((uint64_t)waves * kUnitsPerWave + 1);
+    const uint64_t adaptive = total / ((uint64_t)waves * kUnitsPerWave<K> + 1);
     return adaptive > floor_t ? adaptive : floor_t;
 }
 
@@ -151,7 +159,7 @@ __global__ __launch_bounds__(kPlanThreads) void plan_kernel(const DevGraph *grap
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
     uint64_t est = 0;  // kEstimate: this slot's estimated cost
     const bool live = g.n > 0 && e < min(g.urow[g.n], (int)g.nnz_cap);
-    const uint64_t threshold = PASS == kEstimate ? ~0ull : effective_threshold(counters, floor_t, waves);
+    const uint64_t threshold = PASS == kEstimate ? ~0ull : effective_threshold<K>(counters, floor_t, waves);
     if (live) {
         const uint32_t slot = g.slot_base + (uint32_t)e;
         const int y = (int)(g.uadj[e] >> 2);
