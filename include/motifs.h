@@ -227,7 +227,8 @@ int mk_count_batch(mk_ctx *ctx, const mk_graph *const *gs, int32_t ng,
 typedef struct mk_batch_opts {
     uint64_t split_threshold; /* floor of the estimated subgraphs per work
                                  unit (the planner raises it so that the
-                                 whole batch makes ~64 units per wave) */
+                                 whole batch makes ~16 units per wave, ~64
+                                 on sorted-list adjacency below k = 7) */
     int32_t waves_per_cu;     /* resident enumeration waves per compute unit */
     int32_t use_graph;        /* 1: replay a captured hipGraph (default),
                                  -1: plain stream launches */

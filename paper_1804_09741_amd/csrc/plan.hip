@@ -71,23 +71,29 @@ __device__ __forceinline__ bool adjacent(const DevGraph &g, int v, int x)
 enum PlanPass : int { kEstimate = 0, kCount = 1, kEmit = 2 };
 
 // Split threshold of the count and emit passes: the floor, raised so that
-// the estimated total work makes about kUnitsPerWave<K> units per
+// the estimated total work makes about units_per_wave<K>(g) units per
 // enumeration wave (large batches need little splitting, single graphs need
-// more).  The estimates are rough (a subtree's size is known only within a
-// factor of a few), so finer units even out the waves' loads: on MI355X, 64
-// instead of 16 takes 10% off a single graph of 2^20 vertices at k = 6 and
-// 1% off a batch of 101 graphs at k = 5; more than 64 gains little.  A k = 7
-// unit re-pushes its first members' marks into device memory on large
-// graphs, and 64 costs it 4% there, so k = 7 keeps 16.
+// more).  Graphs counted on sorted lists are those past the bit-matrix limit
+// -- typically one large graph whose hubs make the few largest units the
+// tail of the launch -- and finer units even those out: 64 per wave instead
+// of 16 takes 10% off a power-law graph of 2^20 vertices at k = 6 on MI355X.
+// On bit-matrix graphs finer units do not pay (a mix of single graphs of
+// 100-5,000 vertices at k = 6 takes 7% longer with 64), and a k = 7 unit on
+// a large graph re-pushes its first members' marks into device memory (64
+// costs 4% there), so both keep 16.
 template <int K>
-constexpr uint64_t kUnitsPerWave = K == 7 ? 16 : 64;
+__device__ __forceinline__ uint64_t units_per_wave(const DevGraph &g)
+{
+    return K < 7 && !g.bits_out ? 64u : 16u;
+}
 
 template <int K>
-__device__ __forceinline__ uint64_t effective_threshold(const uint32_t *counters, uint64_t floor_t,
+__device__ __forceinline__ uint64_t effective_threshold(const DevGraph &g,
+                                                        const uint32_t *counters, uint64_t floor_t,
                                                         uint32_t waves)
 {
     const uint64_t total = *reinterpret_cast<const unsigned long long *>(counters + kEstTotal);
-    const uint64_t adaptive = total / ((uint64_t)waves * kUnitsPerWave<K> + 1);
+    const uint64_t adaptive = total / ((uint64_t)waves * units_per_wave<K>(g) + 1);
     return adaptive > floor_t ? adaptive : floor_t;
 }
 
@@ -159,7 +165,7 @@ __global__ __launch_bounds__(kPlanThreads) void plan_kernel(const DevGraph *grap
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
     uint64_t est = 0;  // kEstimate: this slot's estimated cost
     const bool live = g.n > 0 && e < min(g.urow[g.n], (int)g.nnz_cap);
-    const uint64_t threshold = PASS == kEstimate ? ~0ull : effective_threshold<K>(counters, floor_t, waves);
+    const uint64_t threshold = PASS == kEstimate ? ~0ull : effective_threshold<K>(g, counters, floor_t, waves);
     if (live) {
         const uint32_t slot = g.slot_base + (uint32_t)e;
         const int y = (int)(g.uadj[e] >> 2);
