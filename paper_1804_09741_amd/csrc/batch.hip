@@ -839,7 +839,7 @@ static int count7_once(mk_batch *b, int class_log2, int cache_log2, int64_t cap,
                             b->lds_bytes, st);
     if (!rc && hipEventRecord(b->ev[2], st) != hipSuccess) rc = fail(MK_EDEVICE, "event record");
     if (!rc) rc = launch_k7_collect(a, ng, cap, d_codes, d_counts, d_n, st);
-    std::vector<unsigned long long> hn(ng), ht(ng), hc((size_t)ng * cap), hv((size_t)ng * cap);
+    std::vector<unsigned long long> hn(ng), ht(ng);
     uint32_t cnt[kNumCounters], ovf = 0;
     auto copy = [&](void *dst, const void *src, size_t bytes) {
         if (!rc && bytes) {
@@ -847,13 +847,22 @@ static int count7_once(mk_batch *b, int class_log2, int cache_log2, int64_t cap,
             if (ce != hipSuccess) rc = fail(MK_EDEVICE, "mk_count7: copy: %s", hipGetErrorString(ce));
         }
     };
+    // the class counts first, then only each graph's own classes, straight
+    // into the caller's lists
     copy(hn.data(), d_n, 8 * (size_t)ng);
     copy(ht.data(), a.totals, 8 * (size_t)ng);
-    copy(hc.data(), d_codes, 8 * (size_t)ng * cap);
-    copy(hv.data(), d_counts, 8 * (size_t)ng * cap);
     copy(cnt, b->d_counters, sizeof(cnt));
     copy(&ovf, a.overflow, 4);
     if (!rc && hipStreamSynchronize(st) != hipSuccess) rc = fail(MK_EDEVICE, "mk_count7: sync");
+    const bool device_ok = !rc && cnt[kErrors] == 0 && cnt[kAdjOverflow] == 0 && ovf == 0;
+    if (device_ok) {
+        for (int g = 0; g < ng; ++g) {
+            const size_t m = (size_t)std::min<int64_t>((int64_t)hn[g], cap);
+            copy(codes + (size_t)g * cap, d_codes + (size_t)g * cap, 8 * m);
+            copy(counts + (size_t)g * cap, d_counts + (size_t)g * cap, 8 * m);
+        }
+        if (!rc && hipStreamSynchronize(st) != hipSuccess) rc = fail(MK_EDEVICE, "mk_count7: sync");
+    }
     float ms = 0.f;
     if (!rc) (void)hipEventElapsedTime(&ms, b->ev[1], b->ev[2]);
     release();
@@ -865,17 +874,19 @@ static int count7_once(mk_batch *b, int class_log2, int cache_log2, int64_t cap,
     if (*overflow) return MK_OK;
     if (kernel_ms) *kernel_ms = ms;
     bool small = false;
+    std::vector<std::pair<uint64_t, uint64_t>> pr;
     for (int g = 0; g < ng; ++g) {
         n_classes[g] = (int64_t)hn[g];
         if (totals) totals[g] = ht[g];
-        const int64_t m = std::min<int64_t>((int64_t)hn[g], cap);
+        const size_t m = (size_t)std::min<int64_t>((int64_t)hn[g], cap);
         small |= (int64_t)hn[g] > cap;
-        std::vector<std::pair<uint64_t, uint64_t>> pr((size_t)m);
-        for (int64_t i = 0; i < m; ++i) pr[i] = {hc[(size_t)g * cap + i], hv[(size_t)g * cap + i]};
+        uint64_t *gc = codes + (size_t)g * cap, *gv = counts + (size_t)g * cap;
+        pr.resize(m);
+        for (size_t i = 0; i < m; ++i) pr[i] = {gc[i], gv[i]};
         std::sort(pr.begin(), pr.end());
-        for (int64_t i = 0; i < m; ++i) {
-            codes[(size_t)g * cap + i] = pr[i].first;
-            counts[(size_t)g * cap + i] = pr[i].second;
+        for (size_t i = 0; i < m; ++i) {
+            gc[i] = pr[i].first;
+            gv[i] = pr[i].second;
         }
     }
     if (small) return fail(MK_ERANGE, "mk_count7: a graph has more classes than cap=%lld", (long long)cap);
