@@ -346,7 +346,10 @@ void mk_batch_free(mk_batch *b);
    codes[g * cap + i] with their counts in counts[g * cap + i].  totals[g]
    (may be NULL) receives the number of connected 7-sets; kernel_ms (may be
    NULL) the counting kernel's time.  MK_ERANGE when a graph has more than
-   cap classes (n_classes is still filled).  Blocks. */
+   cap classes (n_classes is still filled).  Blocks.  The first call on a
+   context allocates a 64 MiB cache of canonical codes that the context
+   keeps (and mk_destroy frees), so later calls skip the codes already
+   canonicalised. */
 int mk_count7(mk_ctx *ctx, const mk_graph *const *gs, int32_t ng, int64_t cap,
               uint64_t *codes, uint64_t *counts, int64_t *n_classes, uint64_t *totals,
               double *kernel_ms);

@@ -102,6 +102,8 @@ extern "C" void mk_destroy(mk_ctx *ctx)
     (void)hipSetDevice(ctx->device);
     (void)hipStreamSynchronize(ctx->stream);
     for (int k = 0; k < 7; ++k) free_table(ctx->tables[k]);
+    if (ctx->k7_cache_key) (void)hipFree(ctx->k7_cache_key);
+    if (ctx->k7_cache_val) (void)hipFree(ctx->k7_cache_val);
     (void)hipStreamDestroy(ctx->stream);
     delete ctx;
 }
@@ -781,19 +783,22 @@ extern "C" int mk_count(mk_ctx *ctx, const mk_graph *g, const mk_table *t, uint6
 
 // ------------------------------------------------------------------ k = 7
 
+// slots of a context's k = 7 canonical-code cache: 2^22
+constexpr int kK7CacheLog2 = 22;
+
 // one k = 7 pass over a prepared batch with class tables of 2^class_log2
 // slots per graph; *overflow tells whether a table was too small
-static int count7_once(mk_batch *b, int class_log2, int cache_log2, int64_t cap, uint64_t *codes,
+static int count7_once(mk_batch *b, int class_log2, int64_t cap, uint64_t *codes,
                        uint64_t *counts, int64_t *n_classes, uint64_t *totals, double *kernel_ms,
                        bool *overflow)
 {
     mk_ctx *ctx = b->ctx;
     hipStream_t st = ctx->stream;
     const int ng = b->ng;
-    const size_t cache_slots = (size_t)1 << cache_log2;
+    const size_t cache_slots = (size_t)1 << kK7CacheLog2;
     const size_t class_slots = ((size_t)1 << class_log2) * (size_t)ng;
     K7Launch a{};
-    a.cache_log2 = cache_log2;
+    a.cache_log2 = kK7CacheLog2;
     a.class_log2 = class_log2;
     unsigned long long *d_out = nullptr, *d_n = nullptr;
     std::vector<void *> bufs;
@@ -805,9 +810,29 @@ static int count7_once(mk_batch *b, int class_log2, int cache_log2, int64_t cap,
     auto release = [&]() {
         for (void *p : bufs) (void)hipFree(p);
     };
-    hipError_t e = alloc((void **)&a.cache_key, 8 * cache_slots);
-    if (e == hipSuccess) e = alloc((void **)&a.cache_val, 8 * cache_slots);
-    if (e == hipSuccess) e = alloc((void **)&a.class_key, 8 * class_slots);
+    // the canonical-code cache of the context: made and cleared once, then
+    // kept warm across counts (its entries do not depend on the graphs)
+    hipError_t e = hipSuccess;
+    if (!ctx->k7_cache_key) {
+        unsigned long long *ck = nullptr, *cv = nullptr;
+        e = hipMalloc(&ck, 8 * cache_slots);
+        if (e == hipSuccess) e = hipMalloc(&cv, 8 * cache_slots);
+        int frc = MK_OK;
+        if (e == hipSuccess) frc = fill_u32(ck, 0xFFFFFFFFu, 2 * cache_slots, st);
+        if (e == hipSuccess && !frc) frc = fill_u32(cv, 0xFFFFFFFFu, 2 * cache_slots, st);
+        if (e != hipSuccess || frc) {
+            if (ck) (void)hipFree(ck);
+            if (cv) (void)hipFree(cv);
+            if (frc) return frc;
+            return fail(e == hipErrorOutOfMemory ? MK_ENOMEM : MK_EDEVICE,
+                        "mk_count7: cache allocation: %s", hipGetErrorString(e));
+        }
+        ctx->k7_cache_key = ck;
+        ctx->k7_cache_val = cv;
+    }
+    a.cache_key = ctx->k7_cache_key;
+    a.cache_val = ctx->k7_cache_val;
+    e = alloc((void **)&a.class_key, 8 * class_slots);
     if (e == hipSuccess) e = alloc((void **)&a.class_cnt, 8 * class_slots);
     if (e == hipSuccess) e = alloc((void **)&a.totals, 8 * (size_t)ng);
     if (e == hipSuccess) e = alloc((void **)&a.overflow, 4);
@@ -823,9 +848,7 @@ static int count7_once(mk_batch *b, int class_log2, int cache_log2, int64_t cap,
                     hipGetErrorString(e));
     }
     unsigned long long *d_codes = d_out, *d_counts = d_out + (size_t)ng * (size_t)cap;
-    int rc = fill_u32(a.cache_key, 0xFFFFFFFFu, 2 * cache_slots, st);
-    if (!rc) rc = fill_u32(a.cache_val, 0xFFFFFFFFu, 2 * cache_slots, st);
-    if (!rc) rc = fill_u32(a.class_key, 0xFFFFFFFFu, 2 * class_slots, st);
+    int rc = fill_u32(a.class_key, 0xFFFFFFFFu, 2 * class_slots, st);
     if (!rc) rc = fill_u32(a.class_cnt, 0u, 2 * class_slots, st);
     if (!rc) rc = fill_u32(a.totals, 0u, 2 * (size_t)ng, st);
     if (!rc) rc = fill_u32(a.overflow, 0u, 1, st);
@@ -928,7 +951,7 @@ extern "C" int mk_count7(mk_ctx *ctx, const mk_graph *const *gs, int32_t ng, int
     // at first), 4x larger after an overflow
     for (int class_log2 = ctx->k7_class_log2;; class_log2 += 2) {
         bool overflow = false;
-        rc = count7_once(b, class_log2, 22, cap, codes, counts, n_classes, totals, kernel_ms,
+        rc = count7_once(b, class_log2, cap, codes, counts, n_classes, totals, kernel_ms,
                          &overflow);
         if (rc || !overflow) {
             if (!rc) ctx->k7_class_log2 = class_log2;

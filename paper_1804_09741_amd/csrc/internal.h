@@ -123,6 +123,9 @@ struct Ctx {
     size_t max_lds = 0;
     Table *tables[7] = {};
     int k7_class_log2 = 10;  // class-table size of the last k = 7 count (grows as needed)
+    // k = 7 canonical-code cache (labelled code -> canonical code; 2^22
+    // slots each, made by the first count and kept: it holds no graph data)
+    unsigned long long *k7_cache_key = nullptr, *k7_cache_val = nullptr;
     std::recursive_mutex mu;
 };
 

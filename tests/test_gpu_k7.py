@@ -135,3 +135,26 @@ def test_errors(ctx):
             tiny.free()
     finally:
         g.free()
+
+
+def test_cache_kept_across_calls():
+    """The canonical-code cache a context keeps between calls: counts of one
+    graph, another, then the first again on a fresh context, each equal to
+    the oracle's."""
+    rng = np.random.default_rng(8500)
+    g1 = I.chung_lu_digraph(45, 75, 2.2, 8, 0.2, rng)
+    g2 = I.relabel(*I.chung_lu_digraph(40, 70, 2.4, 8, 0.2, rng), rng.permutation(40))
+    exp1, exp2 = O.count(*g1, 7), O.count(*g2, 7)
+    c = M.Context(0)
+    try:
+        for g, exp in ((g1, exp1), (g2, exp2), (g1, exp1)):
+            gr = c.load_graph(*g)
+            try:
+                out, totals, _ = c.count7([gr])
+            finally:
+                gr.free()
+            codes, counts = out[0]
+            assert dict(zip(codes.tolist(), counts.tolist())) == exp
+            assert int(totals[0]) == sum(exp.values())
+    finally:
+        c.close()
