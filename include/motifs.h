@@ -228,7 +228,10 @@ typedef struct mk_batch_opts {
     uint64_t split_threshold; /* floor of the estimated subgraphs per work
                                  unit (the planner raises it so that the
                                  whole batch makes ~16 units per wave, ~64
-                                 on sorted-list adjacency below k = 7) */
+                                 on sorted-list adjacency below k = 7);
+                                 0: 512 for k = 6 by enumeration, else 4096
+                                 (nodes planned for sets of 3 or fewer
+                                 vertices are not split) */
     int32_t waves_per_cu;     /* resident enumeration waves per compute unit */
     int32_t use_graph;        /* 1: replay a captured hipGraph (default),
                                  -1: plain stream launches */
