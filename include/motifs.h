@@ -350,12 +350,22 @@ void mk_batch_free(mk_batch *b);
    (may be NULL) receives the number of connected 7-sets; kernel_ms (may be
    NULL) the counting kernel's time.  MK_ERANGE when a graph has more than
    cap classes (n_classes is still filled).  Blocks.  The first call on a
-   context allocates a 64 MiB cache of canonical codes that the context
-   keeps (and mk_destroy frees), so later calls skip the codes already
-   canonicalised. */
+   context allocates a cache of 2^22 canonical codes (64 MiB) that the
+   context keeps (and mk_destroy frees), so later calls skip the codes
+   already canonicalised (see mk_k7_cache_info). */
 int mk_count7(mk_ctx *ctx, const mk_graph *const *gs, int32_t ng, int64_t cap,
               uint64_t *codes, uint64_t *counts, int64_t *n_classes, uint64_t *totals,
               double *kernel_ms);
+
+/* The canonical-code cache of mk_count7: its number of slots (0 before the
+   context's first k = 7 count) and how many hold a code.  mk_count7 clears
+   it by itself before a count once more than half of the slots are used
+   (long probes, codes no longer entered). */
+int mk_k7_cache_info(mk_ctx *ctx, uint64_t *slots, uint64_t *used);
+
+/* Empty the canonical-code cache of mk_count7 (the next count starts cold).
+   Blocks. */
+int mk_k7_cache_clear(mk_ctx *ctx);
 
 /* Autotuner: time the batch path on these graphs (best of `trials` runs
    each) under candidate settings -- counting method, split-threshold floor,

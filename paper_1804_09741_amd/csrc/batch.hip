@@ -104,6 +104,7 @@ extern "C" void mk_destroy(mk_ctx *ctx)
     for (int k = 0; k < 7; ++k) free_table(ctx->tables[k]);
     if (ctx->k7_cache_key) (void)hipFree(ctx->k7_cache_key);
     if (ctx->k7_cache_val) (void)hipFree(ctx->k7_cache_val);
+    if (ctx->k7_cache_used) (void)hipFree(ctx->k7_cache_used);
     (void)hipStreamDestroy(ctx->stream);
     delete ctx;
 }
@@ -786,6 +787,38 @@ extern "C" int mk_count(mk_ctx *ctx, const mk_graph *g, const mk_table *t, uint6
 // slots of a context's k = 7 canonical-code cache: 2^22
 constexpr int kK7CacheLog2 = 22;
 
+// empty the context's canonical-code cache (keys, values, fill counter)
+static int k7_cache_clear(mk_ctx *ctx, hipStream_t st)
+{
+    const size_t cache_slots = (size_t)1 << kK7CacheLog2;
+    int rc = fill_u32(ctx->k7_cache_key, 0xFFFFFFFFu, 2 * cache_slots, st);
+    if (!rc) rc = fill_u32(ctx->k7_cache_val, 0xFFFFFFFFu, 2 * cache_slots, st);
+    if (!rc) rc = fill_u32(ctx->k7_cache_used, 0u, 1, st);
+    if (!rc) ctx->k7_cache_fill = 0;
+    return rc;
+}
+
+extern "C" int mk_k7_cache_info(mk_ctx *ctx, uint64_t *slots, uint64_t *used)
+{
+    if (!ctx) return fail(MK_EINVAL, "mk_k7_cache_info: NULL context");
+    std::lock_guard<std::recursive_mutex> lock(ctx->mu);
+    if (slots) *slots = ctx->k7_cache_key ? (uint64_t)1 << kK7CacheLog2 : 0;
+    if (used) *used = ctx->k7_cache_key ? ctx->k7_cache_fill : 0;
+    return MK_OK;
+}
+
+extern "C" int mk_k7_cache_clear(mk_ctx *ctx)
+{
+    if (!ctx) return fail(MK_EINVAL, "mk_k7_cache_clear: NULL context");
+    std::lock_guard<std::recursive_mutex> lock(ctx->mu);
+    if (!ctx->k7_cache_key) return MK_OK;
+    MK_HIP(hipSetDevice(ctx->device));
+    int rc = k7_cache_clear(ctx, ctx->stream);
+    if (rc) return rc;
+    MK_HIP(hipStreamSynchronize(ctx->stream));
+    return MK_OK;
+}
+
 // one k = 7 pass over a prepared batch with class tables of 2^class_log2
 // slots per graph; *overflow tells whether a table was too small
 static int count7_once(mk_batch *b, int class_log2, int64_t cap, uint64_t *codes,
@@ -815,23 +848,31 @@ static int count7_once(mk_batch *b, int class_log2, int64_t cap, uint64_t *codes
     hipError_t e = hipSuccess;
     if (!ctx->k7_cache_key) {
         unsigned long long *ck = nullptr, *cv = nullptr;
+        uint32_t *cu = nullptr;
         e = hipMalloc(&ck, 8 * cache_slots);
         if (e == hipSuccess) e = hipMalloc(&cv, 8 * cache_slots);
-        int frc = MK_OK;
-        if (e == hipSuccess) frc = fill_u32(ck, 0xFFFFFFFFu, 2 * cache_slots, st);
-        if (e == hipSuccess && !frc) frc = fill_u32(cv, 0xFFFFFFFFu, 2 * cache_slots, st);
-        if (e != hipSuccess || frc) {
+        if (e == hipSuccess) e = hipMalloc(&cu, 4);
+        if (e != hipSuccess) {
             if (ck) (void)hipFree(ck);
             if (cv) (void)hipFree(cv);
-            if (frc) return frc;
+            if (cu) (void)hipFree(cu);
             return fail(e == hipErrorOutOfMemory ? MK_ENOMEM : MK_EDEVICE,
                         "mk_count7: cache allocation: %s", hipGetErrorString(e));
         }
         ctx->k7_cache_key = ck;
         ctx->k7_cache_val = cv;
+        ctx->k7_cache_used = cu;
+        ctx->k7_cache_fill = cache_slots;  // forces the clear below
+    }
+    // a cache past half full is cleared before the count: its probes would
+    // grow long and new codes could no longer be entered
+    if (ctx->k7_cache_fill > cache_slots / 2) {
+        int frc = k7_cache_clear(ctx, st);
+        if (frc) return frc;
     }
     a.cache_key = ctx->k7_cache_key;
     a.cache_val = ctx->k7_cache_val;
+    a.cache_used = ctx->k7_cache_used;
     e = alloc((void **)&a.class_key, 8 * class_slots);
     if (e == hipSuccess) e = alloc((void **)&a.class_cnt, 8 * class_slots);
     if (e == hipSuccess) e = alloc((void **)&a.totals, 8 * (size_t)ng);
@@ -876,7 +917,10 @@ static int count7_once(mk_batch *b, int class_log2, int64_t cap, uint64_t *codes
     copy(ht.data(), a.totals, 8 * (size_t)ng);
     copy(cnt, b->d_counters, sizeof(cnt));
     copy(&ovf, a.overflow, 4);
+    uint32_t used = 0;
+    copy(&used, ctx->k7_cache_used, 4);
     if (!rc && hipStreamSynchronize(st) != hipSuccess) rc = fail(MK_EDEVICE, "mk_count7: sync");
+    if (!rc) ctx->k7_cache_fill = used;
     const bool device_ok = !rc && cnt[kErrors] == 0 && cnt[kAdjOverflow] == 0 && ovf == 0;
     if (device_ok) {
         for (int g = 0; g < ng; ++g) {

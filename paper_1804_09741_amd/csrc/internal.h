@@ -126,6 +126,8 @@ struct Ctx {
     // k = 7 canonical-code cache (labelled code -> canonical code; 2^22
     // slots each, made by the first count and kept: it holds no graph data)
     unsigned long long *k7_cache_key = nullptr, *k7_cache_val = nullptr;
+    uint32_t *k7_cache_used = nullptr;  // device: slots claimed since the last clear
+    uint64_t k7_cache_fill = 0;         // host copy, read back after every count
     std::recursive_mutex mu;
 };
 
@@ -175,6 +177,7 @@ struct K7Launch {
     int class_log2;                              // log2 of the class slots per graph
     unsigned long long *totals;                  // per graph: subgraphs
     uint32_t *overflow;                          // class inserts that found no slot
+    uint32_t *cache_used;                        // cache slots claimed (fill level)
     uint8_t *etag;                               // device-memory marks: tag bytes,
     size_t etag_stride;                          //   per workgroup, all zero
 };

@@ -42,6 +42,7 @@ struct K7Tables {
     uint32_t class_mask;
     unsigned long long *totals;    // per graph: subgraphs counted
     uint32_t *overflow;            // class-table inserts that found no slot
+    uint32_t *cache_used;          // cache slots claimed so far (its fill level)
     uint8_t *etag;                 // marks in device memory: the tags too,
     size_t etag_stride;            //   etag_stride bytes per workgroup, zero
 };
@@ -157,6 +158,7 @@ __device__ void flush7(EnumState<7, V> &s, K7Wave &w, const K7Tables &t)
             const Code7 m = canon7_wave(readlane64(key, l));
             if (lane == l) canon = m;
         }
+        bool claimed = false;
         if (missed) {
             // enter it: the lane that claims the key writes the value; a
             // reader that meets the key before the value computes it again
@@ -165,12 +167,15 @@ __device__ void flush7(EnumState<7, V> &s, K7Wave &w, const K7Tables &t)
                 const Code7 old = atomicCAS(&t.cache_key[h], kNoCode, key);
                 if (old == kNoCode) {
                     atomicExch(&t.cache_val[h], canon);
+                    claimed = true;
                     break;
                 }
                 if (old == key) break;
                 h = (h + 1) & t.cache_mask;
             }
         }
+        const unsigned long long ins = __ballot(claimed);
+        if (lane == 0 && ins) atomicAdd(t.cache_used, (uint32_t)__popcll(ins));
         if (live && cnt != 0u) {
             // sign-extended: the 64-bit sums stay exact modulo 2^64
             const unsigned long long add = (unsigned long long)(long long)(int32_t)cnt;
@@ -781,6 +786,7 @@ int launch_k7(const DevGraph *d_graphs, const int4 *units, uint32_t unit_cap, ui
     t.class_mask = (1u << a.class_log2) - 1u;
     t.totals = a.totals;
     t.overflow = a.overflow;
+    t.cache_used = a.cache_used;
     t.etag = a.etag;
     t.etag_stride = a.etag_stride;
     const void *fn = k7_fn(cfg.variant);

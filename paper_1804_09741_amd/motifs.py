@@ -114,6 +114,8 @@ SIGNATURES = {
     "mk_batch_timing": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double),
                                        ctypes.POINTER(ctypes.c_double)]),
     "mk_batch_free": (None, [_P]),
+    "mk_k7_cache_info": (ctypes.c_int, [_P, ctypes.POINTER(_U64), ctypes.POINTER(_U64)]),
+    "mk_k7_cache_clear": (ctypes.c_int, [_P]),
     "mk_autotune": (ctypes.c_int, [_P, _P, _I32, _P, _I32, ctypes.POINTER(BatchOpts),
                                    ctypes.POINTER(ctypes.c_double)]),
     "mk_server_start": (ctypes.c_int, [_P, ctypes.POINTER(ServerOpts), ctypes.POINTER(_P)]),
@@ -340,6 +342,17 @@ def mk_count7(ctx: int, gs: Sequence[int], cap: int = 1 << 16):
     return out, totals, ms.value
 
 
+def mk_k7_cache_info(ctx: int) -> Tuple[int, int]:
+    """(slots, used) of the context's k = 7 canonical-code cache."""
+    a, b = _U64(), _U64()
+    _check(library().mk_k7_cache_info(ctx, ctypes.byref(a), ctypes.byref(b)))
+    return a.value, b.value
+
+
+def mk_k7_cache_clear(ctx: int) -> None:
+    _check(library().mk_k7_cache_clear(ctx))
+
+
 def mk_batch_create(ctx: int, gs: Sequence[int], t: int, split_threshold: int = 0,
                     waves_per_cu: int = 0, use_graph: int = 0, units_per_grab: int = 0,
                     debug_flags: int = 0, method: int = 0, adjacency: int = 0,
@@ -545,6 +558,12 @@ class Context:
     def count7(self, graphs: Sequence[Graph], cap: int = 1 << 16):
         """H_7: per graph (canonical codes, counts) ascending; totals; kernel ms."""
         return mk_count7(self.handle, [g.handle for g in graphs], cap)
+
+    def k7_cache_info(self) -> Tuple[int, int]:
+        return mk_k7_cache_info(self.handle)
+
+    def k7_cache_clear(self) -> None:
+        mk_k7_cache_clear(self.handle)
 
     def batch(self, graphs: Sequence[Graph], table: Table, **opts) -> Batch:
         return Batch(self, graphs, table, **opts)

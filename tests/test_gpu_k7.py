@@ -146,8 +146,10 @@ def test_cache_kept_across_calls():
     g2 = I.relabel(*I.chung_lu_digraph(40, 70, 2.4, 8, 0.2, rng), rng.permutation(40))
     exp1, exp2 = O.count(*g1, 7), O.count(*g2, 7)
     c = M.Context(0)
+    bound = 0
     try:
         for g, exp in ((g1, exp1), (g2, exp2), (g1, exp1)):
+            bound += sum(exp.values())
             gr = c.load_graph(*g)
             try:
                 out, totals, _ = c.count7([gr])
@@ -156,5 +158,27 @@ def test_cache_kept_across_calls():
             codes, counts = out[0]
             assert dict(zip(codes.tolist(), counts.tolist())) == exp
             assert int(totals[0]) == sum(exp.values())
+            slots, used = c.k7_cache_info()
+            # every distinct labeled code is entered at most once
+            assert slots == 1 << 22 and 0 < used <= bound
+        # cleared: empty, and the next count starts cold and is still exact
+        c.k7_cache_clear()
+        assert c.k7_cache_info()[1] == 0
+        gr = c.load_graph(*g2)
+        try:
+            out, _, _ = c.count7([gr])
+        finally:
+            gr.free()
+        assert dict(zip(out[0][0].tolist(), out[0][1].tolist())) == exp2
+        assert c.k7_cache_info()[1] > 0
+    finally:
+        c.close()
+
+
+def test_cache_info_before_first_count():
+    c = M.Context(0)
+    try:
+        assert c.k7_cache_info() == (0, 0)
+        c.k7_cache_clear()
     finally:
         c.close()
