@@ -406,24 +406,35 @@ class Request:
     graph: Csr
 
 
-def serving_requests(count: int = 1000, rate_per_s: float = 100.0,
-                     seed: int = 5, n_max: int = 5000) -> List[Request]:
-    """Request stream: k ~ U{3..6}, n ~ U[100, n_max], m = round(n*U[2,6]),
-    gamma ~ U[2.0, 2.6], no reciprocity; Poisson arrivals at ``rate_per_s``.
-    Degrees are capped (200 for k<=5, 60 for k=6) so that every request has
-    a bounded number of k-subgraphs."""
+def serving_request(i: int, seed: int = 5, n_max: int = 5000) -> Tuple[int, Csr]:
+    """(k, graph) of request i of the stream: k ~ U{3..6}, n ~ U[100, n_max],
+    m = round(n*U[2,6]), gamma ~ U[2.0, 2.6], no reciprocity, degrees capped
+    at 200 for k<=5 and 60 for k=6 (so that every request has a bounded
+    number of k-subgraphs).  Request i depends only on (seed, i)."""
+    r = np.random.default_rng([5, seed, i])
+    k = int(r.integers(3, 7))
+    n = int(r.integers(100, n_max + 1))
+    m = int(round(n * r.uniform(2.0, 6.0)))
+    gamma = float(r.uniform(2.0, 2.6))
+    cap = 200 if k <= 5 else 60
+    return k, chung_lu_digraph(n, m, gamma, cap, 0.0, r)
+
+
+def serving_arrivals(count: int = 1000, rate_per_s: float = 100.0, seed: int = 5) -> np.ndarray:
+    """Poisson arrival times (seconds, the first at 0) of the stream."""
     rng = np.random.default_rng([5, seed])
     gaps = rng.exponential(1.0 / rate_per_s, size=count)
-    t = np.cumsum(gaps) - gaps[0]
+    return np.cumsum(gaps) - gaps[0]
+
+
+def serving_requests(count: int = 1000, rate_per_s: float = 100.0,
+                     seed: int = 5, n_max: int = 5000) -> List[Request]:
+    """The first ``count`` requests of the stream (``serving_request``) with
+    Poisson arrivals at ``rate_per_s``."""
+    t = serving_arrivals(count, rate_per_s, seed)
     out = []
     for i in range(count):
-        r = np.random.default_rng([5, seed, i])
-        k = int(r.integers(3, 7))
-        n = int(r.integers(100, n_max + 1))
-        m = int(round(n * r.uniform(2.0, 6.0)))
-        gamma = float(r.uniform(2.0, 2.6))
-        cap = 200 if k <= 5 else 60
-        g = chung_lu_digraph(n, m, gamma, cap, 0.0, r)
+        k, g = serving_request(i, seed, n_max)
         out.append(Request(float(t[i]), k, g))
     return out
 
