@@ -1,7 +1,7 @@
 #!/usr/bin/env python3
 """Benchmark of the Motifs-k hot path on one MI355X.
 
-    python bench.py [--steps K] [--warmup W] [--gpus 1]
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--serve R]
 
 One step = one full pass of the path over one batch of synthetic graphs,
 inputs (CSR graphs) and class table already resident in HBM: typed
@@ -12,15 +12,16 @@ Workload: k = 6, one directed graph with n = 700, m = 1500 (power-law
 out-degrees up to 60, Poisson in-degrees) plus 30 degree-preserving
 randomisations, counted in one launch (31 histograms of 1,530,843 classes).
 
-Printed: one JSON line with subgraphs/s, the roofline of the enumeration
-kernel (algorithmic HBM bytes: a 4-byte table entry and an 8-byte counter
-read + write per subgraph, over the kernel's HIP-event duration), the CPU
-oracle timed on a bounded sample, the plain one-graph-per-launch form on
-the same graphs, table build times, and the k = 5 batch (1 + 100
-randomisations of n = 1000, m = 3000) as a second reading; then both
-counting methods, the code-formation variants (arc tests on bit matrices or
-sorted lists, marks in LDS or device memory) with a k = 6 graph of 2^20
-vertices, and the ensemble pipeline.
+Printed: one JSON line with subgraphs/s; the roofline of the counting
+kernel (its busier issue pipe from the committed counter record over the
+kernel's live HIP-event duration, with the HBM, L2 and lane figures beside
+it); the CPU oracle on the host cores with every histogram compared; the
+plain one-graph-per-launch form on the same graphs; the k = 5 batch (1 + 100
+randomisations of n = 1000, m = 3000) as a second reading; the serving
+stream (1,000 Poisson requests, served and plain first-come-first-served
+under the same arrivals: throughput, p50 / p99); then both counting methods,
+the code-formation variants with a k = 6 graph of 2^20 vertices, k = 7, and
+the ensemble pipeline.
 """
 
 from __future__ import annotations
@@ -32,30 +33,64 @@ import sys
 import time
 
 HBM_PEAK_GBS = 8000.0
-BYTES_PER_SUBGRAPH = 4 + 8 + 8
+BYTES_PER_SUBGRAPH = 4 + 8 + 8   # k = 6 model: table entry, counter read + write
 ROOT = os.path.dirname(os.path.abspath(__file__))
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "enum_kernel_hbm_traffic.json")
-KERNEL_SOURCES = ("paper_1804_09741_amd/csrc/enum.hip", "paper_1804_09741_amd/csrc/core.hip",
-                  "paper_1804_09741_amd/csrc/esu.h", "paper_1804_09741_amd/csrc/internal.h")
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "counting_kernel_counters.json")
+DIGESTS_FILE = os.path.join(ROOT, "tests", "golden", "oracle_digests.json")
 
 
-def _measured_traffic(kernel):
-    """HBM bytes per launch of `kernel` from the committed counter runs
-    (FETCH_SIZE + WRITE_SIZE, scaled by a copy of known size), or None when
-    the kernel source changed since they were taken."""
-    import hashlib
+def _counter_record(kernel):
+    """The committed counter record of `kernel` (per-launch means of the
+    rocprofv3 --pmc passes, FETCH_SIZE / WRITE_SIZE scaled to bytes), or None
+    when the kernel sources changed since it was taken."""
+    from paper_1804_09741_amd import profsum as P
     try:
-        with open(TRAFFIC_FILE) as f:
+        with open(COUNTERS_FILE) as f:
             rec = json.load(f)
-        h = hashlib.sha256()
-        for name in KERNEL_SOURCES:
-            with open(os.path.join(ROOT, name), "rb") as f:
-                h.update(f.read())
-        if h.hexdigest()[:16] != rec["source_sha256_16"]:
+        if rec["source_sha256_16"] != P.source_hash():
             return None
-        return rec["kernels"][kernel]["traffic_bytes"]
+        return rec["kernels"][kernel]
     except (OSError, KeyError, ValueError):
         return None
+
+
+def _roofline(kernel, kernel_ms, subgraphs=None):
+    """Roofline of one counting-kernel launch: the busier issue pipe (VALU
+    or SALU wave-instructions per launch from the counter record, over the
+    live kernel duration) against 256 CUs x 2.4 GHz x 1, with lane use,
+    waits, L2 hit rate, L2 atomics and counter-measured HBM traffic beside
+    it, and for k = 6 the 20-byte-per-subgraph HBM model."""
+    from paper_1804_09741_amd import profsum as P
+    rec = _counter_record(kernel)
+    if rec is None:
+        r = {"bound": "alu", "achieved": None, "peak": P.ISSUE_PEAK,
+             "unit": "wave-instructions/s", "frac": None, "traffic": None,
+             "counters": "stale: kernel sources changed since the counter record"}
+    else:
+        d = P.derived(rec["counters"], kernel_ms / 1e3)
+        r = P.issue_roofline(d)
+        r["traffic"] = rec["traffic_bytes"]
+        for key in ("valu", "salu", "lds"):
+            if key in d:
+                r[key] = {"insts_per_launch": d[key]["insts_per_launch"], "frac": d[key]["frac"]}
+        for key in ("lane_util", "wait_frac", "lds_conflict_frac", "l2_hit",
+                    "l2_atomics_per_launch", "l2_atomic_rate", "l2_atomic_frac"):
+            if key in d:
+                r[key] = d[key]
+        r["hbm_measured"] = {"achieved": d["hbm_rate"] / 1e9, "peak": HBM_PEAK_GBS,
+                             "unit": "GB/s", "frac": d["hbm_frac"]}
+        r["counters"] = "profiles/counting_kernel_counters.json (%d dispatches, %s)" % (
+            rec["dispatches"], rec["workload"])
+        r["counters_kernel_ms"] = rec["kernel_ms"]
+    r["kernel"] = kernel
+    r["kernel_ms"] = kernel_ms
+    r["peak_derivation"] = ("256 CUs x 2.4 GHz x 1 wave64 instruction per CU-cycle per pipe "
+                            "(4 SIMD16 per CU, 4 cycles per wave64 VALU op; 1 scalar unit)")
+    if subgraphs is not None:
+        a = BYTES_PER_SUBGRAPH * subgraphs / (kernel_ms / 1e3) / 1e9
+        r["hbm_model"] = {"bytes_per_subgraph": BYTES_PER_SUBGRAPH, "achieved": a,
+                          "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": a / HBM_PEAK_GBS}
+    return r
 
 
 def _kernel_name(k, stats):
@@ -67,6 +102,16 @@ def _log(msg):
     print("[bench] " + msg, file=sys.stderr, flush=True)
 
 
+def _cpu_share():
+    """Worker processes for the oracle: the cores this process may run on,
+    at most 16 (one GPU's share of its host)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
 def _parse():
     p = argparse.ArgumentParser(description=__doc__.split("\n")[1])
     p.add_argument("--gpus", type=int, default=1)
@@ -76,7 +121,7 @@ def _parse():
     p.add_argument("--no-k5", action="store_true", help="skip the k=5 batch reading")
     p.add_argument("--no-plain", action="store_true", help="skip the plain comparator")
     p.add_argument("--cpu-graphs", type=int, default=10,
-                   help="graphs of the batch the CPU oracle counts (bounded sample)")
+                   help="graphs of the k=6 batch the single-thread oracle counts")
     p.add_argument("--split", type=int, default=0,
                    help="k=6 split threshold (0: library default)")
     p.add_argument("--k5-split", type=int, default=0,
@@ -96,8 +141,8 @@ def _parse():
     p.add_argument("--no-k7", action="store_true", help="skip the k=7 reading")
     p.add_argument("--no-ensemble", action="store_true",
                    help="skip the ensemble pipeline (random graphs, counts, z-scores)")
-    p.add_argument("--serve", type=int, default=0, metavar="R",
-                   help="also run the serving workload with R requests (0: skip)")
+    p.add_argument("--serve", type=int, default=1000, metavar="R",
+                   help="requests of the serving stream (0: skip)")
     p.add_argument("--serve-load", type=float, default=0.7,
                    help="open-loop arrival rate as a fraction of the measured capacity")
     return p.parse_args()
@@ -129,40 +174,92 @@ def _timed_batch(ctx, M, graphs, table, steps, warmup, torch, **opts):
         b.free()
 
 
-def _oracle_total(args):
-    """Worker of the parallel CPU baseline: the oracle's count of one graph."""
+def _oracle_hist(args):
+    """Worker of the CPU legs: the oracle's histogram of one graph as
+    ascending (canonical code, count) pairs, and its seconds."""
     rp, col, k = args
     from oracle import oracle as O
+    t0 = time.perf_counter()
     h = O.count(rp, col, k)
-    return sum(h.values())
+    return sorted(h.items()), time.perf_counter() - t0
 
 
 def _oracle_ready(_):
-    """Worker warm-up: load the oracle library."""
+    """Worker warm-up: load the oracle library and its k <= 5 tables."""
     import numpy as np
     from oracle import oracle as O
     O.count(np.zeros(4, np.int32), np.zeros(0, np.int32), 3)
+    O.canon_table(5)
     return os.getpid()
 
 
-def _cpu_parallel(graphs, k, procs):
-    """The oracle over every graph of the workload, one graph per task, in
-    `procs` worker processes, timed from the first task to the last result
-    after the workers are up.  Called before this process touches the GPU,
-    so the workers start from a process without device state."""
+def _cpu_legs(I, procs, single_graphs):
+    """The oracle on the host, before this process touches the GPU (the
+    worker processes start from a process without device state):
+      * all 31 graphs of the k = 6 batch, one graph per task on `procs`
+        processes -- the reported cpu_baseline;
+      * `procs` graphs of the k = 5 batch, one per process;
+      * graphs 0..single_graphs-1 of the k = 6 batch on one thread.
+    Every histogram is kept for the comparison with the GPU's."""
     import multiprocessing
     from concurrent.futures import ProcessPoolExecutor
+
+    from oracle import oracle as O
+    w6 = I.workload_k6_batch()
+    w5 = I.workload_k5_batch()
+    out = {}
     with ProcessPoolExecutor(max_workers=procs,
                              mp_context=multiprocessing.get_context("spawn")) as pool:
         list(pool.map(_oracle_ready, range(procs)))
-        t0 = time.perf_counter()
-        totals = list(pool.map(_oracle_total, [(rp, col, k) for rp, col in graphs]))
-        wall = time.perf_counter() - t0
-    counted = int(sum(totals))
-    return {"value": counted / wall, "unit": "subgraphs/s", "cores": procs, "kind": "oracle",
-            "sample": "all %d graphs of the batch (%d subgraphs), %d processes, %.1f s" % (
-                len(graphs), counted, procs, wall),
-            "totals": [int(x) for x in totals]}
+        for name, w, idx in (("k6", w6, range(len(w6.graphs))),
+                             ("k5", w5, range(min(procs, len(w5.graphs))))):
+            t0 = time.perf_counter()
+            res = list(pool.map(_oracle_hist, [(*w.graphs[i], w.k) for i in idx]))
+            wall = time.perf_counter() - t0
+            out[name] = {"workload": w.name, "graphs": list(idx), "wall_s": wall,
+                         "hists": [dict(h) for h, _ in res],
+                         "cpu_s": sum(t for _, t in res)}
+            _log("cpu oracle %s: %d graphs on %d processes in %.1f s" % (
+                name, len(idx), procs, wall))
+    t0 = time.perf_counter()
+    single = [O.count(*w6.graphs[i], 6) for i in range(min(single_graphs, len(w6.graphs)))]
+    out["single"] = {"wall_s": time.perf_counter() - t0, "hists": single}
+    _log("cpu oracle single thread: %d graphs in %.1f s" % (len(single), out["single"]["wall_s"]))
+    return out
+
+
+def _cpu_report(leg, gpu_hist, class_codes, procs, what):
+    """One CPU leg as a report object, its histograms compared with the
+    GPU's graph by graph."""
+    import numpy as np
+    counted = sum(sum(h.values()) for h in leg["hists"])
+    match = 0
+    for i, h in zip(leg["graphs"], leg["hists"]):
+        nz = np.flatnonzero(gpu_hist[i])
+        match += int(h == {int(class_codes[j]): int(gpu_hist[i][j]) for j in nz})
+    return {"value": counted / leg["wall_s"], "unit": "subgraphs/s", "cores": procs,
+            "kind": "oracle",
+            "sample": "%s: %d graphs (%d subgraphs), one graph per task on %d processes, "
+                      "%.1f s wall, %.0f CPU-s" % (what, len(leg["graphs"]), counted, procs,
+                                                    leg["wall_s"], leg["cpu_s"]),
+            "host_cpu_count": os.cpu_count(), "hists_match_gpu": match == len(leg["graphs"]),
+            "graphs_matching": match}
+
+
+def _digest_check(name, hist, class_codes, graphs):
+    """GPU histograms of every graph against the stored oracle digests
+    (tests/golden/oracle_digests.json, written from the oracle alone)."""
+    from oracle.digest import dense_digest, graph_digest
+    try:
+        with open(DIGESTS_FILE) as f:
+            recs = json.load(f)[name]
+    except (OSError, KeyError, ValueError):
+        return None
+    ok_in = all(r["graph"] == graph_digest(*g) for r, g in zip(recs, graphs))
+    match = sum(int(dense_digest(hist[i], class_codes) == recs[i]["hist"])
+                for i in range(len(recs)))
+    return {"graphs": len(recs), "inputs_match": ok_in, "graphs_matching": match,
+            "all_match": ok_in and match == len(recs) == len(graphs)}
 
 
 def _plain(ctx, graphs, table, steps, torch, **opts):
@@ -251,11 +348,12 @@ def _variants(ctx, M, I, torch):
                     "value": sub / (float(np.mean(r["pass_ms"])) / 1e3),
                     "unit": "subgraphs/s", "adjacency": st["adjacency"], "marks": st["marks"],
                     "grid": st["grid"], "units": st["units"],
-                    "roofline": {"bound": "hbm", "kernel": "enum_lists_kernel<6, 3>",
-                                 "achieved": BYTES_PER_SUBGRAPH * sub / (kern / 1e3) / 1e9,
-                                 "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                                 "frac": BYTES_PER_SUBGRAPH * sub / (kern / 1e3) / 1e9 / HBM_PEAK_GBS,
-                                 "bytes_per_subgraph": BYTES_PER_SUBGRAPH}}
+                    "hbm_model": {"kernel": "enum_lists_kernel<6, 3>",
+                                  "bytes_per_subgraph": BYTES_PER_SUBGRAPH,
+                                  "achieved": BYTES_PER_SUBGRAPH * sub / (kern / 1e3) / 1e9,
+                                  "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                  "frac": BYTES_PER_SUBGRAPH * sub / (kern / 1e3) / 1e9
+                                  / HBM_PEAK_GBS}}
     _log("variants: %s, %d subgraphs, pass %.1f ms (kernel %.1f ms), %.3g subgraphs/s" % (
         w.name, sub, res["large"]["pass_ms"], kern, res["large"]["value"]))
     return res
@@ -263,21 +361,26 @@ def _variants(ctx, M, I, torch):
 
 def _k7(ctx, M, I, torch):
     """k = 7 on the 31 graphs of the k = 6 batch (classes by canonical code,
-    canonicalised on the device): two calls.  The first, on a context that
-    has not counted k = 7 yet, grows the class tables and fills the
-    context's canonical-code cache (its wall time is reported as
-    first_call_ms); the second, timed, finds that cache warm."""
+    canonicalised on the device).  A first call sizes the class tables and
+    fills the canonical-code cache (its wall time: first_call_ms); the cache
+    is then cleared and the timed call starts cold -- every distinct labeled
+    code canonicalised again -- which gives `value`; a third call on the
+    warm cache is reported beside it."""
     import numpy as np
     w = I.workload_k6_batch()
     gs = [ctx.load_graph(*g) for g in w.graphs]
     try:
         t0 = time.perf_counter()
         ctx.count7(gs)
-        torch.cuda.synchronize()
         first = time.perf_counter() - t0
+        ctx.k7_cache_clear()
         t0 = time.perf_counter()
         out, totals, kern = ctx.count7(gs)
         wall = time.perf_counter() - t0
+        slots, used = ctx.k7_cache_info()
+        t0 = time.perf_counter()
+        _, _, kern_warm = ctx.count7(gs)
+        wall_warm = time.perf_counter() - t0
     finally:
         for g in gs:
             g.free()
@@ -285,16 +388,22 @@ def _k7(ctx, M, I, torch):
     classes = [len(c) for c, _ in out]
     res = {"workload": w.name.replace("k6_", "k7_"), "subgraphs": sub, "kernel_ms": kern,
            "call_ms": wall * 1e3, "value": sub / (kern / 1e3), "unit": "subgraphs/s (kernel)",
-           "cache": "warm", "first_call_ms": first * 1e3,
+           "cache": "cold (cleared before the call)", "call_value": sub / wall,
+           "cache_slots": slots, "cache_used_after": used,
+           "warm": {"kernel_ms": kern_warm, "call_ms": wall_warm * 1e3,
+                    "value": sub / (kern_warm / 1e3)},
+           "first_call_ms": first * 1e3,
            "classes_mean": float(np.mean(classes)), "classes_max": int(max(classes))}
-    _log("k=7 on the k=6 batch: %d subgraphs, kernel %.1f ms (%.3g/s), call %.1f ms (warm cache; "
-         "first call %.1f ms), %.0f classes per graph" % (sub, kern, res["value"], res["call_ms"],
-                                                          res["first_call_ms"], res["classes_mean"]))
+    _log("k=7 on the k=6 batch: %d subgraphs, cold kernel %.1f ms (%.3g/s), call %.1f ms; warm "
+         "kernel %.1f ms; first call %.1f ms; cache %d of %d slots" % (
+             sub, kern, res["value"], res["call_ms"], kern_warm, res["first_call_ms"], used,
+             slots))
     # one graph past the LDS limit (marks and tags in device memory)
     wl = I.workload_k6_large(1 << 17)
     g = ctx.load_graph(*wl.graphs[0])
     try:
         ctx.count7([g])
+        ctx.k7_cache_clear()
         t0 = time.perf_counter()
         out, totals, kern = ctx.count7([g])
         wall = time.perf_counter() - t0
@@ -303,8 +412,9 @@ def _k7(ctx, M, I, torch):
     sub = int(totals[0])
     res["large"] = {"workload": wl.name.replace("k6_", "k7_"), "subgraphs": sub, "kernel_ms": kern,
                     "call_ms": wall * 1e3, "value": sub / (kern / 1e3),
-                    "unit": "subgraphs/s (kernel)", "classes": len(out[0][0])}
-    _log("k=7 on %s: %d subgraphs, kernel %.1f ms (%.3g/s), %d classes" % (
+                    "unit": "subgraphs/s (kernel)", "cache": "cold",
+                    "classes": len(out[0][0])}
+    _log("k=7 on %s: %d subgraphs, cold kernel %.1f ms (%.3g/s), %d classes" % (
         res["large"]["workload"], sub, kern, res["large"]["value"], res["large"]["classes"]))
     return res
 
@@ -350,73 +460,123 @@ def _ensemble(ctx, M, I, torch, cpu=True, R=100, spa=10, seed=2024):
 
 
 def _serving(ctx, M, I, R, load, torch):
-    """Serving workload: R (graph, k) requests, graphs resident on the device.
+    """Serving workload: R (graph, k) requests of the stream (k uniform in
+    3..6, n in [100, 5000]), graphs resident on the device.
 
-    1. plain: one request per launch, first come first served (mk_count);
+    1. plain, closed loop: one mk_count per request, first come first
+       served -> plain throughput;
     2. served, closed loop: all requests submitted at once -> capacity;
-    3. served, open loop: Poisson arrivals at `load` x capacity -> p50/p99 of
-       (completion - submission) as timed by the server.
-    Every served histogram must equal the plain one.
+    3. served, open loop: Poisson arrivals at `load` x capacity -> p50 / p99
+       of (completion - arrival) as timed by the server;
+    4. plain, open loop: the same arrivals, one mk_count per request in
+       arrival order on one thread -> p50 / p99 of (completion - arrival).
+    Every served histogram must equal the plain one; those of the requests
+    in the stored oracle digests are compared with the oracle too.
     """
     import threading
 
     import numpy as np
 
-    reqs = I.serving_requests(count=R)
-    _log("serving: %d requests generated" % R)
-    for k in (3, 4, 5, 6):
-        ctx.table(k)
-    graphs = [ctx.load_graph(*r.graph) for r in reqs]
-    tables = {k: ctx.table(k) for k in (3, 4, 5, 6)}
-    t0 = time.perf_counter()
-    plain = [ctx.count(g, tables[r.k])[0] for g, r in zip(graphs, reqs)]
-    plain_s = time.perf_counter() - t0
-    total = int(sum(int(h.sum()) for h in plain))
-    _log("serving: plain FIFO %.2f s, %d subgraphs" % (plain_s, total))
+    from oracle.digest import dense_digest
 
-    srv = ctx.server()
+    t0 = time.perf_counter()
+    reqs = I.serving_requests(count=R)
+    _log("serving: %d requests generated in %.1f s" % (R, time.perf_counter() - t0))
+    tables = {k: ctx.table(k) for k in (3, 4, 5, 6)}
+    codes = {k: tables[k].class_codes() for k in tables}
+    graphs = [ctx.load_graph(*r.graph) for r in reqs]
     try:
         t0 = time.perf_counter()
-        tickets = [srv.submit(g, r.k) for g, r in zip(graphs, reqs)]
-        burst = [srv.wait(t, r.k) for t, r in zip(tickets, reqs)]
-        burst_s = time.perf_counter() - t0
-        same = all(np.array_equal(h, p) for (h, _), p in zip(burst, plain))
-        _log("serving: closed loop %.2f s" % burst_s)
-        rate = load * R / burst_s
-        gaps = np.random.default_rng(55).exponential(1.0 / rate, size=R)
-        arrivals = np.cumsum(gaps) - gaps[0]
-        tickets = [None] * R
+        plain = [ctx.count(g, tables[r.k])[0] for g, r in zip(graphs, reqs)]
+        plain_s = time.perf_counter() - t0
+        total = int(sum(int(h.sum()) for h in plain))
+        _log("serving: plain FIFO closed loop %.2f s, %d subgraphs" % (plain_s, total))
 
-        def submitter():
-            start = time.perf_counter()
+        srv = ctx.server()
+        try:
+            t0 = time.perf_counter()
+            tickets = [srv.submit(g, r.k) for g, r in zip(graphs, reqs)]
+            burst = [srv.wait(t, r.k) for t, r in zip(tickets, reqs)]
+            burst_s = time.perf_counter() - t0
+            same = all(np.array_equal(h, p) for (h, _), p in zip(burst, plain))
+            _log("serving: served closed loop %.2f s" % burst_s)
+            rate = load * R / burst_s
+            gaps = np.random.default_rng(55).exponential(1.0 / rate, size=R)
+            arrivals = np.cumsum(gaps) - gaps[0]
+            tickets = [None] * R
+
+            def submitter():
+                start = time.perf_counter()
+                for i in range(R):
+                    delay = arrivals[i] - (time.perf_counter() - start)
+                    if delay > 0:
+                        time.sleep(delay)
+                    tickets[i] = srv.submit(graphs[i], reqs[i].k)
+
+            th = threading.Thread(target=submitter)
+            t0 = time.perf_counter()
+            th.start()
+            lat = []
             for i in range(R):
-                delay = arrivals[i] - (time.perf_counter() - start)
-                if delay > 0:
-                    time.sleep(delay)
-                tickets[i] = srv.submit(graphs[i], reqs[i].k)
+                while tickets[i] is None:
+                    time.sleep(0.0005)
+                h, tm = srv.wait(tickets[i], reqs[i].k)
+                same &= bool(np.array_equal(h, plain[i]))
+                lat.append((tm["done_us"] - tm["submit_us"]) / 1000.0)
+            th.join()
+            open_s = time.perf_counter() - t0
+        finally:
+            srv.stop()
+        _log("serving: served open loop %.2f s, p50 %.1f ms, p99 %.1f ms" % (
+            open_s, np.percentile(lat, 50), np.percentile(lat, 99)))
 
-        th = threading.Thread(target=submitter)
-        t0 = time.perf_counter()
-        th.start()
-        lat = []
+        # plain FIFO under the same arrivals
+        flat = []
+        start = time.perf_counter()
         for i in range(R):
-            while tickets[i] is None:
-                time.sleep(0.0005)
-            h, tm = srv.wait(tickets[i], reqs[i].k)
+            delay = arrivals[i] - (time.perf_counter() - start)
+            if delay > 0:
+                time.sleep(delay)
+            h = ctx.count(graphs[i], tables[reqs[i].k])[0]
+            flat.append(1000.0 * (time.perf_counter() - start - arrivals[i]))
             same &= bool(np.array_equal(h, plain[i]))
-            lat.append((tm["done_us"] - tm["submit_us"]) / 1000.0)
-        th.join()
-        open_s = time.perf_counter() - t0
+        fifo_open_s = time.perf_counter() - start
+        _log("serving: plain FIFO open loop %.2f s, p50 %.1f ms, p99 %.1f ms" % (
+            fifo_open_s, np.percentile(flat, 50), np.percentile(flat, 99)))
     finally:
-        srv.stop()
-    for g in graphs:
-        g.free()
-    return {"requests": R, "subgraphs": total, "value": total / burst_s,
+        for g in graphs:
+            g.free()
+    # the oracle's histograms of the requests it could count (stored digests)
+    checked = matched = 0
+    try:
+        with open(DIGESTS_FILE) as f:
+            chk = json.load(f)["serving"]["checked"]
+        for i in range(R):
+            rec = chk.get(str(i))
+            if rec is not None:
+                checked += 1
+                matched += int(dense_digest(plain[i], codes[reqs[i].k]) == rec["hist"])
+    except (OSError, KeyError, ValueError):
+        pass
+    by_k = {}
+    for r, h in zip(reqs, plain):
+        d = by_k.setdefault(str(r.k), {"requests": 0, "subgraphs": 0})
+        d["requests"] += 1
+        d["subgraphs"] += int(h.sum())
+    return {"requests": R, "subgraphs": total, "by_k": by_k,
+            "value": total / burst_s, "unit": "subgraphs/s",
             "plain_value": total / plain_s, "speedup_vs_plain": plain_s / burst_s,
-            "capacity_req_per_s": R / burst_s, "open_loop_rate_req_per_s": rate,
-            "open_loop_throughput": total / open_s,
-            "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
-            "served_equals_alone": bool(same)}
+            "capacity_req_per_s": R / burst_s, "plain_req_per_s": R / plain_s,
+            "open_loop": {"load": load, "rate_req_per_s": rate,
+                          "served": {"p50_ms": float(np.percentile(lat, 50)),
+                                     "p99_ms": float(np.percentile(lat, 99)),
+                                     "throughput": total / open_s, "wall_s": open_s},
+                          "plain_fifo": {"p50_ms": float(np.percentile(flat, 50)),
+                                         "p99_ms": float(np.percentile(flat, 99)),
+                                         "throughput": total / fifo_open_s,
+                                         "wall_s": fifo_open_s}},
+            "served_equals_alone": bool(same),
+            "oracle_checked": checked, "oracle_match": matched == checked}
 
 
 def main():
@@ -429,12 +589,11 @@ def main():
 
     from paper_1804_09741_amd import inputs as I
 
-    # the oracle on all host cores, before this process touches the GPU
-    cpu_par = None
+    # the oracle on the host cores, before this process touches the GPU
+    procs = _cpu_share()
+    cpu = None
     if not args.no_cpu_baseline:
-        procs = max(1, min(16, os.cpu_count() or 1, 31))
-        cpu_par = _cpu_parallel(I.workload_k6_batch().graphs, 6, procs)
-        _log("cpu oracle, %d processes: %s" % (procs, cpu_par["sample"]))
+        cpu = _cpu_legs(I, procs, args.cpu_graphs)
 
     import torch  # device buffers and the launch stream only
 
@@ -459,7 +618,6 @@ def main():
         opts["split_threshold"] = args.split
     if args.waves_per_cu:
         opts["waves_per_cu"] = args.waves_per_cu
-    tuned = None
     if args.autotune:
         tuned, tuned_ms = ctx.autotune(graphs, t6, trials=2)
         opts = {kk: v for kk, v in tuned.items() if kk != "debug_flags" and v}
@@ -469,8 +627,8 @@ def main():
     ms_per_step = 1000.0 * r["wall_s"] / args.steps
     value = subgraphs / (r["wall_s"] / args.steps)
     enum_ms = float(np.mean(r["enum_ms"]))
-    algo_bytes = BYTES_PER_SUBGRAPH * subgraphs
-    achieved = algo_bytes / (enum_ms * 1e-3) / 1e9
+    kname = _kernel_name(6, r["stats"])
+    cc6 = t6.class_codes()
     out = {
         "metric": "classified k-subgraphs/sec (k=5,6) batched vs plain; p50/p99 solve latency",
         "value": value,
@@ -486,47 +644,33 @@ def main():
         "data": "synthetic",
         "config": {"workload": w.name, "k": 6, "graphs": len(w.graphs), "n": 700, "m": 1500,
                    "subgraphs_per_step": subgraphs},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": _measured_traffic(_kernel_name(6, r["stats"])),
-                     "kernel": _kernel_name(6, r["stats"]), "kernel_ms": enum_ms,
-                     "bytes_per_subgraph": BYTES_PER_SUBGRAPH},
+        "roofline": _roofline(kname, enum_ms, subgraphs),
         "pass_ms": float(np.mean(r["pass_ms"])),
         "batch_stats": r["stats"],
         "batch_opts": opts,
         "table_build_ms": {"6": t6.build_ms},
+        "parity": {"k6_batch": _digest_check(w.name, r["hist"], cc6, w.graphs)},
     }
-    _log("batched k=6: %.3f ms/step, enum kernel %.3f ms" % (ms_per_step, enum_ms))
+    _log("batched k=6: %.3f ms/step, counting kernel %.3f ms" % (ms_per_step, enum_ms))
     if not args.no_plain:
         plain_s = _plain(ctx, graphs, t6, max(1, args.steps // 5), torch,
                          **({"method": method} if method else {}))
         _log("plain k=6: %.3f ms/pass" % (1000 * plain_s))
         out["plain"] = {"value": subgraphs / plain_s, "ms_per_step": 1000.0 * plain_s,
                         "speedup_batched": plain_s / (r["wall_s"] / args.steps)}
-
-    # CPU oracle on a bounded sample of the same workload (graph by graph)
-    if not args.no_cpu_baseline:
-        from oracle import oracle as O
-        cc = t6.class_codes()
-        ns = min(args.cpu_graphs, len(w.graphs))
-        t0 = time.perf_counter()
-        ok = True
-        counted = 0
-        for i in range(ns):
-            h = O.count(*w.graphs[i], 6)
-            counted += sum(h.values())
-            nz = np.flatnonzero(r["hist"][i])
-            ok &= h == {int(cc[j]): int(r["hist"][i][j]) for j in nz}
-        cpu_s = time.perf_counter() - t0
-        _log("cpu oracle: %d graphs in %.1f s" % (ns, cpu_s))
-        out["cpu_baseline"] = {"value": counted / cpu_s, "unit": "subgraphs/s", "cores": 1,
-                               "kind": "oracle",
-                               "sample": "graphs 0..%d of the batch (%d subgraphs), single "
-                                         "thread, %.1f s" % (ns - 1, counted, cpu_s),
-                               "matches_gpu": bool(ok)}
-        totals = cpu_par.pop("totals")
-        cpu_par["totals_match_gpu"] = totals == [int(x) for x in r["totals"]]
-        out["cpu_baseline_parallel"] = cpu_par
+    if cpu is not None:
+        out["cpu_baseline"] = _cpu_report(cpu["k6"], r["hist"], cc6, procs,
+                                          "all graphs of the k=6 batch")
+        single = cpu["single"]
+        ns = len(single["hists"])
+        ok = all(h == {int(cc6[j]): int(r["hist"][i][j]) for j in np.flatnonzero(r["hist"][i])}
+                 for i, h in enumerate(single["hists"]))
+        counted = sum(sum(h.values()) for h in single["hists"])
+        out["cpu_baseline_single_thread"] = {
+            "value": counted / single["wall_s"], "unit": "subgraphs/s", "cores": 1,
+            "kind": "oracle", "sample": "graphs 0..%d of the k=6 batch (%d subgraphs), one "
+                                        "thread, %.1f s" % (ns - 1, counted, single["wall_s"]),
+            "hists_match_gpu": bool(ok)}
     for g in graphs:
         g.free()
 
@@ -537,17 +681,32 @@ def main():
         o5 = {"split_threshold": args.k5_split} if args.k5_split else {}
         if method:
             o5["method"] = method
-        r5 = _timed_batch(ctx, M, g5, t5, max(2, args.steps // 3), 1, torch, **o5)
+        steps5 = max(2, args.steps // 3)
+        r5 = _timed_batch(ctx, M, g5, t5, steps5, 1, torch, **o5)
         s5 = int(r5["totals"].sum())
-        k5 = {"workload": w5.name, "value": s5 / (r5["wall_s"] / max(2, args.steps // 3)),
-              "subgraphs_per_step": s5, "kernel_ms": float(np.mean(r5["enum_ms"])),
+        k5_ms = float(np.mean(r5["enum_ms"]))
+        k5name = _kernel_name(5, r5["stats"])
+        # work unit of the counting from (k-2)-sets: the connected 3-sets
+        # (cores) of the batch, counted by the k = 3 path on the same graphs
+        h3, _ = ctx.count_batch(g5, ctx.table(3))
+        cores = int(h3.sum())
+        cc5 = t5.class_codes()
+        k5 = {"workload": w5.name, "value": s5 / (r5["wall_s"] / steps5),
+              "subgraphs_per_step": s5, "kernel_ms": k5_ms,
               "pass_ms": float(np.mean(r5["pass_ms"])), "table_build_ms": t5.build_ms,
-              "kernel": _kernel_name(5, r5["stats"]),
-              "traffic": _measured_traffic(_kernel_name(5, r5["stats"])),
-              "batch_stats": r5["stats"]}
+              "kernel": k5name,
+              "roofline": _roofline(k5name, k5_ms,
+                                    None if k5name.startswith("core") else s5),
+              "cores_per_launch": cores, "cores_per_s": cores / (k5_ms / 1e3),
+              "batch_stats": r5["stats"],
+              "parity": _digest_check(w5.name, r5["hist"], cc5, w5.graphs)}
+        if cpu is not None:
+            k5["cpu_baseline"] = _cpu_report(cpu["k5"], r5["hist"], cc5, procs,
+                                             "first graphs of the k=5 batch")
         if not args.no_plain:
             p5 = _plain(ctx, g5, t5, 1, torch, **({"method": method} if method else {}))
             k5["plain_value"] = s5 / p5
+            k5["speedup_batched"] = p5 / (r5["wall_s"] / steps5)
         out["k5_batch"] = k5
         _log("k=5 batch: %.3f ms/step" % k5["pass_ms"])
         for g in g5:

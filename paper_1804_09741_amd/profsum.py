@@ -62,6 +62,62 @@ def short_name(name: str) -> str:
     return s[4:] if s.startswith("mk::") else s
 
 
+# MI355X figures used by the rooflines (vendor-published unit counts and
+# clock).  Issue: every compute unit has four SIMD16 vector units -- a wave64
+# VALU instruction occupies one for four cycles, so a CU completes at most
+# one wave64 VALU instruction per cycle -- and one scalar unit that issues
+# one SALU instruction per cycle; the LDS takes one instruction per cycle.
+NUM_CUS = 256
+CLOCK_HZ = 2.4e9
+ISSUE_PEAK = NUM_CUS * CLOCK_HZ          # wave-instructions/s per pipe
+HBM_PEAK_BPS = 8.0e12
+# L2 atomics: 16 channels per XCD, 8 XCDs, one 64-bit atomic per channel and
+# cycle (an assumption of the channel design, stated as such)
+L2_ATOMIC_PEAK = 8 * 16 * CLOCK_HZ
+
+
+def derived(c: dict, kernel_s: float) -> dict:
+    """Issue, lane, wait, L2 and HBM figures of one kernel launch from its
+    per-dispatch counter means `c` (FETCH_SIZE / WRITE_SIZE already scaled to
+    bytes as `fetch_bytes` / `write_bytes`) and its duration in seconds."""
+    out = {}
+    pipes = {"VALU": "SQ_INSTS_VALU", "SALU": "SQ_INSTS_SALU", "LDS": "SQ_INSTS_LDS"}
+    for name, key in pipes.items():
+        if key in c and kernel_s > 0:
+            rate = c[key] / kernel_s
+            out[name.lower()] = {"insts_per_launch": c[key], "rate": rate,
+                                 "frac": rate / ISSUE_PEAK}
+    if c.get("SQ_ACTIVE_INST_VALU"):
+        out["lane_util"] = c.get("SQ_THREAD_CYCLES_VALU", 0.0) / (64.0 * c["SQ_ACTIVE_INST_VALU"])
+    if c.get("SQ_WAVE_CYCLES"):
+        out["wait_frac"] = c.get("SQ_WAIT_ANY", 0.0) / c["SQ_WAVE_CYCLES"]
+    if c.get("SQ_ACTIVE_INST_LDS"):
+        out["lds_conflict_frac"] = c.get("SQ_LDS_BANK_CONFLICT", 0.0) / c["SQ_ACTIVE_INST_LDS"]
+    hits, miss = c.get("TCC_HIT_sum"), c.get("TCC_MISS_sum")
+    if hits is not None and miss is not None and hits + miss > 0:
+        out["l2_hit"] = hits / (hits + miss)
+    if "TCC_ATOMIC_sum" in c and kernel_s > 0:
+        out["l2_atomics_per_launch"] = c["TCC_ATOMIC_sum"]
+        out["l2_atomic_rate"] = c["TCC_ATOMIC_sum"] / kernel_s
+        out["l2_atomic_frac"] = out["l2_atomic_rate"] / L2_ATOMIC_PEAK
+    if "fetch_bytes" in c and "write_bytes" in c and kernel_s > 0:
+        t = c["fetch_bytes"] + c["write_bytes"]
+        out["hbm_bytes_per_launch"] = t
+        out["hbm_rate"] = t / kernel_s
+        out["hbm_frac"] = t / kernel_s / HBM_PEAK_BPS
+    return out
+
+
+def issue_roofline(d: dict) -> dict:
+    """The busier of the VALU and SALU issue pipes as the binding roofline."""
+    cand = [(d[p]["frac"], p) for p in ("valu", "salu") if p in d]
+    if not cand:
+        return {}
+    frac, pipe = max(cand)
+    return {"bound": "alu", "pipe": pipe.upper(), "achieved": d[pipe]["rate"],
+            "peak": ISSUE_PEAK, "unit": "wave-instructions/s", "frac": frac}
+
+
 def _csv(path):
     with open(path, newline="") as f:
         return list(csv.DictReader(f))
@@ -148,6 +204,8 @@ def main(argv=None):
     c.add_argument("--bench-log", required=True)
     c.add_argument("--out-md", required=True)
     c.add_argument("--out-json", required=True)
+    c.add_argument("--stats-dir", default="",
+                   help="a --kernel-trace --stats run of the same command: kernel durations")
     c.add_argument("--title", default="enum_kernel hardware counters")
     c.add_argument("--command", nargs="+", required=True)
     q = sub.add_parser("pmc")
@@ -224,29 +282,43 @@ def main(argv=None):
     if "k5_batch" in bench:
         per_launch[kernel(5, bench["k5_batch"]["batch_stats"])] = (
             bench["k5_batch"]["workload"], bench["k5_batch"]["subgraphs_per_step"])
-    bps = bench["roofline"]["bytes_per_subgraph"]
+    # kernel durations: a --kernel-trace --stats run of the same command
+    # (counter passes serialise and slow the kernels), else the bench log
+    kernel_ms = {}
+    if a.stats_dir:
+        for r in _csv(os.path.join(a.stats_dir, "run_kernel_stats.csv")):
+            kernel_ms[short_name(r["Name"])] = float(r["AverageNs"]) / 1e6
+    else:
+        kernel_ms[kernel(6, bench["batch_stats"])] = bench["roofline"]["kernel_ms"]
+        if "k5_batch" in bench:
+            kernel_ms[kernel(5, bench["k5_batch"]["batch_stats"])] = bench["k5_batch"]["kernel_ms"]
     rec = {"source_sha256_16": source_hash(), "sources": list(KERNEL_SOURCES),
            "calibration": {"kernel": COPY_KERNEL + " (torch copy_ of %d MiB)" % a.copy_mib,
                            "bytes": copy_bytes, "FETCH_SIZE_KiB": cal["FETCH_SIZE"],
                            "WRITE_SIZE_KiB": cal["WRITE_SIZE"], "fetch_scale": fetch_scale,
                            "write_scale": write_scale},
+           "commands": a.command,
            "kernels": {}}
     for kern, (wl, sub_) in sorted(per_launch.items()):
         m = means[kern]
         fb = m["FETCH_SIZE"] * 1024.0 * fetch_scale
         wb = m["WRITE_SIZE"] * 1024.0 * write_scale
+        cm = dict(m)
+        cm["fetch_bytes"], cm["write_bytes"] = fb, wb
         rec["kernels"][kern] = {"workload": wl, "dispatches": counts[kern], "fetch_bytes": fb,
                                 "write_bytes": wb, "traffic_bytes": fb + wb,
                                 "subgraphs_per_launch": sub_,
-                                "algorithmic_bytes": bps * sub_}
+                                "kernel_ms": kernel_ms.get(kern),
+                                "counters": cm}
     with open(a.out_json, "w") as f:
         json.dump(rec, f, indent=1)
         f.write("\n")
 
     kerns = sorted(k for k in means if k.startswith(("enum_kernel", "core_kernel"))) + [copy_key]
     lines = ["# " + a.title, "",
-             "One rocprofv3 `--pmc` run per counter set, from /tmp with TMPDIR=/tmp; "
-             "$R is the repository root:", "", "```"] + a.command + [
+             "One rocprofv3 `--pmc` run per counter set (and one `--kernel-trace --stats` run "
+             "for the durations), from /tmp with TMPDIR=/tmp; $R is the repository root:", "",
+             "```"] + a.command + [
              "```", "",
              "Kernel sources (enum.hip, core.hip, esu.h, internal.h) sha256[:16] = `%s`." % rec["source_sha256_16"],
              "Mean per dispatch over %s." % ", ".join(
@@ -260,12 +332,30 @@ def main(argv=None):
     lines += ["", "HBM traffic per launch (FETCH_SIZE x %.4f + WRITE_SIZE x %.4f, KiB -> bytes; "
               "the factors make the %d MiB copy read and write %d MiB):" % (
                   fetch_scale, write_scale, a.copy_mib, a.copy_mib), "",
-              "| kernel | workload | read (MB) | written (MB) | algorithmic (MB) | "
-              "traffic / algorithmic |", "|---|---|---:|---:|---:|---:|"]
+              "| kernel | workload | read (MB) | written (MB) | subgraphs | bytes / subgraph |",
+              "|---|---|---:|---:|---:|---:|"]
     for kern, r in rec["kernels"].items():
-        lines.append("| %s | %s | %.1f | %.1f | %.1f | %.3f |" % (
+        lines.append("| %s | %s | %.1f | %.1f | %.4g | %.3f |" % (
             kern, r["workload"], r["fetch_bytes"] / 1e6, r["write_bytes"] / 1e6,
-            r["algorithmic_bytes"] / 1e6, r["traffic_bytes"] / r["algorithmic_bytes"]))
+            r["subgraphs_per_launch"], r["traffic_bytes"] / r["subgraphs_per_launch"]))
+    lines += ["", "Derived per launch (issue peak %.4g wave-instructions/s per pipe = %d CUs x "
+              "%.1f GHz x 1; HBM peak %.0f TB/s; L2 atomic peak %.4g/s = 128 channels x %.1f GHz):"
+              % (ISSUE_PEAK, NUM_CUS, CLOCK_HZ / 1e9, HBM_PEAK_BPS / 1e12, L2_ATOMIC_PEAK,
+                 CLOCK_HZ / 1e9), "",
+              "| kernel | ms | VALU frac | SALU frac | LDS frac | lanes active | waves waiting | "
+              "LDS bank-conflict / LDS-active | L2 hit | L2 atomics | atomic frac | HBM frac |",
+              "|---|---:|---:|---:|---:|---:|---:|---:|---:|---:|---:|---:|"]
+    for kern, r in rec["kernels"].items():
+        ms = r["kernel_ms"] or float("nan")
+        d = derived(r["counters"], ms / 1e3)
+        g = lambda key: d.get(key, float("nan"))
+        lines.append("| %s | %.3f | %.3f | %.3f | %.3f | %.3f | %.3f | %.3f | %.3f | %.4g | "
+                     "%.4f | %.4f |" % (
+                         kern, ms, d.get("valu", {}).get("frac", float("nan")),
+                         d.get("salu", {}).get("frac", float("nan")),
+                         d.get("lds", {}).get("frac", float("nan")), g("lane_util"),
+                         g("wait_frac"), g("lds_conflict_frac"), g("l2_hit"),
+                         g("l2_atomics_per_launch"), g("l2_atomic_frac"), g("hbm_frac")))
     with open(a.out_md, "w") as f:
         f.write("\n".join(lines) + "\n")
 

@@ -33,7 +33,7 @@ def test_counters_and_traffic_record(tmp_path):
                                           (3, enum6, 100.0), (4, enum6, 600.0)])
     _pass(tmp_path / "p2", "WRITE_SIZE", [(1, copy, 1024.0), (3, enum6, 50.0), (4, enum6, 150.0)])
     bench = {"config": {"workload": "w6", "subgraphs_per_step": 1000},
-             "roofline": {"bytes_per_subgraph": 20}, "batch_stats": {"method": 1}}
+             "roofline": {"kernel_ms": 2.0}, "batch_stats": {"method": 1}}
     log = tmp_path / "bench.log"
     log.write_text("[bench] noise\n" + json.dumps(bench) + "\n")
     out_md, out_json = tmp_path / "c.md", tmp_path / "t.json"
@@ -47,7 +47,8 @@ def test_counters_and_traffic_record(tmp_path):
     # mean FETCH_SIZE (200 + 600) / 2 = 400 KiB, x 2 -> 800 KiB; WRITE (50 + 150) / 2 = 100 KiB
     assert k["fetch_bytes"] == 800 * 1024 and k["write_bytes"] == 100 * 1024
     assert k["traffic_bytes"] == 900 * 1024
-    assert k["algorithmic_bytes"] == 20 * 1000
+    assert k["subgraphs_per_launch"] == 1000 and k["kernel_ms"] == 2.0
+    assert k["counters"]["fetch_bytes"] == 800 * 1024
     assert rec["source_sha256_16"] == P.source_hash()
     assert "| enum_kernel<6> | w6 |" in out_md.read_text()
 
@@ -73,3 +74,19 @@ def test_pmc_means_per_dispatch_and_unit(tmp_path):
     # VALU: (400 + 800) / 2 = 600 per dispatch, 3 per unit of 200
     assert "| SQ_INSTS_VALU | 600 | 3 |" in text
     assert "| SQ_WAVES | 64 | 0.32 |" in text
+
+
+def test_derived_rooflines():
+    """Issue, lane, wait, L2 and HBM figures from counter means."""
+    c = {"SQ_INSTS_VALU": P.ISSUE_PEAK * 1e-3 * 0.5, "SQ_INSTS_SALU": P.ISSUE_PEAK * 1e-3 * 0.25,
+         "SQ_ACTIVE_INST_VALU": 100.0, "SQ_THREAD_CYCLES_VALU": 3200.0,
+         "SQ_WAVE_CYCLES": 10.0, "SQ_WAIT_ANY": 4.0, "TCC_HIT_sum": 3.0, "TCC_MISS_sum": 1.0,
+         "TCC_ATOMIC_sum": P.L2_ATOMIC_PEAK * 1e-3 * 0.1,
+         "fetch_bytes": 4e9, "write_bytes": 4e9}
+    d = P.derived(c, 1e-3)
+    assert abs(d["valu"]["frac"] - 0.5) < 1e-12 and abs(d["salu"]["frac"] - 0.25) < 1e-12
+    assert d["lane_util"] == 0.5 and d["wait_frac"] == 0.4 and d["l2_hit"] == 0.75
+    assert abs(d["l2_atomic_frac"] - 0.1) < 1e-12
+    assert abs(d["hbm_frac"] - 1.0) < 1e-12   # 8e9 bytes in 1 ms = 8 TB/s
+    r = P.issue_roofline(d)
+    assert r["bound"] == "alu" and r["pipe"] == "VALU" and abs(r["frac"] - 0.5) < 1e-12
