@@ -338,6 +338,28 @@ int mk_batch_timing(mk_batch *b, double *pass_ms, double *enum_ms);
 
 void mk_batch_free(mk_batch *b);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+   capture, tight serving loops, harnesses that forbid hipMalloc): H_k of one
+   graph by enumeration, equal to mk_count's histogram, with every buffer of
+   the path other than the caller's -- counters, typed adjacency, bit
+   matrices, planner slots and work units -- taken from one static device
+   array of mk_static_scratch_bytes() bytes (64 MiB) that the library holds
+   on each device it runs on until the process ends.  No hipMalloc, hipFree
+   or allocating library call is made.  g: a loaded graph with n <=
+   MK_LDS_MARKS_MAX_VERTICES whose workspace fits the array (about 8 n^2/32 +
+   20 |delta| bytes plus the work units), else MK_ERANGE with a message
+   giving the size needed.  t: a built table (k = 3..6).  d_hist: device
+   array of t's num_classes uint64, overwritten with the histogram.  Runs on
+   `stream` (NULL: the context's stream) and blocks until done, then checks
+   the device-side status.  Calls through one context are serialised; calls
+   from two contexts on one device at the same time share the array and
+   race. */
+int mk_count_static(mk_ctx *ctx, const mk_graph *g, const mk_table *t, uint64_t *d_hist,
+                    void *stream);
+
+/* Size in bytes of the static device array of mk_count_static. */
+uint64_t mk_static_scratch_bytes(void);
+
 /* H_7 of ng graphs.  Section 1 counts 880,471,142 classes of 7-vertex
    digraphs, too many for a table of all 2^42 codes, so classes are reported
    by canonical code: the minimum adjacency code over the 5040 relabelings

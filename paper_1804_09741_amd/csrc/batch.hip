@@ -69,6 +69,13 @@ struct mk_batch {
 static constexpr uint64_t kDefaultSplit[8] = {0,       0,       1u << 30, 1u << 30,
                                               1u << 12, 1u << 12, 1u << 9, 1u << 12};
 
+namespace mk {
+uint64_t default_split_floor(int plan_k)
+{
+    return plan_k >= 0 && plan_k < 8 ? kDefaultSplit[plan_k] : (1u << 12);
+}
+}  // namespace mk
+
 // ----------------------------------------------------------------- context
 
 extern "C" int mk_init(int device, mk_ctx **out)
@@ -82,6 +89,9 @@ extern "C" int mk_init(int device, mk_ctx **out)
     MK_HIP(hipSetDevice(device));
     hipDeviceProp_t prop;
     MK_HIP(hipGetDeviceProperties(&prop, device));
+    // the static scratch of mk_count_static, looked up once per device
+    int src = static_scratch_init(device);
+    if (src) return src;
     mk_ctx *c = new mk_ctx();
     c->device = device;
     c->num_cus = prop.multiProcessorCount;

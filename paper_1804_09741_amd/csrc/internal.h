@@ -246,6 +246,14 @@ int launch_core_divide(unsigned long long *hist, int ng, uint32_t num_classes,
 
 void free_table(Table *t);
 
+// Default split floor (estimated subgraphs per work unit) for units planned
+// for sets of plan_k vertices.
+uint64_t default_split_floor(int plan_k);
+
+// Address of the static device scratch of mk_count_static on `device`
+// (which must be current), looked up once per device.
+int static_scratch_init(int device);
+
 // Prepared-batch hooks used by the request server.
 uint64_t batch_units(const mk_batch *b);
 uint64_t batch_device_bytes(const mk_batch *b);

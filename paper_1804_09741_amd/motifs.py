@@ -104,6 +104,8 @@ SIGNATURES = {
     "mk_table_core_mult": (ctypes.c_int, [_P, _U32, _U32, _P]),
     "mk_count": (ctypes.c_int, [_P, _P, _P, _P, ctypes.POINTER(_U64)]),
     "mk_count_batch": (ctypes.c_int, [_P, _P, _I32, _P, _P, _P]),
+    "mk_count_static": (ctypes.c_int, [_P, _P, _P, _P, _P]),
+    "mk_static_scratch_bytes": (_U64, []),
     "mk_count7": (ctypes.c_int, [_P, _P, _I32, _I64, _P, _P, _P, _P,
                                  ctypes.POINTER(ctypes.c_double)]),
     "mk_batch_create": (ctypes.c_int, [_P, _P, _I32, _P, ctypes.POINTER(BatchOpts),
@@ -307,6 +309,16 @@ def mk_count(ctx: int, g: int, t: int) -> Tuple[np.ndarray, int]:
     total = _U64()
     _check(library().mk_count(ctx, g, t, hist.ctypes.data_as(_P), ctypes.byref(total)))
     return hist, total.value
+
+
+def mk_count_static(ctx: int, g: int, t: int, d_hist: int, stream: int = 0) -> None:
+    """H_k of one graph into the device array d_hist (num_classes uint64)
+    with no allocation (the library's static device scratch).  Blocks."""
+    _check(library().mk_count_static(ctx, g, t, d_hist or None, stream or None))
+
+
+def mk_static_scratch_bytes() -> int:
+    return int(library().mk_static_scratch_bytes())
 
 
 def _handles(gs: Sequence[int]):
@@ -554,6 +566,15 @@ class Context:
 
     def count_batch(self, graphs: Sequence[Graph], table: Table):
         return mk_count_batch(self.handle, [g.handle for g in graphs], table.handle)
+
+    def count_static(self, graph: Graph, table: Table, d_hist, stream=None) -> None:
+        """H_k of one graph into d_hist (a device tensor of num_classes
+        int64/uint64, or a device address) without any allocation."""
+        ptr = d_hist.data_ptr() if hasattr(d_hist, "data_ptr") else int(d_hist)
+        sp = 0
+        if stream is not None:
+            sp = stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+        mk_count_static(self.handle, graph.handle, table.handle, ptr, sp)
 
     def count7(self, graphs: Sequence[Graph], cap: int = 1 << 16):
         """H_7: per graph (canonical codes, counts) ascending; totals; kernel ms."""
