@@ -13,6 +13,7 @@
 #include <cstring>
 
 #include "internal.h"
+#include "server_hooks.h"
 
 using namespace mk;
 
@@ -36,6 +37,7 @@ struct mk_batch {
     int4 *d_units = nullptr;
     uint32_t unit_cap = 0;
     uint32_t *d_counters = nullptr;
+    uint32_t *d_unit_begin = nullptr;    // first unit of every graph, plus the total
     unsigned long long *d_hist_own = nullptr;
     uint32_t *d_wave_scratch = nullptr;  // core method: per-workgroup arc lists
     void *d_marks = nullptr;             // MK_MARKS_GLOBAL: per-workgroup marks
@@ -168,7 +170,8 @@ static void batch_release(mk_batch *b)
     if (b->graph) (void)hipGraphDestroy(b->graph);
     void *bufs[] = {b->d_graphs, b->d_ws, b->d_slot_cnt, b->d_slot_off, b->d_slot_est,
                     b->d_slot_vi, b->d_scan_tmp,
-                    b->d_units, b->d_counters, b->d_hist_own, b->d_wave_scratch, b->d_marks};
+                    b->d_units, b->d_counters, b->d_unit_begin, b->d_hist_own, b->d_wave_scratch,
+                    b->d_marks};
     for (void *p : bufs)
         if (p) (void)hipFree(p);
 }
@@ -399,6 +402,7 @@ static int batch_create(mk_ctx *ctx, const mk_graph *const *gs, int32_t ng, int 
     BAIL_HIP(hipMalloc(&b->d_slot_vi, sizeof(uint32_t) * std::max<uint64_t>(slots, 1)));
     BAIL_HIP(hipMalloc(&b->d_scan_tmp, sizeof(uint32_t) * scan_tmp_words(slots)));
     BAIL_HIP(hipMalloc(&b->d_counters, sizeof(uint32_t) * kNumCounters));
+    BAIL_HIP(hipMalloc(&b->d_unit_begin, sizeof(uint32_t) * ((size_t)ng + 1)));
     for (hipEvent_t &e : b->ev) BAIL_HIP(hipEventCreate(&e));
 
     int per_cu = 0;
@@ -586,7 +590,7 @@ uint64_t batch_device_bytes(const mk_batch *b)
                                                  : list_ws_words(b->total_n, b->total_m);
     for (const mk_graph *g : b->graphs) words += (uint64_t)g->n + 1 + (uint64_t)g->nnz_u;
     return 4 * words + 16ull * b->total_slots + 4 * scan_tmp_words(b->total_slots) +
-           16ull * b->unit_cap + 8ull * b->ng * b->table->num_classes +
+           16ull * b->unit_cap + 8ull * b->ng * b->table->num_classes + 4ull * (b->ng + 1) +
            sizeof(DevGraph) * b->graphs.size() + 4 * kNumCounters +
            (b->d_wave_scratch ? 4ull * kParentArcCap * (uint64_t)b->grid : 0) + b->mark_bytes;
 }
@@ -616,6 +620,51 @@ int batch_enum_slice(mk_batch *b, uint32_t begin, uint32_t end, hipStream_t stre
     if (rc) return rc;
     const int grid = (int)std::min<uint64_t>((uint64_t)b->grid, end - begin);
     return batch_launch_count(b, b->d_hist_own, end, grid, stream);
+}
+
+// First work unit of every graph of a batch after mk_batch_create (its
+// sizing plan), plus the total, into *out (ng + 1 values).  Blocks.
+int batch_unit_begins(mk_batch *b, std::vector<uint32_t> *out)
+{
+    std::lock_guard<std::recursive_mutex> lock(b->ctx->mu);
+    MK_HIP(hipSetDevice(b->ctx->device));
+    out->assign((size_t)b->ng + 1, 0u);
+    if (b->ng == 0) return MK_OK;
+    int rc = launch_unit_begins(b->d_graphs, b->ng, b->d_slot_off, b->total_slots, b->d_counters,
+                                b->d_unit_begin, b->ctx->stream);
+    if (rc) return rc;
+    MK_HIP(hipMemcpyAsync(out->data(), b->d_unit_begin, sizeof(uint32_t) * out->size(),
+                          hipMemcpyDeviceToHost, b->ctx->stream));
+    MK_HIP(hipStreamSynchronize(b->ctx->stream));
+    if ((*out)[b->ng] != b->units)
+        return fail(MK_EDEVICE, "batch_unit_begins: %u units, the plan made %llu", (*out)[b->ng],
+                    (unsigned long long)b->units);
+    return MK_OK;
+}
+
+// Copy graph gi's histogram of a prepared batch whose units of that graph
+// are known to be done (the event of the slice that ended them completed),
+// finishing it first (the core method's division), on `copy_stream`; check
+// the device-side counters and wait only for that copy.
+int batch_collect_graph(mk_batch *b, int gi, uint64_t *hist, hipStream_t copy_stream)
+{
+    MK_HIP(hipSetDevice(b->ctx->device));
+    if (gi < 0 || gi >= b->ng) return fail(MK_EINVAL, "batch_collect_graph: graph %d of %d", gi, b->ng);
+    const size_t nc = b->table->num_classes;
+    unsigned long long *row = b->d_hist_own + (size_t)gi * nc;
+    if (b->method == MK_METHOD_CORES) {
+        int rc = launch_core_divide(row, 1, (uint32_t)nc, b->table->d_core_mult, b->d_counters,
+                                    copy_stream);
+        if (rc) return rc;
+    }
+    uint32_t cnt[kNumCounters];
+    MK_HIP(hipMemcpyAsync(cnt, b->d_counters, sizeof(cnt), hipMemcpyDeviceToHost, copy_stream));
+    MK_HIP(hipMemcpyAsync(hist, row, sizeof(uint64_t) * nc, hipMemcpyDeviceToHost, copy_stream));
+    MK_HIP(hipStreamSynchronize(copy_stream));
+    if (cnt[kErrors] != 0 || cnt[kAdjOverflow] != 0)
+        return fail(MK_EDEVICE, "device-side check failed (%u lookup/plan errors, %u adjacency overflows)",
+                    cnt[kErrors], cnt[kAdjOverflow]);
+    return MK_OK;
 }
 
 // Copy the histograms of a prepared batch whose last slice is known to be

@@ -17,6 +17,7 @@
 // the units of every slot, a scan gives offsets, pass two writes the units.
 // The order is graph by graph, root by root.
 #include "internal.h"
+#include "server_hooks.h"
 
 namespace mk {
 
@@ -275,6 +276,34 @@ static int plan_k(const DevGraph *d_graphs, int ng, int64_t max_nnz, uint32_t to
     hipLaunchKernelGGL((plan_kernel<K, kEmit>), grid, dim3(kPlanThreads), 0, stream, d_graphs,
                        slot_cnt, slot_off, slot_est, slot_vi, units, unit_cap, threshold, waves,
                        counters);
+    MK_HIP(hipGetLastError());
+    return MK_OK;
+}
+
+// First work unit of every graph of a planned batch (the exclusive scan of
+// the unit counts at the graph's first slot), and the total at out[ng].
+// Units are emitted graph by graph, so graph gi owns [out[gi], out[gi+1]).
+__global__ void unit_begins_kernel(const DevGraph *graphs, int ng, const uint32_t *slot_off,
+                                   uint32_t total_slots, const uint32_t *counters, uint32_t *out)
+{
+    const int gi = blockIdx.x * blockDim.x + threadIdx.x;
+    if (gi > ng) return;
+    const uint32_t total = counters[kNumUnits];
+    if (gi == ng) {
+        out[gi] = total;
+        return;
+    }
+    const uint32_t slot = graphs[gi].slot_base;
+    out[gi] = slot < total_slots ? slot_off[slot] : total;
+}
+
+int launch_unit_begins(const DevGraph *d_graphs, int ng, const uint32_t *slot_off,
+                       uint32_t total_slots, const uint32_t *counters, uint32_t *out,
+                       hipStream_t stream)
+{
+    const int n = ng + 1;
+    hipLaunchKernelGGL(unit_begins_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream,
+                       d_graphs, ng, slot_off, total_slots, counters, out);
     MK_HIP(hipGetLastError());
     return MK_OK;
 }

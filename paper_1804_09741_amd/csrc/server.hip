@@ -6,22 +6,29 @@
 // resident and runs the requests through the same kernels as mk_count:
 //
 //   submit   -> FIFO queue
-//   admit    -> while the head fits the HBM budget and a slot is free: plan it
-//               (typed adjacency + work units) on one of the server's streams
-//   slices   -> every admitted request has one slice of at most tick_units
-//               of its work units in flight on its stream; a HIP event marks
-//               the slice's end, and the server thread (polling the events)
-//               launches the request's next slice as soon as it is done
-//   complete -> a request whose units are all done has its histogram copied
-//               out on a separate copy stream, its memory released, and its
-//               waiter woken
+//   admit    -> while the head fits the HBM budget and a slot is free; the
+//               requests admitted together are grouped by k and by size
+//               class of n (ceil log2), and each group becomes one batch (one typed-adjacency and plan pass, one
+//               persistent launch per slice for all its graphs), its graphs
+//               ordered by size so that the small ones come first in the
+//               unit queue
+//   slices   -> every group keeps two slices of its work units queued on
+//               its stream (the first of tick_units, each next one twice
+//               the last); a HIP event marks each slice's end, and the
+//               server thread (polling the events) queues the group's next
+//               slice as soon as one ends
+//   complete -> after each slice, every request whose units all lie in the
+//               finished slices has its histogram finished and copied out
+//               on a separate copy stream, and its waiter is woken; the
+//               group's memory is released when its last request is done
 //
-// A request that arrives while others run is admitted as soon as a slot and
-// the memory budget allow, and its slices then share the device with
-// everyone else's; a long request holds a stream for at most one slice at a
-// time.  There is no global barrier between slices.  Each request has its
-// own histogram and its slices cover its units exactly once, so its result
-// is the same as when it runs alone.
+// Requests that arrive while others run form new groups as soon as a slot
+// and the memory budget allow; their slices share the device with the
+// running groups' (the streams run concurrently), so small late requests do
+// not wait for a long one to end.  Each request has its own histogram rows
+// and the slices cover every unit exactly once, so its result is the same
+// as when it runs alone.
+#include <algorithm>
 #include <chrono>
 #include <condition_variable>
 #include <deque>
@@ -29,34 +36,58 @@
 #include <unordered_map>
 
 #include "internal.h"
+#include "server_hooks.h"
 
 using namespace mk;
 
 namespace {
 
-constexpr int kServerStreams = 8;
+constexpr int kServerStreams = 4;  // the hardware queues a process gets
 constexpr uint64_t kDefaultBudget = 8ull << 30;
 constexpr int kDefaultSlots = 64;
 constexpr int kDefaultTickUnits = 8192;
+// slices of a group queued on its stream at once: the next one is already
+// there when one ends, so the host's polling leaves no gap
+constexpr int kInFlight = 2;
 
 enum class State { Queued, Active, Done, Failed };
+
+struct Group;
 
 struct Request {
     uint64_t ticket = 0;
     const mk_graph *g = nullptr;
     int k = 0;
     uint64_t est_bytes = 0;
-    uint64_t bytes = 0;
     State state = State::Queued;
     int status = MK_OK;
     std::string error;
-    mk_batch *batch = nullptr;
-    uint64_t units = 0, cursor = 0;
-    int stream = 0;
-    hipEvent_t ev = nullptr;  // end of the work last launched for the request
-    bool inflight = false;
+    Group *group = nullptr;
+    int gi = 0;  // graph index in its group's batch
     std::vector<uint64_t> hist;
     mk_request_times times{};
+};
+
+// requests of one k admitted together, counted as one batch
+struct Group {
+    int k = 0;
+    mk_batch *batch = nullptr;
+    std::vector<Request *> reqs;       // in graph order
+    std::vector<uint32_t> unit_begin;  // per graph, plus the total
+    uint64_t units = 0;
+    uint64_t launched = 0;             // units of the slices launched so far
+    uint64_t done = 0;                 // units of the slices known to be done
+    uint64_t slice = 0;                // size of the next slice
+    size_t next = 0;                   // first request not yet collected
+    int stream = 0;
+    // slices in flight, oldest first: their end events and end units
+    hipEvent_t ev[kInFlight] = {};
+    uint64_t ev_end[kInFlight] = {};
+    int head = 0, inflight = 0;
+    bool prepared = false;             // the planning pass is known to be done
+    uint64_t bytes = 0;                // device bytes charged to the budget
+    int status = MK_OK;
+    std::string error;
 };
 
 }  // namespace
@@ -68,15 +99,16 @@ struct mk_server {
     std::mutex mu;
     std::condition_variable cv_work, cv_done;
     std::deque<Request *> queue;
-    std::vector<Request *> active;
+    std::vector<Group *> groups;
     std::unordered_map<uint64_t, Request *> all;
     uint64_t next_ticket = 1;
     uint64_t used_bytes = 0;
+    size_t active_requests = 0;
     bool stopping = false;
     int next_stream = 0;
     hipStream_t streams[kServerStreams] = {};
     hipStream_t copy_stream = nullptr;
-    // finished requests' batches, freed only when nothing runs (a free can
+    // finished groups' batches, freed only when nothing runs (a free can
     // wait for every kernel in flight); their bytes stay in used_bytes
     std::vector<std::pair<mk_batch *, uint64_t>> graveyard;
     std::chrono::steady_clock::time_point t0;
@@ -88,28 +120,39 @@ struct mk_server {
     }
 };
 
-static void finish(mk_server *s, Request *r, State st, int status, const char *why)
+// vertex-count class of a graph: ceil(log2(n)), at least 10 (n <= 1024)
+static int size_class(int n)
+{
+    int c = 10;
+    while (c < 31 && (1 << c) < n) ++c;
+    return c;
+}
+
+// a request leaves the server (its waiter is woken)
+static void finish_request(mk_server *s, Request *r, State st, int status, const char *why)
 {
     std::lock_guard<std::mutex> lock(s->mu);
-    if (r->batch) {
-        s->graveyard.emplace_back(r->batch, r->bytes);
-        r->batch = nullptr;
-    } else {
-        s->used_bytes -= std::min(s->used_bytes, r->bytes);
-    }
-    if (r->ev) {
-        (void)hipEventDestroy(r->ev);
-        r->ev = nullptr;
-    }
     r->state = st;
     r->status = status;
     if (why) r->error = why;
     r->times.done_us = s->now_us();
+    s->active_requests -= std::min<size_t>(s->active_requests, 1);
     s->cv_done.notify_all();
 }
 
-// free the finished batches (call when no request is in flight, or when
-// their memory is needed)
+// the group's batch goes to the graveyard (freed when nothing runs)
+static void retire_group(mk_server *s, Group *gp)
+{
+    for (hipEvent_t e : gp->ev)
+        if (e) (void)hipEventDestroy(e);
+    std::lock_guard<std::mutex> lock(s->mu);
+    if (gp->batch) s->graveyard.emplace_back(gp->batch, gp->bytes);
+    else s->used_bytes -= std::min(s->used_bytes, gp->bytes);
+    delete gp;
+}
+
+// free the finished batches (call when no group is in flight, or when their
+// memory is needed)
 static void bury(mk_server *s)
 {
     std::vector<std::pair<mk_batch *, uint64_t>> g;
@@ -126,34 +169,79 @@ static void bury(mk_server *s)
     s->used_bytes -= std::min(s->used_bytes, freed);
 }
 
-// plan an admitted request on its stream; false if it failed
-static bool start_request(mk_server *s, Request *r)
+// fail every request of a group that is not collected yet
+static void fail_group(mk_server *s, Group *gp, int status, const char *why)
 {
+    for (size_t i = gp->next; i < gp->reqs.size(); ++i)
+        finish_request(s, gp->reqs[i], State::Failed, status, why);
+    gp->next = gp->reqs.size();
+}
+
+// one batch for the admitted requests of one k, planned on the group's stream
+static Group *start_group(mk_server *s, int k, std::vector<Request *> reqs, uint64_t est_bytes)
+{
+    // small graphs first: their units come first in the queue, so they are
+    // done after the first slices
+    std::stable_sort(reqs.begin(), reqs.end(), [](const Request *a, const Request *b) {
+        return a->g->nnz_u < b->g->nnz_u;
+    });
+    Group *gp = new Group();
+    gp->k = k;
+    gp->reqs = reqs;
+    gp->bytes = est_bytes;
+    gp->stream = s->next_stream++ % kServerStreams;
+    for (size_t i = 0; i < reqs.size(); ++i) {
+        reqs[i]->group = gp;
+        reqs[i]->gi = (int)i;
+    }
     mk_table *t = nullptr;
-    int rc = mk_table_build(s->ctx, r->k, &t);
+    int rc = mk_table_build(s->ctx, k, &t);
+    std::vector<const mk_graph *> gs;
+    for (Request *r : reqs) gs.push_back(r->g);
     if (rc == MK_OK) {
         mk_batch_opts o{};
         o.use_graph = -1;
-        rc = mk_batch_create(s->ctx, &r->g, 1, t, &o, &r->batch);
+        rc = mk_batch_create(s->ctx, gs.data(), (int32_t)gs.size(), t, &o, &gp->batch);
     }
-    if (rc == MK_OK) rc = batch_prepare(r->batch, s->streams[r->stream]);
-    if (rc == MK_OK) {
-        hipError_t e = hipEventCreateWithFlags(&r->ev, hipEventDisableTiming);
-        if (e == hipSuccess) e = hipEventRecord(r->ev, s->streams[r->stream]);
+    if (rc == MK_OK) rc = batch_unit_begins(gp->batch, &gp->unit_begin);
+    if (rc == MK_OK) rc = batch_prepare(gp->batch, s->streams[gp->stream]);
+    for (int i = 0; i < kInFlight && rc == MK_OK; ++i) {
+        hipError_t e = hipEventCreateWithFlags(&gp->ev[i], hipEventDisableTiming);
         if (e != hipSuccess) rc = fail(MK_EDEVICE, "server event: %s", hipGetErrorString(e));
-        r->inflight = true;
     }
-    if (rc != MK_OK) {
-        finish(s, r, State::Failed, rc, mk_last_error());
-        return false;
+    if (rc == MK_OK) {
+        // the planning pass counts as a slice of no units: requests are
+        // collected only after it (the histograms are cleared there)
+        if (hipEventRecord(gp->ev[0], s->streams[gp->stream]) != hipSuccess)
+            rc = fail(MK_EDEVICE, "server event record failed");
+        gp->ev_end[0] = 0;
+        gp->inflight = 1;
     }
-    r->units = batch_units(r->batch);
-    r->hist.assign(t->num_classes, 0);
-    std::lock_guard<std::mutex> lock(s->mu);
-    const uint64_t actual = batch_device_bytes(r->batch);
-    s->used_bytes = s->used_bytes - std::min(s->used_bytes, r->bytes) + actual;
-    r->bytes = actual;
-    return true;
+    if (rc == MK_OK) {
+        gp->units = gp->unit_begin.back();
+        for (Request *r : reqs) r->hist.assign(t->num_classes, 0);
+        std::lock_guard<std::mutex> lock(s->mu);
+        const uint64_t actual = batch_device_bytes(gp->batch);
+        s->used_bytes = s->used_bytes - std::min(s->used_bytes, gp->bytes) + actual;
+        gp->bytes = actual;
+    } else {
+        gp->status = rc;
+        gp->error = mk_last_error();
+    }
+    return gp;
+}
+
+// collect the requests whose units all lie in finished slices
+static void collect_done(mk_server *s, Group *gp)
+{
+    while (gp->prepared && gp->next < gp->reqs.size() &&
+           gp->unit_begin[gp->next + 1] <= gp->done) {
+        Request *r = gp->reqs[gp->next];
+        int rc = batch_collect_graph(gp->batch, r->gi, r->hist.data(), s->copy_stream);
+        if (rc == MK_OK) finish_request(s, r, State::Done, MK_OK, nullptr);
+        else finish_request(s, r, State::Failed, rc, mk_last_error());
+        ++gp->next;
+    }
 }
 
 static void server_loop(mk_server *s)
@@ -168,82 +256,115 @@ static void server_loop(mk_server *s)
             std::lock_guard<std::mutex> lock(s->mu);
             const bool blocked = !s->queue.empty() &&
                                  s->used_bytes + s->queue.front()->est_bytes > budget;
-            need_bury = !s->graveyard.empty() && (s->active.empty() || blocked);
+            need_bury = !s->graveyard.empty() && (s->groups.empty() || blocked);
         }
         if (need_bury) bury(s);
+        // admit: FIFO while a slot is free and the head fits the budget
         std::vector<Request *> admitted;
         {
             std::unique_lock<std::mutex> lock(s->mu);
             auto can_admit = [&] {
-                return !s->queue.empty() && s->active.size() + admitted.size() < slots &&
+                return !s->queue.empty() && s->active_requests < slots &&
                        s->used_bytes + s->queue.front()->est_bytes <= budget;
             };
-            if (s->active.empty() && s->graveyard.empty())
+            if (s->groups.empty() && s->graveyard.empty())
                 s->cv_work.wait(lock, [&] { return s->stopping || can_admit(); });
-            if (s->stopping && s->queue.empty() && s->active.empty() && s->graveyard.empty())
+            if (s->stopping && s->queue.empty() && s->groups.empty() && s->graveyard.empty())
                 break;
             while (can_admit()) {
                 Request *r = s->queue.front();
                 s->queue.pop_front();
                 r->state = State::Active;
                 r->times.admit_us = s->now_us();
-                r->bytes = r->est_bytes;
                 s->used_bytes += r->est_bytes;
-                r->stream = s->next_stream++ % kServerStreams;
+                ++s->active_requests;
                 admitted.push_back(r);
             }
         }
-        for (Request *r : admitted)
-            if (start_request(s, r)) s->active.push_back(r);
-
         bool progress = !admitted.empty();
-        // finished slices
-        for (Request *r : s->active) {
-            if (!r->inflight) continue;
-            const hipError_t q = hipEventQuery(r->ev);
-            if (q == hipSuccess) {
-                r->inflight = false;
-                progress = true;
-            } else if (q != hipErrorNotReady) {
-                r->status = fail(MK_EDEVICE, "request %llu: %s", (unsigned long long)r->ticket,
-                                 hipGetErrorString(q));
-                r->error = mk_last_error();
-                r->inflight = false;
-                r->cursor = r->units;
+        // groups: one per k and vertex-count class (a batch sizes every
+        // wave's LDS marks for its largest graph, so graphs of very
+        // different n are not mixed: the small ones would run at the large
+        // one's occupancy)
+        std::vector<std::pair<int, std::vector<Request *>>> parts;
+        for (Request *r : admitted) {
+            const int key = r->k * 64 + size_class(r->g->n);
+            auto it = std::find_if(parts.begin(), parts.end(),
+                                   [key](const auto &p) { return p.first == key; });
+            if (it == parts.end()) {
+                parts.emplace_back(key, std::vector<Request *>{});
+                it = parts.end() - 1;
+            }
+            it->second.push_back(r);
+        }
+        for (auto &part : parts) {
+            uint64_t bytes = 0;
+            for (Request *r : part.second) bytes += r->est_bytes;
+            Group *gp = start_group(s, part.first / 64, part.second, bytes);
+            if (gp->status != MK_OK) {
+                fail_group(s, gp, gp->status, gp->error.c_str());
+                retire_group(s, gp);
+            } else {
+                s->groups.push_back(gp);
             }
         }
-        // next slices, and completions
-        std::vector<Request *> still;
-        for (Request *r : s->active) {
-            if (r->inflight) {
-                still.push_back(r);
+        // finished slices (oldest first) and the requests they complete
+        for (Group *gp : s->groups) {
+            while (gp->inflight > 0 && gp->status == MK_OK) {
+                const hipError_t q = hipEventQuery(gp->ev[gp->head]);
+                if (q == hipErrorNotReady) break;
+                if (q != hipSuccess) {
+                    gp->status = fail(MK_EDEVICE, "server group: %s", hipGetErrorString(q));
+                    gp->error = mk_last_error();
+                    break;
+                }
+                gp->done = gp->ev_end[gp->head];
+                gp->prepared = true;
+                gp->head = (gp->head + 1) % kInFlight;
+                --gp->inflight;
+                progress = true;
+            }
+            if (gp->status == MK_OK) collect_done(s, gp);
+        }
+        // next slices: each group keeps kInFlight queued on its stream; the
+        // first covers tick units and every next one twice the last (the
+        // small graphs first in the queue finish early, the rest in few
+        // launches)
+        std::vector<Group *> still;
+        for (Group *gp : s->groups) {
+            while (gp->status == MK_OK && gp->inflight < kInFlight && gp->launched < gp->units) {
+                if (gp->slice == 0) gp->slice = tick;
+                const uint64_t end = std::min(gp->units, gp->launched + gp->slice);
+                gp->slice *= 2;
+                hipStream_t st = s->streams[gp->stream];
+                const int slot = (gp->head + gp->inflight) % kInFlight;
+                int rc = batch_enum_slice(gp->batch, (uint32_t)gp->launched, (uint32_t)end, st);
+                if (rc == MK_OK && hipEventRecord(gp->ev[slot], st) != hipSuccess)
+                    rc = fail(MK_EDEVICE, "server event record failed");
+                if (rc != MK_OK) {
+                    gp->status = rc;
+                    gp->error = mk_last_error();
+                    break;
+                }
+                gp->ev_end[slot] = end;
+                gp->launched = end;
+                ++gp->inflight;
+                progress = true;
+            }
+            if (gp->status == MK_OK && (gp->inflight > 0 || gp->next < gp->reqs.size())) {
+                still.push_back(gp);
                 continue;
             }
-            if (r->cursor < r->units && r->status == MK_OK) {
-                const uint64_t end = std::min(r->units, r->cursor + tick);
-                hipStream_t st = s->streams[r->stream];
-                int rc = batch_enum_slice(r->batch, (uint32_t)r->cursor, (uint32_t)end, st);
-                if (rc == MK_OK && hipEventRecord(r->ev, st) != hipSuccess)
-                    rc = fail(MK_EDEVICE, "server event record failed");
-                if (rc == MK_OK) {
-                    r->cursor = end;
-                    r->inflight = true;
-                    progress = true;
-                    still.push_back(r);
-                    continue;
-                }
-                // a failed launch ends the request now (reported below)
-                r->status = rc;
-                r->error = mk_last_error();
-                r->cursor = r->units;
+            if (gp->status != MK_OK) {
+                // wait for its slices before the batch can go
+                for (int i = 0; i < gp->inflight; ++i)
+                    (void)hipEventSynchronize(gp->ev[(gp->head + i) % kInFlight]);
+                fail_group(s, gp, gp->status, gp->error.c_str());
             }
-            int rc = r->status;
-            if (rc == MK_OK) rc = batch_collect(r->batch, r->hist.data(), s->copy_stream);
-            if (rc == MK_OK) finish(s, r, State::Done, MK_OK, nullptr);
-            else finish(s, r, State::Failed, rc, r->error.empty() ? mk_last_error() : r->error.c_str());
+            retire_group(s, gp);
             progress = true;
         }
-        s->active.swap(still);
+        s->groups.swap(still);
         if (!progress) std::this_thread::sleep_for(std::chrono::microseconds(20));
     }
 }
@@ -343,11 +464,7 @@ extern "C" int mk_server_stop(mk_server *s)
     }
     if (s->thread.joinable()) s->thread.join();
     bury(s);
-    for (auto &kv : s->all) {
-        if (kv.second->batch) mk_batch_free(kv.second->batch);
-        if (kv.second->ev) (void)hipEventDestroy(kv.second->ev);
-        delete kv.second;
-    }
+    for (auto &kv : s->all) delete kv.second;
     (void)hipSetDevice(s->ctx->device);
     for (hipStream_t st : s->streams)
         if (st) (void)hipStreamDestroy(st);

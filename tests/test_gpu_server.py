@@ -50,6 +50,33 @@ def test_served_equals_alone(ctx):
         g.free()
 
 
+def test_groups_across_sizes_and_empty(ctx):
+    """Requests admitted together are grouped by k and size class of n;
+    every one equals its count alone, including graphs with no k-subgraph
+    (a group with no work units) and one class per group."""
+    rng = np.random.default_rng(9200)
+    specs = [(4, I.chung_lu_digraph(n, 3 * n, 2.3, 40, 0.1, rng)) for n in (90, 700, 1500, 3000)]
+    specs += [(4, I.empty_graph(2)), (4, I.empty_graph(50)), (5, I.directed_path(4)),
+              (3, I.chung_lu_digraph(2500, 6000, 2.2, 60, 0.2, rng)),
+              (3, I.chung_lu_digraph(60, 150, 2.2, 20, 0.2, rng))]
+    graphs = [ctx.load_graph(*g) for _, g in specs]
+    try:
+        alone = [ctx.count(g, ctx.table(k))[0] for (k, _), g in zip(specs, graphs)]
+        srv = ctx.server(tick_units=32)
+        try:
+            tickets = [srv.submit(g, k) for (k, _), g in zip(specs, graphs)]
+            res = [srv.wait(t, k)[0] for t, (k, _) in zip(tickets, specs)]
+        finally:
+            srv.stop()
+        for h, a in zip(res, alone):
+            assert np.array_equal(h, a)
+        assert not res[4].any() and not res[5].any() and not res[6].any()
+        assert_hist_equals_oracle(res[0], ctx.table(4).class_codes(), *specs[0][1], 4)
+    finally:
+        for g in graphs:
+            g.free()
+
+
 def test_served_graph_past_lds_limit(ctx):
     """A request whose graph is too large for LDS marks runs with marks in
     device memory inside the server too, beside a small one."""
