@@ -618,10 +618,12 @@ def main():
         opts["split_threshold"] = args.split
     if args.waves_per_cu:
         opts["waves_per_cu"] = args.waves_per_cu
+    autotune = None
     if args.autotune:
-        tuned, tuned_ms = ctx.autotune(graphs, t6, trials=2)
-        opts = {kk: v for kk, v in tuned.items() if kk != "debug_flags" and v}
-        _log("autotune: %s (pass %.3f ms)" % (opts, tuned_ms))
+        tuned, tuned_ms, default_ms = ctx.autotune(graphs, t6, trials=3)
+        opts = {kk: v for kk, v in tuned.items() if v}
+        autotune = {"opts": opts, "tuned_pass_ms": tuned_ms, "default_pass_ms": default_ms}
+        _log("autotune: %s (pass %.3f ms; defaults %.3f ms)" % (opts, tuned_ms, default_ms))
     r = _timed_batch(ctx, M, graphs, t6, args.steps, args.warmup, torch, **opts)
     subgraphs = int(r["totals"].sum())
     ms_per_step = 1000.0 * r["wall_s"] / args.steps
@@ -648,10 +650,20 @@ def main():
         "pass_ms": float(np.mean(r["pass_ms"])),
         "batch_stats": r["stats"],
         "batch_opts": opts,
+        "autotune": autotune,
         "table_build_ms": {"6": t6.build_ms},
         "parity": {"k6_batch": _digest_check(w.name, r["hist"], cc6, w.graphs)},
     }
     _log("batched k=6: %.3f ms/step, counting kernel %.3f ms" % (ms_per_step, enum_ms))
+    # the same pass captured whole (preparation, counting kernel, finish) as
+    # one hipGraph: replays timed by the wall clock and by events around them
+    rg = _timed_batch(ctx, M, graphs, t6, args.steps, args.warmup, torch,
+                      **dict(opts, use_graph=2))
+    out["whole_graph"] = {"ms_per_step": 1000.0 * rg["wall_s"] / args.steps,
+                          "pass_ms": float(np.mean(rg["pass_ms"])),
+                          "value": subgraphs / (rg["wall_s"] / args.steps),
+                          "hists_equal": bool(np.array_equal(rg["hist"], r["hist"]))}
+    _log("batched k=6, whole pass as one graph: %.3f ms/step" % out["whole_graph"]["ms_per_step"])
     if not args.no_plain:
         plain_s = _plain(ctx, graphs, t6, max(1, args.steps // 5), torch,
                          **({"method": method} if method else {}))

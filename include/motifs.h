@@ -227,21 +227,27 @@ int mk_count_batch(mk_ctx *ctx, const mk_graph *const *gs, int32_t ng,
 typedef struct mk_batch_opts {
     uint64_t split_threshold; /* floor of the estimated subgraphs per work
                                  unit (the planner raises it so that the
-                                 whole batch makes ~16 units per wave, ~64
-                                 on sorted-list adjacency below k = 7);
-                                 0: 512 for k = 6 by enumeration, else 4096
-                                 (nodes planned for sets of 3 or fewer
-                                 vertices are not split) */
+                                 whole batch makes about units_per_wave
+                                 units per wave); 0: 512 for k = 6 by
+                                 enumeration, 1024 for k = 5 by counting
+                                 from (k-2)-sets and k = 4 by enumeration,
+                                 else 4096 (nodes planned for sets of 3 or
+                                 fewer vertices are not split) */
     int32_t waves_per_cu;     /* resident enumeration waves per compute unit */
-    int32_t use_graph;        /* 1: replay a captured hipGraph (default),
-                                 -1: plain stream launches */
+    int32_t use_graph;        /* 1 (default): the preparation replayed as a
+                                 captured hipGraph, the counting kernel
+                                 launched between its timing events;
+                                 2: the whole pass (preparation, counting
+                                 kernel, finish) as one captured hipGraph,
+                                 mk_batch_timing then gives the pass time
+                                 only; -1: plain stream launches */
     int32_t units_per_grab;   /* work units a wave takes per queue atomic
-                                 (0: about 1/16 of a wave's share, <= 16) */
-    int32_t debug_flags;      /* tests only: 1 = every code straight to the
-                                 histogram, 2 = flush the per-wave count hash
-                                 after every insert, 4 = MK_METHOD_CORES
-                                 rescans every list instead of sharing a
-                                 parent's arc pairs; results are the same */
+                                 (0: about 1/32 of a wave's share, <= 16) */
+    int32_t units_per_wave;   /* work-unit granularity: the planner splits
+                                 nodes until the batch's estimated work
+                                 makes about this many units per counting
+                                 wave (0: 32, 128 for graphs counted on
+                                 sorted lists, 16 for k = 7; 1..4096) */
     int32_t method;           /* MK_METHOD_*: how H_k is counted (0: the
                                  library's choice); results are the same */
     int32_t adjacency;        /* MK_ADJ_*: how arcs between extension
@@ -307,7 +313,8 @@ int mk_batch_create(mk_ctx *ctx, const mk_graph *const *gs, int32_t ng,
    lookups and histograms.  Asynchronous.  d_hist: device array of
    ng * num_classes uint64 that receives the histograms (overwritten), or
    NULL to use the batch's own buffer.  The first run on a given d_hist
-   captures the sequence as a hipGraph; later runs replay it. */
+   captures the sequence as a hipGraph (see mk_batch_opts.use_graph); later
+   runs replay it. */
 int mk_batch_run(mk_batch *b, uint64_t *d_hist, void *stream);
 
 /* Wait for the batch's last run, check its device-side status and copy the
@@ -332,8 +339,9 @@ typedef struct mk_batch_stats {
 int mk_batch_stats_get(const mk_batch *b, mk_batch_stats *out);
 
 /* GPU time of the batch's last run, from HIP events recorded on the run's
-   stream: the whole pass and the enumeration kernel alone (milliseconds).
-   Waits for the run to finish. */
+   stream: the whole pass and the counting kernel alone (milliseconds; -1
+   for the kernel when the whole pass is one graph, use_graph = 2).  Waits
+   for the run to finish. */
 int mk_batch_timing(mk_batch *b, double *pass_ms, double *enum_ms);
 
 void mk_batch_free(mk_batch *b);
@@ -390,15 +398,17 @@ int mk_k7_cache_info(mk_ctx *ctx, uint64_t *slots, uint64_t *used);
 int mk_k7_cache_clear(mk_ctx *ctx);
 
 /* Autotuner: time the batch path on these graphs (best of `trials` runs
-   each) under candidate settings -- counting method, split-threshold floor,
-   units per queue grab, waves per CU, tried one knob at a time from the
-   library defaults -- and return the fastest in *best and its whole-pass
-   time (preparation, counting and, for MK_METHOD_CORES, the division) in
-   *best_ms (may be NULL).  Every candidate's histograms must equal the
-   defaults' (MK_EDEVICE otherwise).  Allocates and frees its own batches;
-   takes as long as about a dozen runs of the batch. */
+   each) under candidate settings -- counting method, arc tests, work-unit
+   granularity (split floors 128 .. 2^18 estimated subgraphs per unit and
+   4 .. 128 units per wave, two passes), units per queue grab, waves per CU,
+   tried one knob at a time from the library defaults -- and return the
+   fastest in *best, its whole-pass time (preparation, counting and, for
+   MK_METHOD_CORES, the division) in *best_ms and the defaults' in
+   *default_ms (either may be NULL).  Every candidate's histograms must
+   equal the defaults' (MK_EDEVICE otherwise).  Allocates and frees its own
+   batches; takes as long as about 35 runs of the batch. */
 int mk_autotune(mk_ctx *ctx, const mk_graph *const *gs, int32_t ng, const mk_table *t,
-                int32_t trials, mk_batch_opts *best, double *best_ms);
+                int32_t trials, mk_batch_opts *best, double *best_ms, double *default_ms);
 
 /* ----------------------------------------------------------------- server */
 

@@ -13,6 +13,7 @@
 #include <cstring>
 
 #include "internal.h"
+#include "motifs_testing.h"
 #include "server_hooks.h"
 
 using namespace mk;
@@ -24,6 +25,7 @@ struct mk_batch {
     int ng = 0;
     std::vector<const mk_graph *> graphs;
     mk_batch_opts opts{};
+    int32_t debug_flags = 0;  // test hooks (mk_batch_debug)
 
     DevGraph *d_graphs = nullptr;
     uint32_t *d_ws = nullptr;  // bit matrices (or list-build arrays), urow, uadj
@@ -61,6 +63,7 @@ struct mk_batch {
     hipEvent_t ev[4] = {};
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    bool graph_whole = false;   // exec holds the whole pass (else the preparation)
     unsigned long long *exec_hist = nullptr;
     hipStream_t last_stream = nullptr;
 };
@@ -69,7 +72,7 @@ struct mk_batch {
 // adaptive threshold); 512 at k = 6 lets the hubs of a batch of small graphs
 // split (12% off the k = 6 kernel on 31 power-law graphs of 700 vertices)
 static constexpr uint64_t kDefaultSplit[8] = {0,       0,       1u << 30, 1u << 30,
-                                              1u << 12, 1u << 12, 1u << 9, 1u << 12};
+                                              1u << 10, 1u << 12, 1u << 9, 1u << 12};
 
 namespace mk {
 uint64_t default_split_floor(int plan_k)
@@ -181,7 +184,7 @@ static EnumConfig enum_config(const mk_batch *b)
     EnumConfig c;
     c.max_n = b->max_n;
     c.seg_cap = b->seg_cap;
-    c.flags = (uint32_t)b->opts.debug_flags;
+    c.flags = (uint32_t)b->debug_flags;
     c.chunk = (uint32_t)std::max(b->opts.units_per_grab, 0);
     c.wave_scratch = b->d_wave_scratch;
     c.hash_bits = b->method == MK_METHOD_CORES ? core_hash_bits(b->k) : enum_hash_bits(b->k);
@@ -215,8 +218,8 @@ static int batch_enqueue_prep(mk_batch *b, unsigned long long *hist, hipStream_t
     if (rc) return rc;
     return launch_plan(b->plan_k, b->d_graphs, b->ng, b->max_nnz, b->total_slots, b->d_slot_cnt,
                        b->d_slot_off, b->d_slot_est, b->d_slot_vi, b->d_scan_tmp, b->d_units,
-                       b->unit_cap,
-                       b->opts.split_threshold, (uint32_t)b->max_grid, b->d_counters, stream);
+                       b->unit_cap, b->opts.split_threshold, (uint32_t)b->max_grid,
+                       (uint32_t)std::max(b->opts.units_per_wave, 0), b->d_counters, stream);
 }
 
 // the counting kernel over units [counters[kSliceBegin], unit_end)
@@ -238,6 +241,14 @@ static int batch_launch_finish(mk_batch *b, unsigned long long *hist, hipStream_
     if (b->method != MK_METHOD_CORES) return MK_OK;
     return launch_core_divide(hist, b->ng, b->table->num_classes, b->table->d_core_mult,
                               b->d_counters, stream);
+}
+
+// the counting kernel and the finish, no events (a whole-pass graph)
+static int batch_enqueue_count_finish(mk_batch *b, unsigned long long *hist, hipStream_t stream)
+{
+    int rc = batch_launch_count(b, hist, kAllUnits, b->grid, stream);
+    if (rc) return rc;
+    return batch_launch_finish(b, hist, stream);
 }
 
 // the counting kernel between two timing events, then the finish
@@ -272,12 +283,17 @@ static int batch_create(mk_ctx *ctx, const mk_graph *const *gs, int32_t ng, int 
     b->ng = ng;
     b->graphs.assign(gs, gs + ng);
     if (opts) b->opts = *opts;
-    if (b->opts.method < MK_METHOD_AUTO || b->opts.method > MK_METHOD_CORES ||
-        b->opts.adjacency < MK_ADJ_AUTO || b->opts.adjacency > MK_ADJ_LISTS ||
-        b->opts.marks < MK_MARKS_AUTO || b->opts.marks > MK_MARKS_GLOBAL) {
+    const mk_batch_opts o = b->opts;
+    if (o.units_per_wave < 0 || o.units_per_wave > 4096) {
+        delete b;
+        return fail(MK_EINVAL, "mk_batch_create: units_per_wave %d outside 0..4096",
+                    o.units_per_wave);
+    }
+    if (o.method < MK_METHOD_AUTO || o.method > MK_METHOD_CORES || o.adjacency < MK_ADJ_AUTO ||
+        o.adjacency > MK_ADJ_LISTS || o.marks < MK_MARKS_AUTO || o.marks > MK_MARKS_GLOBAL) {
         delete b;
         return fail(MK_EINVAL, "mk_batch_create: unknown method %d, adjacency %d or marks %d",
-                    b->opts.method, b->opts.adjacency, b->opts.marks);
+                    o.method, o.adjacency, o.marks);
     }
 
     // workspace layout: [bit matrices of every graph, or the list-build
@@ -300,9 +316,10 @@ static int batch_create(mk_ctx *ctx, const mk_graph *const *gs, int32_t ng, int 
         slots += (uint64_t)g->nnz_u;
     }
     if (slots >= 0xFFFFFFFFull || 2 * b->total_m >= 0xFFFFFFFFull || b->total_n >= 0x7FFFFFFFull) {
+        const unsigned long long tm = b->total_m;
         delete b;
         return fail(MK_ERANGE, "batch too large: %llu adjacency entries, %llu arcs",
-                    (unsigned long long)slots, (unsigned long long)b->total_m);
+                    (unsigned long long)slots, tm);
     }
 
     // where the marks live, how arcs are tested, the counting method
@@ -319,9 +336,10 @@ static int batch_create(mk_ctx *ctx, const mk_graph *const *gs, int32_t ng, int 
                     ? b->opts.method
                     : (b->k <= 5 && b->marks == MK_MARKS_LDS ? MK_METHOD_CORES : MK_METHOD_ESU);
     if (b->marks == MK_MARKS_LDS && big) {
+        const int max_n = b->max_n;
         delete b;
         return fail(MK_ERANGE, "n=%d exceeds MK_LDS_MARKS_MAX_VERTICES=%d for MK_MARKS_LDS",
-                    b->max_n, MK_LDS_MARKS_MAX_VERTICES);
+                    max_n, MK_LDS_MARKS_MAX_VERTICES);
     }
     if (b->marks == MK_MARKS_GLOBAL && b->adjacency != MK_ADJ_LISTS) {
         delete b;
@@ -347,8 +365,9 @@ static int batch_create(mk_ctx *ctx, const mk_graph *const *gs, int32_t ng, int 
                        ? core_lds_bytes(b->k, std::max(b->max_n, 1), b->seg_cap)
                        : enum_lds_bytes(b->k, std::max(b->max_n, 1), b->seg_cap, b->variant);
     if ((size_t)b->lds_bytes > ctx->max_lds) {
+        const int lds = b->lds_bytes;
         delete b;
-        return fail(MK_ERANGE, "graphs need %d bytes of LDS per wave (limit %zu)", b->lds_bytes,
+        return fail(MK_ERANGE, "graphs need %d bytes of LDS per wave (limit %zu)", lds,
                     ctx->max_lds);
     }
     int rc = MK_OK;
@@ -431,8 +450,8 @@ static int batch_create(mk_ctx *ctx, const mk_graph *const *gs, int32_t ng, int 
     if (!rc)
         rc = launch_plan(b->plan_k, b->d_graphs, ng, b->max_nnz, b->total_slots, b->d_slot_cnt,
                          b->d_slot_off, b->d_slot_est, b->d_slot_vi, b->d_scan_tmp, nullptr, 0,
-                         b->opts.split_threshold,
-                         (uint32_t)b->max_grid, b->d_counters, ctx->stream);
+                         b->opts.split_threshold, (uint32_t)b->max_grid,
+                         (uint32_t)std::max(b->opts.units_per_wave, 0), b->d_counters, ctx->stream);
     if (rc) return bail(rc);
     uint32_t cnt[kNumCounters];
     BAIL_HIP(hipMemcpyAsync(cnt, b->d_counters, sizeof(cnt), hipMemcpyDeviceToHost, ctx->stream));
@@ -497,8 +516,15 @@ extern "C" int mk_batch_run(mk_batch *b, uint64_t *d_hist, void *stream)
             if (b->graph) (void)hipGraphDestroy(b->graph);
             b->exec = nullptr;
             b->graph = nullptr;
+            // use_graph 2: the whole pass -- preparation, counting kernel
+            // and finish -- as one graph; else the preparation alone, the
+            // counting kernel then launched between its timing events
+            // (events recorded inside a captured graph cannot be used for
+            // elapsed times on this runtime)
+            const bool whole = b->opts.use_graph == 2;
             MK_HIP(hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
             int rc = batch_enqueue_prep(b, hist, ctx->stream);
+            if (!rc && whole) rc = batch_enqueue_count_finish(b, hist, ctx->stream);
             hipGraph_t g = nullptr;
             hipError_t e = hipStreamEndCapture(ctx->stream, &g);
             if (rc) {
@@ -508,17 +534,23 @@ extern "C" int mk_batch_run(mk_batch *b, uint64_t *d_hist, void *stream)
             if (e != hipSuccess) return fail(MK_EDEVICE, "hipStreamEndCapture: %s", hipGetErrorString(e));
             b->graph = g;
             MK_HIP(hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0));
+            b->graph_whole = whole;
             b->exec_hist = hist;
         }
         MK_HIP(hipEventRecord(b->ev[0], s));
         MK_HIP(hipGraphLaunch(b->exec, s));
+        if (b->graph_whole) {
+            MK_HIP(hipEventRecord(b->ev[3], s));
+        } else {
+            int rc = batch_enqueue_enum(b, hist, s);
+            if (rc) return rc;
+        }
     } else {
         MK_HIP(hipEventRecord(b->ev[0], s));
         int rc = batch_enqueue_prep(b, hist, s);
+        if (!rc) rc = batch_enqueue_enum(b, hist, s);
         if (rc) return rc;
     }
-    int rc = batch_enqueue_enum(b, hist, s);
-    if (rc) return rc;
     b->hist_last = hist;
     b->last_stream = s;
     return MK_OK;
@@ -697,11 +729,22 @@ extern "C" int mk_batch_timing(mk_batch *b, double *pass_ms, double *enum_ms)
     std::lock_guard<std::recursive_mutex> lock(b->ctx->mu);
     MK_HIP(hipSetDevice(b->ctx->device));
     MK_HIP(hipEventSynchronize(b->ev[3]));
-    float a = 0.f, e = 0.f;
+    float a = 0.f, e = -1.f;
     MK_HIP(hipEventElapsedTime(&a, b->ev[0], b->ev[3]));
-    MK_HIP(hipEventElapsedTime(&e, b->ev[1], b->ev[2]));
+    if (!(b->opts.use_graph == 2)) MK_HIP(hipEventElapsedTime(&e, b->ev[1], b->ev[2]));
     if (pass_ms) *pass_ms = a;
     if (enum_ms) *enum_ms = e;
+    return MK_OK;
+}
+
+extern "C" int mk_batch_debug(mk_batch *b, int32_t flags)
+{
+    if (!b) return fail(MK_EINVAL, "mk_batch_debug: NULL batch");
+    if (flags & ~(int32_t)(kDebugNoHash | kDebugFlushAlways | kDebugNoShare))
+        return fail(MK_EINVAL, "mk_batch_debug: unknown flags %d", flags);
+    std::lock_guard<std::recursive_mutex> lock(b->ctx->mu);
+    if (b->debug_flags != flags) b->exec_hist = nullptr;  // captured with the old flags
+    b->debug_flags = flags;
     return MK_OK;
 }
 
@@ -746,7 +789,8 @@ static int time_candidate(mk_ctx *ctx, const mk_graph *const *gs, int32_t ng, co
 }
 
 extern "C" int mk_autotune(mk_ctx *ctx, const mk_graph *const *gs, int32_t ng, const mk_table *t,
-                           int32_t trials, mk_batch_opts *best, double *best_ms)
+                           int32_t trials, mk_batch_opts *best, double *best_ms,
+                           double *default_ms)
 {
     if (!ctx || !t || !best || (ng > 0 && !gs)) return fail(MK_EINVAL, "mk_autotune: NULL argument");
     if (ng <= 0) return fail(MK_EINVAL, "mk_autotune: no graphs");
@@ -758,6 +802,7 @@ extern "C" int mk_autotune(mk_ctx *ctx, const mk_graph *const *gs, int32_t ng, c
     int per_cu = 0;
     int rc = time_candidate(ctx, gs, ng, t, cur, trials, &cur_ms, &ref, &per_cu);
     if (rc) return rc;
+    if (default_ms) *default_ms = cur_ms;
     auto trial = [&](mk_batch_opts o) -> int {
         double ms = 0;
         int r = time_candidate(ctx, gs, ng, t, o, trials, &ms, &h);
@@ -789,12 +834,24 @@ extern "C" int mk_autotune(mk_ctx *ctx, const mk_graph *const *gs, int32_t ng, c
             }
         }
     }
-    static const uint64_t floors[] = {1u << 10, 1u << 14, 1u << 18, 1u << 22};
-    const mk_batch_opts base1 = cur;
-    for (uint64_t f : floors) {
-        mk_batch_opts o = base1;
-        o.split_threshold = f;
-        if ((rc = trial(o))) return rc;
+    // work-unit granularity: the split floor (estimated subgraphs per unit,
+    // below and above the defaults) and the planner's units per wave, two
+    // passes of the two so that each is tried at the other's best
+    static const uint64_t floors[] = {128, 256, 512, 1u << 10, 1u << 12, 1u << 14, 1u << 18};
+    static const int upws[] = {4, 8, 16, 32, 64, 128};
+    for (int pass = 0; pass < 2; ++pass) {
+        const mk_batch_opts base1 = cur;
+        for (uint64_t f : floors) {
+            mk_batch_opts o = base1;
+            o.split_threshold = f;
+            if ((rc = trial(o))) return rc;
+        }
+        const mk_batch_opts base2 = cur;
+        for (int u : upws) {
+            mk_batch_opts o = base2;
+            o.units_per_wave = u;
+            if ((rc = trial(o))) return rc;
+        }
     }
     static const int grabs[] = {1, 4, 16, 64};
     const mk_batch_opts base2 = cur;

@@ -424,8 +424,8 @@ __device__ __forceinline__ void unit_loop(EnumState<K, V> &s, const DevGraph *gr
     const uint32_t end = navail < cap ? navail : cap;
     const uint32_t begin = counters[kSliceBegin];
     const uint32_t span = end > begin ? end - begin : 0u;
-    // units per grab: about 1/16 of a wave's share, 1..16
-    uint32_t chunk = cfg.chunk ? cfg.chunk : span / (gridDim.x * 16u);
+    // units per grab: about 1/32 of a wave's share, 1..16
+    uint32_t chunk = cfg.chunk ? cfg.chunk : span / (gridDim.x * 32u);
     chunk = chunk < 1u ? 1u : (chunk > 256u ? 256u : chunk);
     if (!cfg.chunk && chunk > 16u) chunk = 16u;
     int cur = -1;

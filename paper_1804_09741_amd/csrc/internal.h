@@ -161,12 +161,14 @@ int launch_typed_csr(const DevGraph *d_graphs, int ng, int max_n, int64_t max_m,
                      hipStream_t stream);
 
 // Work-unit planner: cost estimate, counts per slot, scan, emit (units ==
-// nullptr: sizing only).  k = 2 plans one unit per vertex with a neighbour.  Writes counters[kNumUnits].  The split threshold
-// is max(split_threshold, estimated total / (waves * 16)).
+// nullptr: sizing only).  k = 2 plans one unit per vertex with a neighbour.
+// Writes counters[kNumUnits].  The split threshold is max(split_threshold,
+// estimated total / (waves * units_per_wave)); units_per_wave 0 takes the
+// planner's rule (16, or 64 on sorted-list adjacency below k = 7).
 int launch_plan(int k, const DevGraph *d_graphs, int ng, int64_t max_nnz, uint32_t total_slots,
                 uint32_t *slot_cnt, uint32_t *slot_off, uint32_t *slot_est, uint32_t *slot_vi,
                 uint32_t *scan_tmp, int4 *units, uint32_t unit_cap, uint64_t split_threshold,
-                uint32_t waves, uint32_t *counters, hipStream_t stream);
+                uint32_t waves, uint32_t units_per_wave, uint32_t *counters, hipStream_t stream);
 
 // Enumeration + code + lookup + histogram over the queued units.
 // k = 7 (k7.hip): device tables of one count
@@ -208,7 +210,7 @@ struct EnumConfig {
     int max_n;       // largest n of the batch (LDS marks)
     int seg_cap;     // largest undirected degree (LDS extension segments)
     uint32_t flags;  // kDebug* bits below (tests only; 0 in production)
-    uint32_t chunk;  // units per queue grab; 0 = about 1/16 of a wave's share
+    uint32_t chunk;  // units per queue grab; 0 = about 1/32 of a wave's share
     uint32_t *wave_scratch;  // core kernel: kParentArcCap words per workgroup
     int hash_bits;           // log2 of the per-wave hash slots (enum_/core_hash_bits)
     int variant;             // kVar* bits of the enumeration kernel (esu.h)

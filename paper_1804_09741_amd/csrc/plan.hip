@@ -74,27 +74,30 @@ enum PlanPass : int { kEstimate = 0, kCount = 1, kEmit = 2 };
 // Split threshold of the count and emit passes: the floor, raised so that
 // the estimated total work makes about units_per_wave<K>(g) units per
 // enumeration wave (large batches need little splitting, single graphs need
-// more).  Graphs counted on sorted lists are those past the bit-matrix limit
-// -- typically one large graph whose hubs make the few largest units the
-// tail of the launch -- and finer units even those out: 64 per wave instead
-// of 16 takes 10% off a power-law graph of 2^20 vertices at k = 6 on MI355X.
-// On bit-matrix graphs finer units do not pay (a mix of single graphs of
-// 100-5,000 vertices at k = 6 takes 7% longer with 64), and a k = 7 unit on
-// a large graph re-pushes its first members' marks into device memory (64
-// costs 4% there), so both keep 16.
+// more).  The defaults are the autotuner's picks on MI355X: 32 on
+// bit-matrix graphs (the k = 6 batch of 31 graphs: 1.968 -> 1.929 ms per
+// pass against 16; the k = 5 batch 25.58 -> 23.99 ms with the floor at
+// 1,024 and one unit per grab) and 128 on graphs counted on sorted lists,
+// past the bit-matrix limit -- typically one large graph whose hubs make
+// the few largest units the tail of the launch (a power-law graph of 2^20
+// vertices at k = 6: 197.8 -> 182.2 ms against 64).  k = 7 keeps 16: its
+// units on a large graph re-push their first members' marks into device
+// memory (64 cost 4% there).  A caller can set it per batch
+// (mk_batch_opts.units_per_wave).
 template <int K>
 __device__ __forceinline__ uint64_t units_per_wave(const DevGraph &g)
 {
-    return K < 7 && !g.bits_out ? 64u : 16u;
+    return K >= 7 ? 16u : (!g.bits_out ? 128u : 32u);
 }
 
 template <int K>
 __device__ __forceinline__ uint64_t effective_threshold(const DevGraph &g,
                                                         const uint32_t *counters, uint64_t floor_t,
-                                                        uint32_t waves)
+                                                        uint32_t waves, uint32_t upw)
 {
     const uint64_t total = *reinterpret_cast<const unsigned long long *>(counters + kEstTotal);
-    const uint64_t adaptive = total / ((uint64_t)waves * units_per_wave<K>(g) + 1);
+    const uint64_t per_wave = upw ? (uint64_t)upw : units_per_wave<K>(g);
+    const uint64_t adaptive = total / ((uint64_t)waves * per_wave + 1);
     return adaptive > floor_t ? adaptive : floor_t;
 }
 
@@ -159,14 +162,14 @@ __global__ __launch_bounds__(kPlanThreads) void plan_kernel(const DevGraph *grap
                                                             uint32_t *slot_est, uint32_t *slot_vi,
                                                             int4 *units, uint32_t unit_cap,
                                                             uint64_t floor_t, uint32_t waves,
-                                                            uint32_t *counters)
+                                                            uint32_t upw, uint32_t *counters)
 {
     const int gi = blockIdx.y;
     const DevGraph &g = graphs[gi];
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
     uint64_t est = 0;  // kEstimate: this slot's estimated cost
     const bool live = g.n > 0 && e < min(g.urow[g.n], (int)g.nnz_cap);
-    const uint64_t threshold = PASS == kEstimate ? ~0ull : effective_threshold<K>(g, counters, floor_t, waves);
+    const uint64_t threshold = PASS == kEstimate ? ~0ull : effective_threshold<K>(g, counters, floor_t, waves, upw);
     if (live) {
         const uint32_t slot = g.slot_base + (uint32_t)e;
         const int y = (int)(g.uadj[e] >> 2);
@@ -253,7 +256,7 @@ template <int K>
 static int plan_k(const DevGraph *d_graphs, int ng, int64_t max_nnz, uint32_t total_slots,
                   uint32_t *slot_cnt, uint32_t *slot_off, uint32_t *slot_est, uint32_t *slot_vi,
                   uint32_t *scan_tmp, int4 *units, uint32_t unit_cap, uint64_t threshold,
-                  uint32_t waves, uint32_t *counters, hipStream_t stream)
+                  uint32_t waves, uint32_t upw, uint32_t *counters, hipStream_t stream)
 {
     const dim3 grid((unsigned)((max_nnz + kPlanThreads - 1) / kPlanThreads > 0
                                    ? (max_nnz + kPlanThreads - 1) / kPlanThreads
@@ -264,18 +267,18 @@ static int plan_k(const DevGraph *d_graphs, int ng, int64_t max_nnz, uint32_t to
     int rc = MK_OK;
     hipLaunchKernelGGL((plan_kernel<K, kEstimate>), grid, dim3(kPlanThreads), 0, stream, d_graphs,
                        slot_cnt, slot_off, slot_est, slot_vi, units, unit_cap, threshold, waves,
-                       counters);
+                       upw, counters);
     MK_HIP(hipGetLastError());
     hipLaunchKernelGGL((plan_kernel<K, kCount>), grid, dim3(kPlanThreads), 0, stream, d_graphs,
                        slot_cnt, slot_off, slot_est, slot_vi, units, unit_cap, threshold, waves,
-                       counters);
+                       upw, counters);
     MK_HIP(hipGetLastError());
     rc = scan_u32(slot_cnt, slot_off, total_slots, 0, &counters[kNumUnits], scan_tmp, stream);
     if (rc != MK_OK) return rc;
     if (!units) return MK_OK;  // sizing pass
     hipLaunchKernelGGL((plan_kernel<K, kEmit>), grid, dim3(kPlanThreads), 0, stream, d_graphs,
                        slot_cnt, slot_off, slot_est, slot_vi, units, unit_cap, threshold, waves,
-                       counters);
+                       upw, counters);
     MK_HIP(hipGetLastError());
     return MK_OK;
 }
@@ -311,28 +314,28 @@ int launch_unit_begins(const DevGraph *d_graphs, int ng, const uint32_t *slot_of
 int launch_plan(int k, const DevGraph *d_graphs, int ng, int64_t max_nnz, uint32_t total_slots,
                 uint32_t *slot_cnt, uint32_t *slot_off, uint32_t *slot_est, uint32_t *slot_vi,
                 uint32_t *scan_tmp, int4 *units, uint32_t unit_cap, uint64_t split_threshold,
-                uint32_t waves, uint32_t *counters, hipStream_t stream)
+                uint32_t waves, uint32_t units_per_wave, uint32_t *counters, hipStream_t stream)
 {
     if (ng <= 0) return MK_OK;
     switch (k) {
     case 2:
         return plan_k<2>(d_graphs, ng, max_nnz, total_slots, slot_cnt, slot_off, slot_est, slot_vi, scan_tmp, units,
-                         unit_cap, split_threshold, waves, counters, stream);
+                         unit_cap, split_threshold, waves, units_per_wave, counters, stream);
     case 3:
         return plan_k<3>(d_graphs, ng, max_nnz, total_slots, slot_cnt, slot_off, slot_est, slot_vi, scan_tmp, units,
-                         unit_cap, split_threshold, waves, counters, stream);
+                         unit_cap, split_threshold, waves, units_per_wave, counters, stream);
     case 4:
         return plan_k<4>(d_graphs, ng, max_nnz, total_slots, slot_cnt, slot_off, slot_est, slot_vi, scan_tmp, units,
-                         unit_cap, split_threshold, waves, counters, stream);
+                         unit_cap, split_threshold, waves, units_per_wave, counters, stream);
     case 5:
         return plan_k<5>(d_graphs, ng, max_nnz, total_slots, slot_cnt, slot_off, slot_est, slot_vi, scan_tmp, units,
-                         unit_cap, split_threshold, waves, counters, stream);
+                         unit_cap, split_threshold, waves, units_per_wave, counters, stream);
     case 6:
         return plan_k<6>(d_graphs, ng, max_nnz, total_slots, slot_cnt, slot_off, slot_est, slot_vi, scan_tmp, units,
-                         unit_cap, split_threshold, waves, counters, stream);
+                         unit_cap, split_threshold, waves, units_per_wave, counters, stream);
     case 7:
         return plan_k<7>(d_graphs, ng, max_nnz, total_slots, slot_cnt, slot_off, slot_est, slot_vi, scan_tmp, units,
-                         unit_cap, split_threshold, waves, counters, stream);
+                         unit_cap, split_threshold, waves, units_per_wave, counters, stream);
     default: return fail(MK_ERANGE, "plan size k=%d outside 2..7", k);
     }
 }

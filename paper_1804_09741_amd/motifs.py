@@ -48,7 +48,7 @@ class MotifsError(RuntimeError):
 class BatchOpts(ctypes.Structure):
     _fields_ = [("split_threshold", ctypes.c_uint64), ("waves_per_cu", ctypes.c_int32),
                 ("use_graph", ctypes.c_int32), ("units_per_grab", ctypes.c_int32),
-                ("debug_flags", ctypes.c_int32), ("method", ctypes.c_int32),
+                ("units_per_wave", ctypes.c_int32), ("method", ctypes.c_int32),
                 ("adjacency", ctypes.c_int32), ("marks", ctypes.c_int32)]
 
 
@@ -119,7 +119,9 @@ SIGNATURES = {
     "mk_k7_cache_info": (ctypes.c_int, [_P, ctypes.POINTER(_U64), ctypes.POINTER(_U64)]),
     "mk_k7_cache_clear": (ctypes.c_int, [_P]),
     "mk_autotune": (ctypes.c_int, [_P, _P, _I32, _P, _I32, ctypes.POINTER(BatchOpts),
+                                   ctypes.POINTER(ctypes.c_double),
                                    ctypes.POINTER(ctypes.c_double)]),
+    "mk_batch_debug": (ctypes.c_int, [_P, _I32]),
     "mk_server_start": (ctypes.c_int, [_P, ctypes.POINTER(ServerOpts), ctypes.POINTER(_P)]),
     "mk_submit": (ctypes.c_int, [_P, _P, ctypes.c_int, ctypes.POINTER(_U64)]),
     "mk_wait": (ctypes.c_int, [_P, _U64, _P, _U32, _I32, ctypes.POINTER(RequestTimes)]),
@@ -367,14 +369,19 @@ def mk_k7_cache_clear(ctx: int) -> None:
 
 def mk_batch_create(ctx: int, gs: Sequence[int], t: int, split_threshold: int = 0,
                     waves_per_cu: int = 0, use_graph: int = 0, units_per_grab: int = 0,
-                    debug_flags: int = 0, method: int = 0, adjacency: int = 0,
+                    units_per_wave: int = 0, method: int = 0, adjacency: int = 0,
                     marks: int = 0) -> int:
-    opts = BatchOpts(split_threshold, waves_per_cu, use_graph, units_per_grab, debug_flags,
+    opts = BatchOpts(split_threshold, waves_per_cu, use_graph, units_per_grab, units_per_wave,
                      method, adjacency, marks)
     h = _P()
     _check(library().mk_batch_create(ctx, _handles(gs), len(gs), t, ctypes.byref(opts),
                                      ctypes.byref(h)))
     return h.value
+
+
+def mk_batch_debug(b: int, flags: int) -> None:
+    """Test hook (include/motifs_testing.h): alternative internal paths."""
+    _check(library().mk_batch_debug(b, flags))
 
 
 def mk_batch_run(b: int, d_hist: int = 0, stream: int = 0) -> None:
@@ -408,13 +415,14 @@ def mk_batch_free(b: int) -> None:
     library().mk_batch_free(b)
 
 
-def mk_autotune(ctx: int, gs: Sequence[int], t: int, trials: int = 2) -> Tuple[dict, float]:
-    """(fastest batch options, its whole-pass ms) for these graphs."""
+def mk_autotune(ctx: int, gs: Sequence[int], t: int, trials: int = 2) -> Tuple[dict, float, float]:
+    """(fastest batch options, its whole-pass ms, the defaults' whole-pass
+    ms) for these graphs."""
     o = BatchOpts()
-    ms = ctypes.c_double()
+    ms, dms = ctypes.c_double(), ctypes.c_double()
     _check(library().mk_autotune(ctx, _handles(gs), len(gs), t, trials, ctypes.byref(o),
-                                 ctypes.byref(ms)))
-    return {f: getattr(o, f) for f, _ in BatchOpts._fields_}, ms.value
+                                 ctypes.byref(ms), ctypes.byref(dms)))
+    return {f: getattr(o, f) for f, _ in BatchOpts._fields_}, ms.value, dms.value
 
 
 # ------------------------------------------------------------------- server
@@ -497,8 +505,15 @@ class Batch:
         self.ctx = ctx
         self.graphs = list(graphs)
         self.table = table
+        debug = opts.pop("debug_flags", 0)
         self.handle = mk_batch_create(ctx.handle, [g.handle for g in graphs], table.handle,
                                       **opts)
+        if debug:
+            try:
+                mk_batch_debug(self.handle, debug)
+            except MotifsError:
+                self.free()
+                raise
 
     def run(self, d_hist=None, stream=None) -> None:
         ptr = 0

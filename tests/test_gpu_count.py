@@ -195,7 +195,8 @@ def test_counting_paths_agree(ctx, k):
     g = I.chung_lu_digraph(300, 1000, 2.1, 60 if k < 6 else 20, 0.15, rng)
     ref, _ = _count(ctx, g, k)
     for opts in ({"debug_flags": 1}, {"debug_flags": 2}, {"units_per_grab": 1},
-                 {"units_per_grab": 64}, {"split_threshold": 1, "units_per_grab": 3}):
+                 {"units_per_grab": 64}, {"split_threshold": 1, "units_per_grab": 3},
+                 {"units_per_wave": 4}, {"units_per_wave": 128, "split_threshold": 128}):
         h, _ = _count(ctx, g, k, **opts)
         assert np.array_equal(h, ref), opts
     if k <= 5:
@@ -209,10 +210,10 @@ def test_autotune_keeps_results(ctx):
     t = ctx.table(k)
     loaded = [ctx.load_graph(*g) for g in graphs]
     try:
-        opts, ms = ctx.autotune(loaded, t, trials=1)
+        opts, ms, dms = ctx.autotune(loaded, t, trials=1)
         assert ms > 0
         ref, _ = ctx.count_batch(loaded, t)
-        b = ctx.batch(loaded, t, **{kk: v for kk, v in opts.items() if kk != "debug_flags"})
+        b = ctx.batch(loaded, t, **opts)
         try:
             b.run()
             h, _ = b.read()
@@ -222,3 +223,49 @@ def test_autotune_keeps_results(ctx):
     finally:
         for g in loaded:
             g.free()
+
+
+@pytest.mark.parametrize("method", [M.METHOD_ESU, M.METHOD_CORES])
+def test_graph_replays_equal_eager(ctx, method):
+    """The captured pass -- the preparation (use_graph 1) or the whole pass,
+    preparation, counting kernel and finish (use_graph 2): every replay,
+    with eager work and host synchronisation between replays, equals the
+    eager pass; the timing events give the pass (and, with 1, the kernel)
+    durations; a new histogram buffer is captured anew."""
+    rng = np.random.default_rng(4200)
+    graphs = [I.chung_lu_digraph(int(rng.integers(100, 400)), int(rng.integers(300, 1200)),
+                                 2.2, 40, 0.1, rng) for _ in range(4)]
+    k = 5
+    t = ctx.table(k)
+    loaded = [ctx.load_graph(*g) for g in graphs]
+    try:
+        eager = ctx.batch(loaded, t, method=method, use_graph=-1)
+        try:
+            eager.run()
+            ref, _ = eager.read()
+        finally:
+            eager.free()
+        for use_graph in (1, 2):
+            _replays(ctx, loaded, t, method, use_graph, ref)
+    finally:
+        for g in loaded:
+            g.free()
+
+
+def _replays(ctx, loaded, t, method, use_graph, ref):
+    import torch
+    b = ctx.batch(loaded, t, method=method, use_graph=use_graph)
+    try:
+        for buf in range(2):
+            d = torch.full((len(loaded), t.num_classes), 3, dtype=torch.int64, device="cuda:0")
+            for _ in range(3):
+                b.run(d, torch.cuda.current_stream())
+                pass_ms, kern_ms = b.timing()
+                assert pass_ms > 0
+                assert (0 < kern_ms <= pass_ms) if use_graph == 1 else kern_ms == -1
+                assert np.array_equal(d.cpu().numpy().astype(np.uint64), ref)
+                h, _ = ctx.count(loaded[buf], t)  # eager work between replays
+                assert np.array_equal(h, ref[buf])
+                d.fill_(5)
+    finally:
+        b.free()

@@ -164,6 +164,8 @@ def test_variant_option_errors(ctx):
             (small, dict(marks=M.MARKS_GLOBAL, adjacency=M.ADJ_BITS), M.MK_EINVAL),
             (small, dict(adjacency=3), M.MK_EINVAL),
             (small, dict(marks=-1), M.MK_EINVAL),
+            (small, dict(units_per_wave=-1), M.MK_EINVAL),
+            (small, dict(units_per_wave=5000), M.MK_EINVAL),
         ]:
             with pytest.raises(M.MotifsError) as e:
                 ctx.batch([gr], t, **opts)
@@ -171,6 +173,9 @@ def test_variant_option_errors(ctx):
         with pytest.raises(M.MotifsError) as e:
             ctx.randomise(big, 1, 1)
         assert e.value.status == M.MK_ERANGE
+        with pytest.raises(M.MotifsError) as e:
+            ctx.batch([small], t, debug_flags=8)
+        assert e.value.status == M.MK_EINVAL
     finally:
         big.free()
         small.free()
@@ -181,7 +186,7 @@ def test_autotune_tries_adjacency(ctx):
     graphs = [ctx.load_graph(*I.chung_lu_digraph(400, 1500, 2.2, 40, 0.2, rng))
               for _ in range(3)]
     try:
-        best, ms = ctx.autotune(graphs, ctx.table(5), trials=1)
+        best, ms, dms = ctx.autotune(graphs, ctx.table(5), trials=1)
         assert best["adjacency"] in (M.ADJ_AUTO, M.ADJ_BITS, M.ADJ_LISTS) and ms > 0
     finally:
         for g in graphs:
