@@ -355,7 +355,7 @@ void mk_batch_free(mk_batch *b);
    on each device it runs on until the process ends.  No hipMalloc, hipFree
    or allocating library call is made.  g: a loaded graph with n <=
    MK_LDS_MARKS_MAX_VERTICES whose workspace fits the array (about 8 n^2/32 +
-   20 |delta| bytes plus the work units), else MK_ERANGE with a message
+   24 |delta| bytes plus the work units), else MK_ERANGE with a message
    giving the size needed.  t: a built table (k = 3..6).  d_hist: device
    array of t's num_classes uint64, overwritten with the histogram.  Runs on
    `stream` (NULL: the context's stream) and blocks until done, then checks

@@ -34,6 +34,7 @@ struct mk_batch {
     uint32_t *d_slot_off = nullptr;
     uint32_t *d_slot_est = nullptr;
     uint32_t *d_slot_vi = nullptr;
+    uint32_t *d_slot_l2 = nullptr;
     uint32_t *d_scan_tmp = nullptr;
     uint32_t total_slots = 0;
     int4 *d_units = nullptr;
@@ -146,7 +147,7 @@ extern "C" int mk_graph_footprint(const mk_graph *g, int k, uint64_t *bytes)
     const bool big = g->n > MK_LDS_MARKS_MAX_VERTICES;  // list-built adjacency, global marks
     const uint64_t region = big ? list_ws_words(n, (uint64_t)g->m) : 2 * n * w;
     const uint64_t ws = 4 * (region + (n + 1) + (uint64_t)g->nnz_u);
-    const uint64_t slots = 8 * (uint64_t)g->nnz_u + 4 * ((uint64_t)g->nnz_u / 4096 + 2);
+    const uint64_t slots = 20 * (uint64_t)g->nnz_u + 4 * ((uint64_t)g->nnz_u / 4096 + 2);
     const uint64_t units = 16 * (uint64_t)g->nnz_u * 4;  // planning estimate
     const uint64_t hist = 8ull * classes_for_k(k);
     // per-workgroup arc lists of the core method (the default for k <= 5 on
@@ -172,7 +173,7 @@ static void batch_release(mk_batch *b)
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
     if (b->graph) (void)hipGraphDestroy(b->graph);
     void *bufs[] = {b->d_graphs, b->d_ws, b->d_slot_cnt, b->d_slot_off, b->d_slot_est,
-                    b->d_slot_vi, b->d_scan_tmp,
+                    b->d_slot_vi, b->d_slot_l2, b->d_scan_tmp,
                     b->d_units, b->d_counters, b->d_unit_begin, b->d_hist_own, b->d_wave_scratch,
                     b->d_marks};
     for (void *p : bufs)
@@ -205,7 +206,11 @@ static int batch_enqueue_typed(mk_batch *b, hipStream_t stream)
 }
 
 // enqueue the preparation part of one pass on stream: counters and
-// histograms cleared, typed adjacency, work-unit plan (captured as a hipGraph)
+// histograms cleared, typed adjacency, work-unit plan (captured as a
+// hipGraph).  (Clearing the histograms from extra workgroups of the
+// latency-bound plan passes instead was measured slower: the streaming
+// stores raise the latency of the passes' dependent loads, 0.24 ms for the
+// k = 6 batch's preparation either way.)
 static int batch_enqueue_prep(mk_batch *b, unsigned long long *hist, hipStream_t stream)
 {
     int rc = fill_u32(b->d_counters, 0, kNumCounters, stream);
@@ -217,8 +222,8 @@ static int batch_enqueue_prep(mk_batch *b, unsigned long long *hist, hipStream_t
     rc = batch_enqueue_typed(b, stream);
     if (rc) return rc;
     return launch_plan(b->plan_k, b->d_graphs, b->ng, b->max_nnz, b->total_slots, b->d_slot_cnt,
-                       b->d_slot_off, b->d_slot_est, b->d_slot_vi, b->d_scan_tmp, b->d_units,
-                       b->unit_cap, b->opts.split_threshold, (uint32_t)b->max_grid,
+                       b->d_slot_off, b->d_slot_est, b->d_slot_vi, b->d_slot_l2, b->d_scan_tmp,
+                       b->d_units, b->unit_cap, b->opts.split_threshold, (uint32_t)b->max_grid,
                        (uint32_t)std::max(b->opts.units_per_wave, 0), b->d_counters, stream);
 }
 
@@ -419,6 +424,7 @@ static int batch_create(mk_ctx *ctx, const mk_graph *const *gs, int32_t ng, int 
     BAIL_HIP(hipMalloc(&b->d_slot_off, sizeof(uint32_t) * std::max<uint64_t>(slots, 1)));
     BAIL_HIP(hipMalloc(&b->d_slot_est, sizeof(uint32_t) * std::max<uint64_t>(slots, 1)));
     BAIL_HIP(hipMalloc(&b->d_slot_vi, sizeof(uint32_t) * std::max<uint64_t>(slots, 1)));
+    BAIL_HIP(hipMalloc(&b->d_slot_l2, sizeof(uint32_t) * std::max<uint64_t>(slots, 1)));
     BAIL_HIP(hipMalloc(&b->d_scan_tmp, sizeof(uint32_t) * scan_tmp_words(slots)));
     BAIL_HIP(hipMalloc(&b->d_counters, sizeof(uint32_t) * kNumCounters));
     BAIL_HIP(hipMalloc(&b->d_unit_begin, sizeof(uint32_t) * ((size_t)ng + 1)));
@@ -449,9 +455,10 @@ static int batch_create(mk_ctx *ctx, const mk_graph *const *gs, int32_t ng, int 
     if (!rc) rc = batch_enqueue_typed(b, ctx->stream);
     if (!rc)
         rc = launch_plan(b->plan_k, b->d_graphs, ng, b->max_nnz, b->total_slots, b->d_slot_cnt,
-                         b->d_slot_off, b->d_slot_est, b->d_slot_vi, b->d_scan_tmp, nullptr, 0,
-                         b->opts.split_threshold, (uint32_t)b->max_grid,
-                         (uint32_t)std::max(b->opts.units_per_wave, 0), b->d_counters, ctx->stream);
+                         b->d_slot_off, b->d_slot_est, b->d_slot_vi, b->d_slot_l2, b->d_scan_tmp,
+                         nullptr, 0, b->opts.split_threshold, (uint32_t)b->max_grid,
+                         (uint32_t)std::max(b->opts.units_per_wave, 0), b->d_counters,
+                         ctx->stream);
     if (rc) return bail(rc);
     uint32_t cnt[kNumCounters];
     BAIL_HIP(hipMemcpyAsync(cnt, b->d_counters, sizeof(cnt), hipMemcpyDeviceToHost, ctx->stream));
@@ -621,7 +628,7 @@ uint64_t batch_device_bytes(const mk_batch *b)
     uint64_t words = b->adjacency == MK_ADJ_BITS ? b->bits_words
                                                  : list_ws_words(b->total_n, b->total_m);
     for (const mk_graph *g : b->graphs) words += (uint64_t)g->n + 1 + (uint64_t)g->nnz_u;
-    return 4 * words + 16ull * b->total_slots + 4 * scan_tmp_words(b->total_slots) +
+    return 4 * words + 20ull * b->total_slots + 4 * scan_tmp_words(b->total_slots) +
            16ull * b->unit_cap + 8ull * b->ng * b->table->num_classes + 4ull * (b->ng + 1) +
            sizeof(DevGraph) * b->graphs.size() + 4 * kNumCounters +
            (b->d_wave_scratch ? 4ull * kParentArcCap * (uint64_t)b->grid : 0) + b->mark_bytes;

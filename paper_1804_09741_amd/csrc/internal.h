@@ -165,10 +165,13 @@ int launch_typed_csr(const DevGraph *d_graphs, int ng, int max_n, int64_t max_m,
 // Writes counters[kNumUnits].  The split threshold is max(split_threshold,
 // estimated total / (waves * units_per_wave)); units_per_wave 0 takes the
 // planner's rule (16, or 64 on sorted-list adjacency below k = 7).
+// slot_l2: per slot, the extension length of its first-level node (written
+// by the estimate pass, read by the count and emit passes).
 int launch_plan(int k, const DevGraph *d_graphs, int ng, int64_t max_nnz, uint32_t total_slots,
                 uint32_t *slot_cnt, uint32_t *slot_off, uint32_t *slot_est, uint32_t *slot_vi,
-                uint32_t *scan_tmp, int4 *units, uint32_t unit_cap, uint64_t split_threshold,
-                uint32_t waves, uint32_t units_per_wave, uint32_t *counters, hipStream_t stream);
+                uint32_t *slot_l2, uint32_t *scan_tmp, int4 *units, uint32_t unit_cap,
+                uint64_t split_threshold, uint32_t waves, uint32_t units_per_wave,
+                uint32_t *counters, hipStream_t stream);
 
 // Enumeration + code + lookup + histogram over the queued units.
 // k = 7 (k7.hip): device tables of one count

@@ -82,37 +82,81 @@ __device__ __forceinline__ Code7 code_bits7(uint32_t m, int p)
            ((Code7)(m & EnumState<7>::INMASK) << (p - 1));
 }
 
-// Canonical code: every lane tries the relabelings l, l + 64, ... of the
-// 5040 (numbered in the factorial number system), the wave takes the
-// minimum.  Call with every lane active and the same code in all lanes.
+// i-th set bit (0-based) of a 7-bit mask
+__device__ __forceinline__ uint32_t nth_bit(uint32_t m, int i)
+{
+    for (int t = 0; t < i; ++t) m &= m - 1u;
+    return (uint32_t)__builtin_ctz(m);
+}
+
+// Canonical code: the minimum code over the relabelings.  Only relabelings
+// that can reach the minimum are tried.  The top six bits of a code are the
+// out-arcs of the vertex at position 6 (bit of arc 6 -> j at 36 + j); for a
+// vertex of out-degree d they are at least 2^d - 1, reached exactly when its
+// out-neighbours take positions 0..d-1.  So the minimum puts at position 6
+// a vertex of the least out-degree d_min and its out-neighbours at 0..d-1;
+// the others take d..5 in any order.  Relabeling t of the |C| d! (6 - d)!
+// left (C: the vertices of out-degree d_min) picks the candidate, the order
+// of its out-neighbours and the order of the rest in the factorial number
+// system; lane l tries t = l, l + 64, ..., the wave takes the minimum.  Call
+// with every lane active and the same code in all lanes.
 __device__ Code7 canon7_wave(Code7 code)
 {
-    constexpr int fact[7] = {720, 120, 24, 6, 2, 1, 1};
-    Code7 best = kNoCode;
-    for (int p = lane_id(); p < 5040; p += kWave) {
-        // relabeling p: position pos of the new order takes vertex perm(pos);
-        // perm is kept as 4-bit fields
-        int idx = p;
-        uint32_t avail = 0x7Fu, perm = 0;
+    constexpr int fact[7] = {1, 1, 2, 6, 24, 120, 720};
+    // out-degree of every vertex within the code
+    uint32_t cand = 0;
+    int dmin = 7;
 #pragma unroll
-        for (int pos = 0; pos < 7; ++pos) {
-            const int d = idx / fact[pos];
-            idx -= d * fact[pos];
-            uint32_t a = avail;
-            for (int t = 0; t < d; ++t) a &= a - 1u;
-            const uint32_t v = (uint32_t)__builtin_ctz(a);
-            perm |= v << (4 * pos);
+    for (int i = 0; i < 7; ++i) {
+        const int od = __builtin_popcountll((code >> (6 * i)) & 63ull);
+        if (od < dmin) {
+            dmin = od;
+            cand = 0;
+        }
+        if (od == dmin) cand |= 1u << i;
+    }
+    const int per = fact[dmin] * fact[6 - dmin];
+    const int total = __builtin_popcount(cand) * per;
+    Code7 best = kNoCode;
+    for (int t = lane_id(); t < total; t += kWave) {
+        const uint32_t c = nth_bit(cand, t / per);
+        int r = t % per;
+        // out-neighbours of c (row c, column r -> vertex r + [r >= c])
+        const uint32_t row = (uint32_t)((code >> (6 * c)) & 63ull);
+        const uint32_t lowc = (1u << c) - 1u;
+        const uint32_t outn = (row & lowc) | ((row & ~lowc) << 1);
+        const uint32_t restm = 0x7Fu & ~outn & ~(1u << c);
+        // sigma(v) = new position of vertex v, as 4-bit fields
+        uint32_t sigma = 6u << (4 * c);
+        int q = r / fact[6 - dmin];
+        r -= q * fact[6 - dmin];
+        uint32_t avail = outn;
+        for (int pos = 0; pos < dmin; ++pos) {
+            const int f = fact[dmin - 1 - pos];
+            const int d = q / f;
+            q -= d * f;
+            const uint32_t v = nth_bit(avail, d);
+            sigma |= (uint32_t)pos << (4 * v);
             avail &= ~(1u << v);
         }
-        Code7 c = 0, rest = code;
+        avail = restm;
+        for (int pos = dmin; pos < 6; ++pos) {
+            const int f = fact[5 - pos];
+            const int d = r / f;
+            r -= d * f;
+            const uint32_t v = nth_bit(avail, d);
+            sigma |= (uint32_t)pos << (4 * v);
+            avail &= ~(1u << v);
+        }
+        Code7 cc = 0, rest = code;
         while (rest) {
             const int b = __builtin_ctzll(rest);
             rest &= rest - 1;
-            const int i = b / 6, r = b - 6 * i;
-            const int j = r + (r >= i ? 1 : 0);
-            c |= 1ull << bit7((int)((perm >> (4 * i)) & 15u), (int)((perm >> (4 * j)) & 15u));
+            const int i = b / 6, rr = b - 6 * i;
+            const int j = rr + (rr >= i ? 1 : 0);
+            cc |= 1ull << bit7((int)((sigma >> (4 * i)) & 15u), (int)((sigma >> (4 * j)) & 15u));
         }
-        best = c < best ? c : best;
+        best = cc < best ? cc : best;
     }
 #pragma unroll
     for (int off = kWave / 2; off > 0; off >>= 1) {

@@ -98,7 +98,7 @@ extern "C" int mk_count_static(mk_ctx *ctx, const mk_graph *g, const mk_table *t
                                               : fail(MK_EDEVICE, "mk_count_static: sync failed");
 
     // layout of the scratch: counters | descriptor | bit matrices | urow |
-    // uadj | 4 planner slot arrays | scan workspace | work units
+    // uadj | 5 planner slot arrays | scan workspace | work units
     const uint64_t n = (uint64_t)g->n, w = (n + 31) / 32, nnz = (uint64_t)g->nnz_u;
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -111,7 +111,7 @@ extern "C" int mk_count_static(mk_ctx *ctx, const mk_graph *g, const mk_table *t
     const size_t o_bits = take(4ull * 2 * n * w);
     const size_t o_urow = take(4ull * (n + 1));
     const size_t o_uadj = take(4ull * nnz);
-    const size_t o_slot = take(4ull * 4 * nnz);
+    const size_t o_slot = take(4ull * 5 * nnz);
     const size_t o_scan = take(4ull * scan_tmp_words(nnz));
     const size_t o_units = off;
     const uint64_t unit_cap =
@@ -156,8 +156,8 @@ extern "C" int mk_count_static(mk_ctx *ctx, const mk_graph *g, const mk_table *t
     if (!rc) rc = launch_typed_csr(dg, 1, g->n, g->m, 2 * n * w, d.bits_out, counters, s);
     if (!rc)
         rc = launch_plan(k, dg, 1, (int64_t)nnz, (uint32_t)nnz, slots, slots + nnz, slots + 2 * nnz,
-                         slots + 3 * nnz, reinterpret_cast<uint32_t *>(base + o_scan), units,
-                         (uint32_t)std::min<uint64_t>(unit_cap, 0xFFFFFFFFull),
+                         slots + 3 * nnz, slots + 4 * nnz, reinterpret_cast<uint32_t *>(base + o_scan),
+                         units, (uint32_t)std::min<uint64_t>(unit_cap, 0xFFFFFFFFull),
                          default_split_floor(k), (uint32_t)grid, 0u, counters, s);
     EnumConfig cfg{};
     cfg.max_n = g->n;

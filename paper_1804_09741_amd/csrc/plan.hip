@@ -16,6 +16,8 @@
 // u in delta(v)); a slot with u > v is a first-level node.  Pass one counts
 // the units of every slot, a scan gives offsets, pass two writes the units.
 // The order is graph by graph, root by root.
+#include <algorithm>
+
 #include "internal.h"
 #include "server_hooks.h"
 
@@ -155,11 +157,13 @@ __device__ __forceinline__ int ext_len(const DevGraph &g, int v, int ext_v, int 
     return ext_v - i - 1 + fresh;
 }
 
+// One workgroup per (graph, 256 slots): blockIdx.y is the graph.
 template <int K, int PASS>
 __global__ __launch_bounds__(kPlanThreads) void plan_kernel(const DevGraph *graphs,
                                                             uint32_t *slot_cnt,
                                                             const uint32_t *slot_off,
                                                             uint32_t *slot_est, uint32_t *slot_vi,
+                                                            uint32_t *slot_l2,
                                                             int4 *units, uint32_t unit_cap,
                                                             uint64_t floor_t, uint32_t waves,
                                                             uint32_t upw, uint32_t *counters)
@@ -188,6 +192,7 @@ __global__ __launch_bounds__(kPlanThreads) void plan_kernel(const DevGraph *grap
                 const int first = first_above(g.uadj, g.urow[v], r1, v);
                 const int i = e - first;
                 const int L2 = ext_len(g, v, r1 - first, i, y);
+                slot_l2[slot] = (uint32_t)L2;
                 if constexpr (K == 3) est = (uint64_t)L2 + 1;
                 else split_children<K, false>(g, v, first, r1, i, y, L2, ~0ull, &est,
                                               [](uint32_t, uint32_t) {});
@@ -213,7 +218,7 @@ __global__ __launch_bounds__(kPlanThreads) void plan_kernel(const DevGraph *grap
                 } else if constexpr (K > 3) {
                     const int r1 = g.urow[v + 1];
                     const int first = e - i;
-                    const int L2 = ext_len(g, v, r1 - first, i, y);
+                    const int L2 = (int)slot_l2[slot];  // from the estimate pass
                     uint32_t base = 0;
                     if (PASS == kEmit) base = slot_off[slot];
                     auto put = [&](uint32_t r, uint32_t w) {
@@ -255,30 +260,28 @@ __global__ __launch_bounds__(kPlanThreads) void plan_kernel(const DevGraph *grap
 template <int K>
 static int plan_k(const DevGraph *d_graphs, int ng, int64_t max_nnz, uint32_t total_slots,
                   uint32_t *slot_cnt, uint32_t *slot_off, uint32_t *slot_est, uint32_t *slot_vi,
-                  uint32_t *scan_tmp, int4 *units, uint32_t unit_cap, uint64_t threshold,
-                  uint32_t waves, uint32_t upw, uint32_t *counters, hipStream_t stream)
+                  uint32_t *slot_l2, uint32_t *scan_tmp, int4 *units, uint32_t unit_cap,
+                  uint64_t threshold, uint32_t waves, uint32_t upw, uint32_t *counters,
+                  hipStream_t stream)
 {
-    const dim3 grid((unsigned)((max_nnz + kPlanThreads - 1) / kPlanThreads > 0
-                                   ? (max_nnz + kPlanThreads - 1) / kPlanThreads
-                                   : 1),
+    const dim3 grid((unsigned)std::max<int64_t>((max_nnz + kPlanThreads - 1) / kPlanThreads, 1),
                     (unsigned)ng);
     // the estimate total (counters[kEstTotal]) starts at zero: the callers
     // clear all counters before every plan
-    int rc = MK_OK;
     hipLaunchKernelGGL((plan_kernel<K, kEstimate>), grid, dim3(kPlanThreads), 0, stream, d_graphs,
-                       slot_cnt, slot_off, slot_est, slot_vi, units, unit_cap, threshold, waves,
-                       upw, counters);
+                       slot_cnt, slot_off, slot_est, slot_vi, slot_l2, units, unit_cap, threshold,
+                       waves, upw, counters);
     MK_HIP(hipGetLastError());
     hipLaunchKernelGGL((plan_kernel<K, kCount>), grid, dim3(kPlanThreads), 0, stream, d_graphs,
-                       slot_cnt, slot_off, slot_est, slot_vi, units, unit_cap, threshold, waves,
-                       upw, counters);
+                       slot_cnt, slot_off, slot_est, slot_vi, slot_l2, units, unit_cap, threshold,
+                       waves, upw, counters);
     MK_HIP(hipGetLastError());
-    rc = scan_u32(slot_cnt, slot_off, total_slots, 0, &counters[kNumUnits], scan_tmp, stream);
+    int rc = scan_u32(slot_cnt, slot_off, total_slots, 0, &counters[kNumUnits], scan_tmp, stream);
     if (rc != MK_OK) return rc;
     if (!units) return MK_OK;  // sizing pass
     hipLaunchKernelGGL((plan_kernel<K, kEmit>), grid, dim3(kPlanThreads), 0, stream, d_graphs,
-                       slot_cnt, slot_off, slot_est, slot_vi, units, unit_cap, threshold, waves,
-                       upw, counters);
+                       slot_cnt, slot_off, slot_est, slot_vi, slot_l2, units, unit_cap, threshold,
+                       waves, upw, counters);
     MK_HIP(hipGetLastError());
     return MK_OK;
 }
@@ -313,31 +316,25 @@ int launch_unit_begins(const DevGraph *d_graphs, int ng, const uint32_t *slot_of
 
 int launch_plan(int k, const DevGraph *d_graphs, int ng, int64_t max_nnz, uint32_t total_slots,
                 uint32_t *slot_cnt, uint32_t *slot_off, uint32_t *slot_est, uint32_t *slot_vi,
-                uint32_t *scan_tmp, int4 *units, uint32_t unit_cap, uint64_t split_threshold,
-                uint32_t waves, uint32_t units_per_wave, uint32_t *counters, hipStream_t stream)
+                uint32_t *slot_l2, uint32_t *scan_tmp, int4 *units, uint32_t unit_cap,
+                uint64_t split_threshold, uint32_t waves, uint32_t units_per_wave,
+                uint32_t *counters, hipStream_t stream)
 {
     if (ng <= 0) return MK_OK;
+#define MK_PLAN(KK)                                                                         \
+    plan_k<KK>(d_graphs, ng, max_nnz, total_slots, slot_cnt, slot_off, slot_est, slot_vi,  \
+               slot_l2, scan_tmp, units, unit_cap, split_threshold, waves, units_per_wave, \
+               counters, stream)
     switch (k) {
-    case 2:
-        return plan_k<2>(d_graphs, ng, max_nnz, total_slots, slot_cnt, slot_off, slot_est, slot_vi, scan_tmp, units,
-                         unit_cap, split_threshold, waves, units_per_wave, counters, stream);
-    case 3:
-        return plan_k<3>(d_graphs, ng, max_nnz, total_slots, slot_cnt, slot_off, slot_est, slot_vi, scan_tmp, units,
-                         unit_cap, split_threshold, waves, units_per_wave, counters, stream);
-    case 4:
-        return plan_k<4>(d_graphs, ng, max_nnz, total_slots, slot_cnt, slot_off, slot_est, slot_vi, scan_tmp, units,
-                         unit_cap, split_threshold, waves, units_per_wave, counters, stream);
-    case 5:
-        return plan_k<5>(d_graphs, ng, max_nnz, total_slots, slot_cnt, slot_off, slot_est, slot_vi, scan_tmp, units,
-                         unit_cap, split_threshold, waves, units_per_wave, counters, stream);
-    case 6:
-        return plan_k<6>(d_graphs, ng, max_nnz, total_slots, slot_cnt, slot_off, slot_est, slot_vi, scan_tmp, units,
-                         unit_cap, split_threshold, waves, units_per_wave, counters, stream);
-    case 7:
-        return plan_k<7>(d_graphs, ng, max_nnz, total_slots, slot_cnt, slot_off, slot_est, slot_vi, scan_tmp, units,
-                         unit_cap, split_threshold, waves, units_per_wave, counters, stream);
+    case 2: return MK_PLAN(2);
+    case 3: return MK_PLAN(3);
+    case 4: return MK_PLAN(4);
+    case 5: return MK_PLAN(5);
+    case 6: return MK_PLAN(6);
+    case 7: return MK_PLAN(7);
     default: return fail(MK_ERANGE, "plan size k=%d outside 2..7", k);
     }
+#undef MK_PLAN
 }
 
 }  // namespace mk
