@@ -89,74 +89,110 @@ __device__ __forceinline__ uint32_t nth_bit(uint32_t m, int i)
     return (uint32_t)__builtin_ctz(m);
 }
 
+// out-neighbours of vertex c in a 7-vertex code (row c, column r is vertex
+// r + [r >= c]), as a 7-bit mask
+__device__ __forceinline__ uint32_t out_nbrs7(Code7 code, uint32_t c)
+{
+    const uint32_t row = (uint32_t)((code >> (6 * c)) & 63ull);
+    const uint32_t lowc = (1u << c) - 1u;
+    return (row & lowc) | ((row & ~lowc) << 1);
+}
+
+// the vertices of mask m in increasing order take positions first.. in the
+// order numbered r (factorial number system), into the 4-bit fields of sigma
+__device__ __forceinline__ void place7(uint32_t &sigma, uint32_t m, int first, int count, int r)
+{
+    constexpr int fact[7] = {1, 1, 2, 6, 24, 120, 720};
+    for (int pos = 0; pos < count; ++pos) {
+        const int f = fact[count - 1 - pos];
+        const int d = r / f;
+        r -= d * f;
+        const uint32_t v = nth_bit(m, d);
+        sigma |= (uint32_t)(first + pos) << (4 * v);
+        m &= ~(1u << v);
+    }
+}
+
 // Canonical code: the minimum code over the relabelings.  Only relabelings
 // that can reach the minimum are tried.  The top six bits of a code are the
 // out-arcs of the vertex at position 6 (bit of arc 6 -> j at 36 + j); for a
 // vertex of out-degree d they are at least 2^d - 1, reached exactly when its
 // out-neighbours take positions 0..d-1.  So the minimum puts at position 6
-// a vertex of the least out-degree d_min and its out-neighbours at 0..d-1;
-// the others take d..5 in any order.  Relabeling t of the |C| d! (6 - d)!
-// left (C: the vertices of out-degree d_min) picks the candidate, the order
-// of its out-neighbours and the order of the rest in the factorial number
-// system; lane l tries t = l, l + 64, ..., the wave takes the minimum.  Call
-// with every lane active and the same code in all lanes.
-__device__ Code7 canon7_wave(Code7 code)
+// a vertex of the least out-degree d6 and its out-neighbours at 0..d6-1.
+// When d6 = 0 (a sink at 6, the usual case in sparse graphs) the next six
+// bits are the row of position 5, whose top bit is its arc to position 6:
+// the minimum puts at 5 a vertex without that arc if there is one, of the
+// least out-degree d5 towards the other five among those, and its
+// out-neighbours at 0..d5-1.  For each candidate at position 6 in turn, the
+// relabelings left are numbered (the candidate at 5, then the order of each
+// group of positions in the factorial number system); lane l tries l,
+// l + 64, ..., and the wave takes the minimum.  Call with every lane active
+// and the same code in all lanes.
+__device__ __forceinline__ Code7 canon7_wave(Code7 code)
 {
     constexpr int fact[7] = {1, 1, 2, 6, 24, 120, 720};
-    // out-degree of every vertex within the code
-    uint32_t cand = 0;
-    int dmin = 7;
+    uint32_t c6m = 0;
+    int d6 = 7;
 #pragma unroll
     for (int i = 0; i < 7; ++i) {
         const int od = __builtin_popcountll((code >> (6 * i)) & 63ull);
-        if (od < dmin) {
-            dmin = od;
-            cand = 0;
+        if (od < d6) {
+            d6 = od;
+            c6m = 0;
         }
-        if (od == dmin) cand |= 1u << i;
+        if (od == d6) c6m |= 1u << i;
     }
-    const int per = fact[dmin] * fact[6 - dmin];
-    const int total = __builtin_popcount(cand) * per;
     Code7 best = kNoCode;
-    for (int t = lane_id(); t < total; t += kWave) {
-        const uint32_t c = nth_bit(cand, t / per);
-        int r = t % per;
-        // out-neighbours of c (row c, column r -> vertex r + [r >= c])
-        const uint32_t row = (uint32_t)((code >> (6 * c)) & 63ull);
-        const uint32_t lowc = (1u << c) - 1u;
-        const uint32_t outn = (row & lowc) | ((row & ~lowc) << 1);
-        const uint32_t restm = 0x7Fu & ~outn & ~(1u << c);
-        // sigma(v) = new position of vertex v, as 4-bit fields
-        uint32_t sigma = 6u << (4 * c);
-        int q = r / fact[6 - dmin];
-        r -= q * fact[6 - dmin];
-        uint32_t avail = outn;
-        for (int pos = 0; pos < dmin; ++pos) {
-            const int f = fact[dmin - 1 - pos];
-            const int d = q / f;
-            q -= d * f;
-            const uint32_t v = nth_bit(avail, d);
-            sigma |= (uint32_t)pos << (4 * v);
-            avail &= ~(1u << v);
+    // one candidate for position 6 at a time (wave-uniform)
+    for (uint32_t left6 = c6m; left6; left6 &= left6 - 1u) {
+        const uint32_t c6 = (uint32_t)__builtin_ctz(left6);
+        // d6 = 0: the candidates for position 5 and their out-degree d5
+        uint32_t c5m = 0;
+        int d5 = 0, cnt = fact[d6] * fact[6 - d6];
+        if (d6 == 0) {
+            int key_min = 64;
+            for (uint32_t v = 0; v < 7; ++v) {
+                if (v == c6) continue;
+                const uint32_t on = out_nbrs7(code, v);
+                const int key = (int)(((on >> c6) & 1u) << 3) + __builtin_popcount(on & ~(1u << c6));
+                if (key < key_min) {
+                    key_min = key;
+                    c5m = 0;
+                }
+                if (key == key_min) c5m |= 1u << v;
+            }
+            d5 = key_min & 7;
+            cnt = __builtin_popcount(c5m) * fact[d5] * fact[5 - d5];
         }
-        avail = restm;
-        for (int pos = dmin; pos < 6; ++pos) {
-            const int f = fact[5 - pos];
-            const int d = r / f;
-            r -= d * f;
-            const uint32_t v = nth_bit(avail, d);
-            sigma |= (uint32_t)pos << (4 * v);
-            avail &= ~(1u << v);
+        for (int t = lane_id(); t < cnt; t += kWave) {
+            uint32_t sigma = 6u << (4 * c6);
+            int r = t;
+            if (d6 > 0) {
+                const uint32_t on = out_nbrs7(code, c6);
+                const int q = r / fact[6 - d6];
+                place7(sigma, on, 0, d6, q);
+                place7(sigma, 0x7Fu & ~on & ~(1u << c6), d6, 6 - d6, r - q * fact[6 - d6]);
+            } else {
+                const int per = fact[d5] * fact[5 - d5];
+                const uint32_t c5 = nth_bit(c5m, r / per);
+                r %= per;
+                sigma |= 5u << (4 * c5);
+                const uint32_t on = out_nbrs7(code, c5) & ~(1u << c6);
+                const int q = r / fact[5 - d5];
+                place7(sigma, on, 0, d5, q);
+                place7(sigma, 0x7Fu & ~on & ~(1u << c6) & ~(1u << c5), d5, 5 - d5,
+                       r - q * fact[5 - d5]);
+            }
+            Code7 cc = 0, rest = code;
+            while (rest) {
+                const int b = __builtin_ctzll(rest);
+                rest &= rest - 1;
+                const int i = b / 6, rr = b - 6 * i;
+                const int j = rr + (rr >= i ? 1 : 0);
+                cc |= 1ull << bit7((int)((sigma >> (4 * i)) & 15u), (int)((sigma >> (4 * j)) & 15u));
+            }
+            best = cc < best ? cc : best;
         }
-        Code7 cc = 0, rest = code;
-        while (rest) {
-            const int b = __builtin_ctzll(rest);
-            rest &= rest - 1;
-            const int i = b / 6, rr = b - 6 * i;
-            const int j = rr + (rr >= i ? 1 : 0);
-            cc |= 1ull << bit7((int)((sigma >> (4 * i)) & 15u), (int)((sigma >> (4 * j)) & 15u));
-        }
-        best = cc < best ? cc : best;
     }
 #pragma unroll
     for (int off = kWave / 2; off > 0; off >>= 1) {
@@ -169,7 +205,7 @@ __device__ Code7 canon7_wave(Code7 code)
 // Move the wave's pending counts to its graph's class table: canonical code
 // from the cache (or computed and entered), count added; hash emptied.
 template <int V>
-__device__ void flush7(EnumState<7, V> &s, K7Wave &w, const K7Tables &t)
+__device__ __forceinline__ void flush7(EnumState<7, V> &s, K7Wave &w, const K7Tables &t)
 {
     __syncthreads();
     const int lane = lane_id();
@@ -252,7 +288,7 @@ __device__ void flush7(EnumState<7, V> &s, K7Wave &w, const K7Tables &t)
 // add n to the pending count of code for every lane with `mine` set; a full
 // hash is flushed and the inserts that found no slot are tried again
 template <int V>
-__device__ void hash7_insert(EnumState<7, V> &s, K7Wave &w, const K7Tables &t, bool mine, Code7 code,
+__device__ __forceinline__ void hash7_insert(EnumState<7, V> &s, K7Wave &w, const K7Tables &t, bool mine, Code7 code,
                              uint32_t n)
 {
     bool pending = mine;
@@ -280,7 +316,7 @@ __device__ void hash7_insert(EnumState<7, V> &s, K7Wave &w, const K7Tables &t, b
 
 // count one code per valid lane (lanes sharing the first lane's code merged)
 template <int V>
-__device__ void count7(EnumState<7, V> &s, K7Wave &w, const K7Tables &t, bool valid, Code7 code)
+__device__ __forceinline__ void count7(EnumState<7, V> &s, K7Wave &w, const K7Tables &t, bool valid, Code7 code)
 {
     const int lane = lane_id();
     const unsigned long long act = __ballot(valid);
@@ -297,7 +333,7 @@ __device__ void count7(EnumState<7, V> &s, K7Wave &w, const K7Tables &t, bool va
 
 // count each valid lane's code with weight -1 (merged like count7)
 template <int V>
-__device__ void uncount7(EnumState<7, V> &s, K7Wave &w, const K7Tables &t, bool valid, Code7 code)
+__device__ __forceinline__ void uncount7(EnumState<7, V> &s, K7Wave &w, const K7Tables &t, bool valid, Code7 code)
 {
     const int lane = lane_id();
     const unsigned long long act = __ballot(valid);
@@ -357,7 +393,7 @@ __device__ __forceinline__ Code7 from_lane64(Code7 v, int l)
 // E[l], its code bits for positions 5 and 6 and its list row; a child of
 // degree >= kRowMin is scanned alone.
 template <int V>
-__device__ void last_two7_cells(EnumState<7, V> &s, K7Wave &w7, const K7Tables &t, const int (&st)[6],
+__device__ __forceinline__ void last_two7_cells(EnumState<7, V> &s, K7Wave &w7, const K7Tables &t, const int (&st)[6],
                                 const int (&rem)[5], int e, Code7 code, int jlo)
 {
     constexpr int B_WU = bit7(5, 6), B_UW = bit7(6, 5);
@@ -523,7 +559,7 @@ __device__ void last_two7_cells(EnumState<7, V> &s, K7Wave &w7, const K7Tables &
 // j > i (arc w - u from the bit matrices) and (B) u an exclusive neighbour
 // of w (its list entry gives the arc).  Same split as the k <= 6 kernel.
 template <int V>
-__device__ void last_two7(EnumState<7, V> &s, K7Wave &w7, const K7Tables &t, const int (&st)[6],
+__device__ __forceinline__ void last_two7(EnumState<7, V> &s, K7Wave &w7, const K7Tables &t, const int (&st)[6],
                           Code7 code, int jlo, int jhi)
 {
     constexpr int NQ = 5;
@@ -637,7 +673,7 @@ __device__ void last_two7(EnumState<7, V> &s, K7Wave &w7, const K7Tables &t, con
 
 // node with members s_0..s_D: children jlo..jhi-1 of its extension list
 template <int D, int V>
-__device__ void visit7(EnumState<7, V> &s, K7Wave &w7, const K7Tables &t, const int (&st)[6],
+__device__ __forceinline__ void visit7(EnumState<7, V> &s, K7Wave &w7, const K7Tables &t, const int (&st)[6],
                        Code7 code, int jlo, int jhi)
 {
     if constexpr (D == 4) {
@@ -681,7 +717,7 @@ __device__ void visit7(EnumState<7, V> &s, K7Wave &w7, const K7Tables &t, const 
 }
 
 template <int V>
-__device__ void run_unit7(EnumState<7, V> &s, K7Wave &w7, const K7Tables &t, int v, int i,
+__device__ __forceinline__ void run_unit7(EnumState<7, V> &s, K7Wave &w7, const K7Tables &t, int v, int i,
                           uint32_t range)
 {
     s.root = v;
