@@ -359,7 +359,9 @@ void mk_batch_free(mk_batch *b);
    giving the size needed.  t: a built table (k = 3..6).  d_hist: device
    array of t's num_classes uint64, overwritten with the histogram.  Runs on
    `stream` (NULL: the context's stream) and blocks until done, then checks
-   the device-side status.  Calls through one context are serialised; calls
+   the device-side status; work the caller queued on another stream that
+   writes d_hist must be ordered before the call (else it can overwrite the
+   result).  Calls through one context are serialised; calls
    from two contexts on one device at the same time share the array and
    race. */
 int mk_count_static(mk_ctx *ctx, const mk_graph *g, const mk_table *t, uint64_t *d_hist,

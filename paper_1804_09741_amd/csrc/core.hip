@@ -567,6 +567,9 @@ __global__ __launch_bounds__(kWave) void core_kernel(const DevGraph *graphs, con
     for (int i = lane_id(); i < kAggWords<K>; i += kWave) c.agg[i] = 0u;
     init_state<K>(s, base, lay, cfg, counters, table, num_classes);
     s.class_keys = true;
+    // flushed at three quarters full: class ids spread evenly, so few
+    // inserts probe far, and each flush then carries more of the counts
+    s.hlimit = (int)((s.hmask >> 1) + (s.hmask >> 2));
     for_each_unit<K>(s, graphs, units, unit_cap, unit_end, counters, hist_base, cfg,
                      [&](int v, int i, uint32_t range) { run_core_unit<K>(s, c, v, i, range); });
 }
@@ -592,11 +595,14 @@ __global__ void core_divide_kernel(unsigned long long *hist, uint32_t num_classe
     }
 }
 
-// Per-wave hash slots of the core kernel: its keys are class ids, and a
-// bigger hash absorbs more of the k = 5 classes before a flush (measured:
-// k = 5 batch 36.0 / 26.9 / 25.2 ms at 128 / 256 / 512 slots).
+// Per-wave hash slots of the core kernel (keys are class ids).  Its LDS
+// sets how many waves a CU holds, and the kernel's speed follows that
+// count, so the hash trades capacity for waves: on the k = 5 batch 256
+// slots flushed at three quarters (8.0 KB of LDS a wave, 20 waves a CU)
+// take 23.1 ms, 512 slots flushed at half (10.1 KB, 16 waves) 23.4 ms,
+// 256 at half 27.5 ms, 1024 at half 33 ms.
 #ifndef MK_CORE_HASH_BITS_K5
-#define MK_CORE_HASH_BITS_K5 9
+#define MK_CORE_HASH_BITS_K5 8
 #endif
 int core_hash_bits(int k) { return k == 5 ? MK_CORE_HASH_BITS_K5 : kHashBits; }
 

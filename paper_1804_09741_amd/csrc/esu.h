@@ -68,8 +68,8 @@ constexpr int kScratchWords = 3 * kWave;
 #endif
 
 // Per-wave hash of pending (code, count) pairs; flushed to the histogram when
-// half full, at the end of a unit once a quarter full, on a graph switch and
-// at exit.
+// half full (the core kernel: three quarters), at the end of a unit once a
+// quarter full, on a graph switch and at exit.
 constexpr int kHashBits = MK_HASH_BITS;  // the enumeration kernel's; see EnumConfig
 constexpr int kHashProbes = 8;
 constexpr uint32_t kEmpty = 0xFFFFFFFFu;
@@ -132,6 +132,7 @@ struct EnumState {
     int hshift;                 // 32 - log2(hash slots)
     uint32_t hmask;             // hash slots - 1
     int hused;                  // keys in the hash (wave-uniform)
+    int hlimit;                 // flush once hused exceeds this
     uint32_t hpending;          // subgraphs pending in the hash (wave-uniform)
     bool class_keys;            // hash keys are class ids, not codes
     uint32_t flags;             // kDebug* bits
@@ -320,7 +321,7 @@ __device__ __forceinline__ void hash_insert(EnumState<K, V> &s, bool mine, uint3
         }
     }
     s.hused += __popcll(__ballot(fresh));
-    if (s.hused > (int)(s.hmask >> 1) || s.hpending >= kPendingMax ||
+    if (s.hused > s.hlimit || s.hpending >= kPendingMax ||
         (s.flags & kDebugFlushAlways))
         flush_hash<K>(s);
 }
@@ -386,6 +387,7 @@ __device__ __forceinline__ void init_state(EnumState<K, V> &s, char *base, const
     s.hmask = (1u << cfg.hash_bits) - 1u;
     s.hcnt = s.hkey + s.hmask + 1;
     s.hused = 0;
+    s.hlimit = (int)(s.hmask >> 1);
     s.hpending = 0;
     s.class_keys = false;
     for (int i = lane_id(); i <= (int)s.hmask; i += kWave) {

@@ -177,6 +177,7 @@ def test_torch_buffer_and_stream(ctx):
         b = ctx.batch([gr], t)
         out = torch.zeros((1, t.num_classes), dtype=torch.int64, device="cuda:0")
         s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())  # the zeros land first
         b.run(out, stream=s)
         s.synchronize()
         h = out.cpu().numpy().astype(np.uint64)

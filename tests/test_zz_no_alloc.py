@@ -15,7 +15,9 @@ pytestmark = pytest.mark.gpu
 def _static(ctx, g, t):
     import torch
     d = torch.full((t.num_classes,), 7, dtype=torch.int64, device="cuda:0")
-    ctx.count_static(g, t, d)
+    # on the stream that wrote the 7s: the library's clear and counts follow
+    # them (on another stream the fill could land after the counts)
+    ctx.count_static(g, t, d, torch.cuda.current_stream())
     return d.cpu().numpy().astype(np.uint64)
 
 
