@@ -56,14 +56,25 @@ constexpr int kAggCells = K == 6 ? 12 : 16;
 template <int K>
 constexpr int kAggWords = 3 * kAggCells<K> * (kAggCells<K> + 1) / 2;
 
+// Extension segments the core walk fills: those of members 0..k-4 (a
+// core's last member only marks).
+template <int K>
+constexpr int kCoreSegs = K - 3;
+// The arc scan keeps each of its 64 vertices' id beside its mark: in one
+// word while marks are 16-bit (k <= 5; LDS marks mean ids below 8,192, in
+// the high half), else in 64 words of their own.
+template <int K>
+constexpr bool kPackedUid = sizeof(MarkT<K>) == 2;
+
 // LDS of the core kernel beyond the enumeration layout: cell counts (u32),
-// the list of non-empty cells and each cell's list position (u8), 64 vertex
-// ids for the arc scan, and the arc-pair table.
+// the list of non-empty cells and each cell's list position (u8), the arc
+// scan's vertex ids (k = 6), and the arc-pair table.  A wave's LDS sets how
+// many waves a CU holds, and the kernel's speed follows that count.
 struct CoreLds {
     uint32_t *cnt;
     uint8_t *list;
     uint8_t *pos;
-    uint32_t *uid;
+    uint32_t *uid;  // null when packed with the marks
     uint32_t *agg;
     uint32_t *ap;  // global: this workgroup's arc list of the current parent
 };
@@ -72,7 +83,8 @@ __host__ __device__ inline int core_extra_bytes(int k)
 {
     const int cells = 1 << (2 * (k - 2));
     const int agg_cells = k == 6 ? 12 : 16;
-    return 4 * cells + 2 * ((cells + 3) & ~3) + 4 * kWave + 4 * 3 * agg_cells * (agg_cells + 1) / 2;
+    return 4 * cells + 2 * ((cells + 3) & ~3) + (k >= 6 ? 4 * kWave : 0) +
+           4 * 3 * agg_cells * (agg_cells + 1) / 2;
 }
 
 // relation vector of a mark: bit 2d = arc s_d -> u, bit 2d+1 = arc u -> s_d
@@ -226,9 +238,13 @@ __device__ __forceinline__ void scan_taken(EnumState<K> &s, const CoreLds &c,
         }
         const int tot = uniform(__shfl(incl, kWave - 1, kWave));
         pre_deg[lane] = (uint32_t)incl;
-        start[lane] = (uint32_t)row;
-        cw[lane] = mu;
-        c.uid[lane] = (uint32_t)u;
+        start[lane] = (uint32_t)(row - (incl - deg));  // flat entry f at start + f
+        if constexpr (kPackedUid<K>) {
+            cw[lane] = mu | ((uint32_t)u << 16);
+        } else {
+            cw[lane] = mu;
+            c.uid[lane] = (uint32_t)u;
+        }
         __syncthreads();
         for (int fb = 0; fb < tot; fb += kWave) {
             const int f = fb + lane;
@@ -241,12 +257,17 @@ __device__ __forceinline__ void scan_taken(EnumState<K> &s, const CoreLds &c,
 #pragma unroll
                 for (int step = kWave / 2; step > 0; step >>= 1)
                     lo += ((int)pre_deg[lo + step - 1] <= f) ? step : 0;
-                const int before = lo ? (int)pre_deg[lo - 1] : 0;
-                const uint32_t ent = s.uadj[start[lo] + (uint32_t)(f - before)];
+                const uint32_t ent = s.uadj[start[lo] + (uint32_t)f];
                 v = (int)(ent >> 2);
                 mv = s.mark[v];
-                uu = (int)c.uid[lo];
-                m_u = cw[lo];
+                const uint32_t w = cw[lo];
+                if constexpr (kPackedUid<K>) {
+                    uu = (int)(w >> 16);
+                    m_u = w & 0xFFFFu;
+                } else {
+                    uu = (int)c.uid[lo];
+                    m_u = w;
+                }
                 t = ent & 3u;
                 edge = mv != 0u && !(mv & FLAG) && keep(v, uu, mv);
             }
@@ -554,14 +575,15 @@ __global__ __launch_bounds__(kWave) void core_kernel(const DevGraph *graphs, con
 {
     extern __shared__ uint32_t lds[];
     EnumState<K> s;
-    const LdsLayout lay = lds_layout(K, cfg.max_n, cfg.seg_cap, cfg.hash_bits);
+    const LdsLayout lay = lds_layout(K, cfg.max_n, cfg.seg_cap, cfg.hash_bits, false, kCoreSegs<K>);
     char *base = reinterpret_cast<char *>(lds);
     CoreLds c;
     c.cnt = reinterpret_cast<uint32_t *>(base + lay.total);
     c.list = reinterpret_cast<uint8_t *>(c.cnt + kCells<K>);
     c.pos = c.list + ((kCells<K> + 3) & ~3);
-    c.uid = reinterpret_cast<uint32_t *>(c.pos + ((kCells<K> + 3) & ~3));
-    c.agg = c.uid + kWave;
+    uint32_t *after_pos = reinterpret_cast<uint32_t *>(c.pos + ((kCells<K> + 3) & ~3));
+    c.uid = kPackedUid<K> ? nullptr : after_pos;
+    c.agg = kPackedUid<K> ? after_pos : after_pos + kWave;
     c.ap = cfg.wave_scratch ? cfg.wave_scratch + (size_t)blockIdx.x * kParentArcCap : nullptr;
     for (int i = lane_id(); i < kCells<K>; i += kWave) c.cnt[i] = 0u;
     for (int i = lane_id(); i < kAggWords<K>; i += kWave) c.agg[i] = 0u;
@@ -598,9 +620,9 @@ __global__ void core_divide_kernel(unsigned long long *hist, uint32_t num_classe
 // Per-wave hash slots of the core kernel (keys are class ids).  Its LDS
 // sets how many waves a CU holds, and the kernel's speed follows that
 // count, so the hash trades capacity for waves: on the k = 5 batch 256
-// slots flushed at three quarters (8.0 KB of LDS a wave, 20 waves a CU)
-// take 23.1 ms, 512 slots flushed at half (10.1 KB, 16 waves) 23.4 ms,
-// 256 at half 27.5 ms, 1024 at half 33 ms.
+// slots flushed at three quarters (7.5 KB of LDS a wave) take 21.2 ms, 512
+// slots 23.9 ms and 128 slots 28.2 ms at three quarters; flushed at half,
+// 256 slots took 27.5 ms.
 #ifndef MK_CORE_HASH_BITS_K5
 #define MK_CORE_HASH_BITS_K5 8
 #endif
@@ -608,7 +630,7 @@ int core_hash_bits(int k) { return k == 5 ? MK_CORE_HASH_BITS_K5 : kHashBits; }
 
 int core_lds_bytes(int k, int max_n, int seg_cap)
 {
-    return lds_layout(k, max_n, seg_cap, core_hash_bits(k)).total + core_extra_bytes(k);
+    return lds_layout(k, max_n, seg_cap, core_hash_bits(k), false, k - 3).total + core_extra_bytes(k);
 }
 
 template <int K>

@@ -193,6 +193,8 @@ __device__ void last_two_small(EnumState<K, V> &s, const int (&st)[K - 1],
     const int totB = uniform(__shfl(incl, kWave - 1, kWave));
     uint32_t *pre = s.scratch;
     pre[lane] = (uint32_t)incl;
+    // flat entry f of this lane's list sits at rowb + f
+    const int rowb = row - (incl - deg);
     __syncthreads();
     const int mm = e - jlo;
     const int npairs = mm * (mm - 1) / 2;
@@ -217,13 +219,13 @@ __device__ void last_two_small(EnumState<K, V> &s, const int (&st)[K - 1],
             for (int step = kWave / 2; step > 0; step >>= 1)
                 lo += ((int)pre[lo + step - 1] <= fb) ? step : 0;
             src1 = lo;
-            off = fb - (lo ? (int)pre[lo - 1] : 0);
+            off = fb;
         }
         const uint32_t w = from_lane(vtx, src1);
         const uint32_t u2 = from_lane(vtx, src2);
         const uint32_t c1 = from_lane(cb1, src1);
         const uint32_t c2 = from_lane(cb2, src2);
-        const int r1 = (int)from_lane((uint32_t)row, src1);
+        const int r1 = (int)from_lane((uint32_t)rowb, src1);
         uint32_t c = 0;
         if (pair) {
             const uint32_t t = pair_type<K>(s, w, u2);
@@ -328,6 +330,8 @@ __device__ void last_two_cells(EnumState<K, V> &s, const int (&st)[K - 1],
     const int totB = uniform(__shfl(incl, kWave - 1, kWave));
     uint32_t *pre = s.scratch;
     pre[lane] = (uint32_t)incl;
+    // flat entry f of this lane's list sits at rowb + f
+    const int rowb = row - (incl - deg);
     __syncthreads();
     // the short lists, flat: Part B entries and arcs inside E
     for (int base = 0; base < totB; base += kWave) {
@@ -340,10 +344,10 @@ __device__ void last_two_cells(EnumState<K, V> &s, const int (&st)[K - 1],
             for (int step = kWave / 2; step > 0; step >>= 1)
                 lo += ((int)pre[lo + step - 1] <= f) ? step : 0;
             src1 = lo;
-            off = f - (lo ? (int)pre[lo - 1] : 0);
+            off = f;
         }
         // the permutes run with every lane active
-        const int r1 = (int)from_lane((uint32_t)row, src1);
+        const int r1 = (int)from_lane((uint32_t)rowb, src1);
         const uint32_t c1 = from_lane(cb1, src1);
         bool bv = false, arc = false;
         uint32_t t = 0;
@@ -572,7 +576,7 @@ __device__ void last_two(EnumState<K, V> &s, const int (&st)[K - 1], uint32_t co
         }
         const int tot = uniform(__shfl(incl, kWave - 1, kWave));
         pre[lane] = (uint32_t)incl;
-        start[lane] = (uint32_t)row;
+        start[lane] = (uint32_t)(row - (incl - deg));  // flat entry f at start + f
         cw[lane] = wcode;
         __syncthreads();
         for (int fb = 0; fb < tot; fb += kWave) {
@@ -585,8 +589,7 @@ __device__ void last_two(EnumState<K, V> &s, const int (&st)[K - 1], uint32_t co
 #pragma unroll
                 for (int step = kWave / 2; step > 0; step >>= 1)
                     lo += ((int)pre[lo + step - 1] <= f) ? step : 0;
-                const int before = lo ? (int)pre[lo - 1] : 0;
-                const uint32_t ent = s.uadj[start[lo] + (uint32_t)(f - before)];
+                const uint32_t ent = s.uadj[start[lo] + (uint32_t)f];
                 const int u = (int)(ent >> 2);
                 const uint32_t t = ent & 3u;
                 valid = u > s.root && s.mark[u] == 0u;

@@ -92,9 +92,9 @@ struct LdsLayout {
 };
 
 __host__ __device__ inline LdsLayout lds_layout(int k, int max_n, int seg_cap, int hash_bits,
-                                                bool global_marks = false)
+                                                bool global_marks = false, int segs = -1)
 {
-    const int segs = k == 3 ? 2 : k - 2;
+    if (segs < 0) segs = k == 3 ? 2 : k - 2;
     const int mark_bytes = global_marks ? 0 : (((k <= 5 ? 2 : 4) * max_n + 3) & ~3);
     const int seg_bytes = ((global_marks ? 4 : 2) * segs * seg_cap + 3) & ~3;
     LdsLayout l;

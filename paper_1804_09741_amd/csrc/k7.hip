@@ -464,6 +464,8 @@ __device__ __forceinline__ void last_two7_cells(EnumState<7, V> &s, K7Wave &w7, 
     const int totB = uniform(__shfl(incl, kWave - 1, kWave));
     uint32_t *pre = s.scratch;
     pre[lane] = (uint32_t)incl;
+    // flat entry f of this lane's list sits at rowb + f
+    const int rowb = row - (incl - deg);
     __syncthreads();
     // the short lists, flat: exclusive neighbours and arcs inside E
     for (int base = 0; base < totB; base += kWave) {
@@ -476,10 +478,10 @@ __device__ __forceinline__ void last_two7_cells(EnumState<7, V> &s, K7Wave &w7, 
             for (int step = kWave / 2; step > 0; step >>= 1)
                 lo += ((int)pre[lo + step - 1] <= f) ? step : 0;
             src1 = lo;
-            off = f - (lo ? (int)pre[lo - 1] : 0);
+            off = f;
         }
         // the permutes run with every lane active
-        const int r1 = (int)from_lane7((uint32_t)row, src1);
+        const int r1 = (int)from_lane7((uint32_t)rowb, src1);
         const Code7 c1 = from_lane64(cb1, src1);
         bool bv = false, arc = false;
         uint32_t tt = 0;
@@ -641,7 +643,7 @@ __device__ __forceinline__ void last_two7(EnumState<7, V> &s, K7Wave &w7, const 
         }
         const int tot = uniform(__shfl(incl, kWave - 1, kWave));
         pre[lane] = (uint32_t)incl;
-        start[lane] = (uint32_t)row;
+        start[lane] = (uint32_t)(row - (incl - deg));  // flat entry f at start + f
         __syncthreads();
         for (int fb = 0; fb < tot; fb += kWave) {
             const int f = fb + lane;
@@ -658,8 +660,7 @@ __device__ __forceinline__ void last_two7(EnumState<7, V> &s, K7Wave &w7, const 
                              (uint32_t)__builtin_amdgcn_ds_bpermute(lo << 2, (int)(uint32_t)wcode);
             Code7 c = 0;
             if (valid) {
-                const int before = lo ? (int)pre[lo - 1] : 0;
-                const uint32_t ent = s.uadj[start[lo] + (uint32_t)(f - before)];
+                const uint32_t ent = s.uadj[start[lo] + (uint32_t)f];
                 const int u = (int)(ent >> 2);
                 const uint32_t tt = ent & 3u;
                 valid = u > s.root && s.mark[u] == 0u;
