@@ -87,16 +87,16 @@ __host__ __device__ inline int core_extra_bytes(int k)
            4 * 3 * agg_cells * (agg_cells + 1) / 2;
 }
 
-// relation vector of a mark: bit 2d = arc s_d -> u, bit 2d+1 = arc u -> s_d
+// relation vector of a mark: bits 0..R-1 = arcs u -> s_0..s_{R-1} (the
+// mark's out bits, already adjacent), bits R..2R-1 = arcs s_0..s_{R-1} -> u
+// (its in bits, at stride k-1)
 template <int K>
 __device__ __forceinline__ uint32_t cell_of(uint32_t m)
 {
-    uint32_t c = 0;
+    constexpr int R = kCoreR<K>;
+    uint32_t c = (m >> EnumState<K>::OUTB) & ((1u << R) - 1u);
 #pragma unroll
-    for (int d = 0; d < kCoreR<K>; ++d) {
-        c |= ((m >> (d * (K - 1))) & 1u) << (2 * d);
-        c |= ((m >> (EnumState<K>::OUTB + d)) & 1u) << (2 * d + 1);
-    }
+    for (int d = 0; d < R; ++d) c |= ((m >> (d * (K - 1))) & 1u) << (R + d);
     return c;
 }
 
@@ -104,12 +104,10 @@ __device__ __forceinline__ uint32_t cell_of(uint32_t m)
 template <int K>
 __device__ __forceinline__ uint32_t mark_of_cell(uint32_t c)
 {
-    uint32_t m = 0;
+    constexpr int R = kCoreR<K>;
+    uint32_t m = (c & ((1u << R) - 1u)) << EnumState<K>::OUTB;
 #pragma unroll
-    for (int d = 0; d < kCoreR<K>; ++d) {
-        m |= ((c >> (2 * d)) & 1u) << (d * (K - 1));
-        m |= ((c >> (2 * d + 1)) & 1u) << (EnumState<K>::OUTB + d);
-    }
+    for (int d = 0; d < R; ++d) m |= ((c >> (R + d)) & 1u) << (d * (K - 1));
     return m;
 }
 
