@@ -448,8 +448,47 @@ __device__ void core_node(EnumState<K> &s, const CoreLds &c, const int (&mem)[K]
                    code_bits<K>(mark_of_cell<K>(cz), K - 1);
             valid = w > 0;
         }
-        hash_insert<K>(s, valid, class_of<K>(s, valid, code), w);
-        if (agg && __ballot(e1 | e2 | e3)) {
+        if (!(agg && __ballot(e1 | e2 | e3))) {
+            hash_insert<K>(s, valid, class_of<K>(s, valid, code), w);
+            continue;
+        }
+        // up to four (code, count) items a lane -- the pair less its arcs,
+        // and its arc pairs by type -- compacted through the scratch into
+        // one insert when they fit a wave
+        const uint32_t nl = (valid ? 1u : 0u) + (e1 ? 1u : 0u) + (e2 ? 1u : 0u) + (e3 ? 1u : 0u);
+        uint32_t incl = nl;
+#pragma unroll
+        for (int d = 1; d < kWave; d <<= 1) {
+            const uint32_t o = __shfl_up(incl, d, kWave);
+            if (lane >= d) incl += o;
+        }
+        const int items = uniform((int)__shfl(incl, kWave - 1, kWave));
+        if (items <= kWave) {
+            uint32_t *qk = s.scratch, *qn = s.scratch + kWave;
+            uint32_t at = incl - nl;
+            if (valid) {
+                qk[at] = code;
+                qn[at++] = w;
+            }
+            if (e1) {
+                qk[at] = code | (1u << B_YZ);
+                qn[at++] = e1;
+            }
+            if (e2) {
+                qk[at] = code | (1u << B_ZY);
+                qn[at++] = e2;
+            }
+            if (e3) {
+                qk[at] = code | (1u << B_YZ) | (1u << B_ZY);
+                qn[at] = e3;
+            }
+            __syncthreads();
+            bool mine = lane < items;
+            const uint32_t ic = mine ? qk[lane] : 0u, in = mine ? qn[lane] : 0u;
+            __syncthreads();
+            hash_insert<K>(s, mine, class_of<K>(s, mine, ic), in);
+        } else {
+            hash_insert<K>(s, valid, class_of<K>(s, valid, code), w);
             bool v1 = e1 > 0, v2 = e2 > 0, v3 = e3 > 0;
             const uint32_t i1 = class_of<K>(s, v1, code | (1u << B_YZ));
             const uint32_t i2 = class_of<K>(s, v2, code | (1u << B_ZY));
