@@ -626,9 +626,12 @@ __global__ __launch_bounds__(kWave) void core_kernel(const DevGraph *graphs, con
     for (int i = lane_id(); i < kAggWords<K>; i += kWave) c.agg[i] = 0u;
     init_state<K>(s, base, lay, cfg, counters, table, num_classes);
     s.class_keys = true;
-    // flushed at three quarters full: class ids spread evenly, so few
-    // inserts probe far, and each flush then carries more of the counts
+    // flushed at three quarters full, and not at the end of a unit: class
+    // ids spread evenly, so few inserts probe far, and each flush then
+    // carries more of the counts (the graph's next units add to the same
+    // classes)
     s.hlimit = (int)((s.hmask >> 1) + (s.hmask >> 2));
+    s.hunit = INT_MAX;
     for_each_unit<K>(s, graphs, units, unit_cap, unit_end, counters, hist_base, cfg,
                      [&](int v, int i, uint32_t range) { run_core_unit<K>(s, c, v, i, range); });
 }

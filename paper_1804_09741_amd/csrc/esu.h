@@ -69,7 +69,7 @@ constexpr int kScratchWords = 3 * kWave;
 
 // Per-wave hash of pending (code, count) pairs; flushed to the histogram when
 // half full (the core kernel: three quarters), at the end of a unit once a
-// quarter full, on a graph switch and at exit.
+// quarter full (not in the core kernel), on a graph switch and at exit.
 constexpr int kHashBits = MK_HASH_BITS;  // the enumeration kernel's; see EnumConfig
 constexpr int kHashProbes = 8;
 constexpr uint32_t kEmpty = 0xFFFFFFFFu;
@@ -133,6 +133,7 @@ struct EnumState {
     uint32_t hmask;             // hash slots - 1
     int hused;                  // keys in the hash (wave-uniform)
     int hlimit;                 // flush once hused exceeds this
+    int hunit;                  //   or, after a unit, exceeds this
     uint32_t hpending;          // subgraphs pending in the hash (wave-uniform)
     bool class_keys;            // hash keys are class ids, not codes
     uint32_t flags;             // kDebug* bits
@@ -388,6 +389,7 @@ __device__ __forceinline__ void init_state(EnumState<K, V> &s, char *base, const
     s.hcnt = s.hkey + s.hmask + 1;
     s.hused = 0;
     s.hlimit = (int)(s.hmask >> 1);
+    s.hunit = (int)((s.hmask + 1) >> 2);
     s.hpending = 0;
     s.class_keys = false;
     for (int i = lane_id(); i <= (int)s.hmask; i += kWave) {
@@ -478,7 +480,7 @@ __device__ __forceinline__ void for_each_unit(EnumState<K, V> &s, const DevGraph
             s.hist = hist_base + (size_t)gi * s.num_classes;
         },
         [&] {
-            if (s.hused > (int)((s.hmask + 1) >> 2)) flush_hash<K>(s);
+            if (s.hused > s.hunit) flush_hash<K>(s);
         });
     if (s.hused) flush_hash<K>(s);
 }
