@@ -189,7 +189,9 @@ static EnumConfig enum_config(const mk_batch *b)
     c.chunk = (uint32_t)std::max(b->opts.units_per_grab, 0);
     c.wave_scratch = b->d_wave_scratch;
     c.hash_bits = b->method == MK_METHOD_CORES ? core_hash_bits(b->k) : enum_hash_bits(b->k);
-    c.variant = b->variant;
+    // the test hooks of the hash run in the kernels built with them
+    c.variant = b->variant |
+                (b->k <= 6 && (b->debug_flags & (kDebugNoHash | kDebugFlushAlways)) ? kVarDebug : 0);
     c.marks = b->d_marks;
     c.mark_stride = b->mark_stride;
     return c;

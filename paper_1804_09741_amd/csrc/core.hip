@@ -123,8 +123,8 @@ __device__ __forceinline__ uint32_t lower_members(int d)
 }
 
 // s_D := x for the last member of a core: marks only (no extension segment)
-template <int K, int D>
-__device__ __forceinline__ void push_marks(EnumState<K> &s, int x)
+template <int K, int D, int V>
+__device__ __forceinline__ void push_marks(EnumState<K, V> &s, int x)
 {
     const int lane = lane_id();
     const int r0 = uniform(s.urow[x]);
@@ -141,8 +141,8 @@ __device__ __forceinline__ void push_marks(EnumState<K> &s, int x)
 }
 
 // push_marks<D>(x) keeping the list for pop_held (see push_held)
-template <int K, int D>
-__device__ __forceinline__ Held push_marks_held(EnumState<K> &s, int x)
+template <int K, int D, int V>
+__device__ __forceinline__ Held push_marks_held(EnumState<K, V> &s, int x)
 {
     const int lane = lane_id();
     const int r0 = uniform(s.urow[x]);
@@ -169,8 +169,8 @@ __device__ __forceinline__ Held push_marks_held(EnumState<K> &s, int x)
 // stand for many differently labelled k-sets, so their codes rarely repeat
 // while their classes do).  A code outside the connected classes is a
 // device error and is dropped.
-template <int K>
-__device__ __forceinline__ uint32_t class_of(EnumState<K> &s, bool &valid, uint32_t code)
+template <int K, int V>
+__device__ __forceinline__ uint32_t class_of(EnumState<K, V> &s, bool &valid, uint32_t code)
 {
     uint32_t id = 0;
     if (valid) {
@@ -205,8 +205,8 @@ __device__ __forceinline__ int member_entry(const int (&pre)[R + 1], const int (
 // member): every entry of u's own list is handed to
 // arc(edge, u, v, mark u, mark v, arc type), edge = v has a mark, is not a
 // member, and keep(v, u, mark v).  Padding lanes get edge = false.
-template <int K, int NM, typename Keep, typename Arc>
-__device__ __forceinline__ void scan_taken(EnumState<K> &s, const CoreLds &c,
+template <int K, int NM, int V, typename Keep, typename Arc>
+__device__ __forceinline__ void scan_taken(EnumState<K, V> &s, const CoreLds &c,
                                            const int (&pre)[NM + 1], const int (&r0)[NM],
                                            int from, Keep keep, Arc arc)
 {
@@ -278,8 +278,8 @@ __device__ __forceinline__ void scan_taken(EnumState<K> &s, const CoreLds &c,
 // The arc pairs (u, v), u < v, inside adj(P) for the parent P = mem[0..NP-1]
 // (all pushed, nothing below): into c.ap as u | v << 13 | type << 26.
 // Returns their number, or -1 when they exceed kParentArcCap.
-template <int K, int NP>
-__device__ int parent_arcs(EnumState<K> &s, const CoreLds &c, const int (&mem)[K])
+template <int K, int NP, int V>
+__device__ int parent_arcs(EnumState<K, V> &s, const CoreLds &c, const int (&mem)[K])
 {
     constexpr uint32_t FLAG = kMemberFlag<K>;
     const int lane = lane_id();
@@ -315,8 +315,8 @@ __device__ int parent_arcs(EnumState<K> &s, const CoreLds &c, const int (&mem)[K
 // nap >= 0: c.ap holds the nap arc pairs inside adj(P), P = X less its last
 // member z, so only the vertices z brings have their lists scanned; nap < 0:
 // every taken vertex's list is scanned.
-template <int K>
-__device__ void core_node(EnumState<K> &s, const CoreLds &c, const int (&mem)[K], uint32_t cx,
+template <int K, int V>
+__device__ void core_node(EnumState<K, V> &s, const CoreLds &c, const int (&mem)[K], uint32_t cx,
                           int nap)
 {
     constexpr int R = kCoreR<K>;
@@ -509,8 +509,8 @@ __device__ void core_node(EnumState<K> &s, const CoreLds &c, const int (&mem)[K]
 
 // node with members s_0..s_D (D < k-3): its children jlo..jhi-1 become
 // member D+1; at D+1 = k-3 each child completes a core
-template <int K, int D>
-__device__ void visit_core(EnumState<K> &s, const CoreLds &c, const int (&st)[K - 1],
+template <int K, int D, int V>
+__device__ void visit_core(EnumState<K, V> &s, const CoreLds &c, const int (&st)[K - 1],
                            uint32_t code, int jlo, int jhi, int (&mem)[K])
 {
     int rem[D + 1];
@@ -562,8 +562,8 @@ __device__ void visit_core(EnumState<K> &s, const CoreLds &c, const int (&st)[K 
 
 // A unit: k = 3, the core {v}; k = 4, the core {v, w_i}; k >= 5, the cores
 // below children jlo..jhi-1 of the node (v, w_i).
-template <int K>
-__device__ void run_core_unit(EnumState<K> &s, const CoreLds &c, int v, int i, uint32_t range)
+template <int K, int V>
+__device__ void run_core_unit(EnumState<K, V> &s, const CoreLds &c, int v, int i, uint32_t range)
 {
     int mem[K];
 #pragma unroll
@@ -602,7 +602,8 @@ __device__ void run_core_unit(EnumState<K> &s, const CoreLds &c, int v, int i, u
     }
 }
 
-template <int K>
+// V = 0, or kVarDebug for the build that honours the test hooks
+template <int K, int V>
 __global__ __launch_bounds__(kWave) void core_kernel(const DevGraph *graphs, const int4 *units,
                                                      uint32_t unit_cap, uint32_t unit_end,
                                                      uint32_t *counters,
@@ -611,7 +612,7 @@ __global__ __launch_bounds__(kWave) void core_kernel(const DevGraph *graphs, con
                                                      EnumConfig cfg)
 {
     extern __shared__ uint32_t lds[];
-    EnumState<K> s;
+    EnumState<K, V> s;
     const LdsLayout lay = lds_layout(K, cfg.max_n, cfg.seg_cap, cfg.hash_bits, false, kCoreSegs<K>);
     char *base = reinterpret_cast<char *>(lds);
     CoreLds c;
@@ -674,19 +675,20 @@ int core_lds_bytes(int k, int max_n, int seg_cap)
 }
 
 template <int K>
-static const void *core_fn()
+static const void *core_fn(bool debug)
 {
-    return reinterpret_cast<const void *>(&core_kernel<K>);
+    return debug ? reinterpret_cast<const void *>(&core_kernel<K, kVarDebug>)
+                 : reinterpret_cast<const void *>(&core_kernel<K, 0>);
 }
 
 int core_max_blocks_per_cu(int k, int lds_bytes, int *blocks)
 {
     const void *fn = nullptr;
     switch (k) {
-    case 3: fn = core_fn<3>(); break;
-    case 4: fn = core_fn<4>(); break;
-    case 5: fn = core_fn<5>(); break;
-    case 6: fn = core_fn<6>(); break;
+    case 3: fn = core_fn<3>(false); break;
+    case 4: fn = core_fn<4>(false); break;
+    case 5: fn = core_fn<5>(false); break;
+    case 6: fn = core_fn<6>(false); break;
     default: return fail(MK_ERANGE, "k=%d outside 3..6", k);
     }
     MK_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, fn, kWave, (size_t)lds_bytes));
@@ -699,17 +701,20 @@ int launch_core(int k, const DevGraph *d_graphs, const int4 *units, uint32_t uni
                 hipStream_t stream)
 {
     if (grid <= 0) return MK_OK;
-#define MK_CORE_LAUNCH(KK)                                                                   \
-    hipLaunchKernelGGL(core_kernel<KK>, dim3(grid), dim3(kWave), lds_bytes, stream, d_graphs, \
-                       units, unit_cap, unit_end, counters, table, num_classes, hist_base, cfg)
+    const bool debug = (cfg.variant & kVarDebug) != 0;
+    const void *fn = nullptr;
     switch (k) {
-    case 3: MK_CORE_LAUNCH(3); break;
-    case 4: MK_CORE_LAUNCH(4); break;
-    case 5: MK_CORE_LAUNCH(5); break;
-    case 6: MK_CORE_LAUNCH(6); break;
+    case 3: fn = core_fn<3>(debug); break;
+    case 4: fn = core_fn<4>(debug); break;
+    case 5: fn = core_fn<5>(debug); break;
+    case 6: fn = core_fn<6>(debug); break;
     default: return fail(MK_ERANGE, "k=%d outside 3..6", k);
     }
-#undef MK_CORE_LAUNCH
+    EnumConfig c = cfg;
+    void *args[] = {(void *)&d_graphs, (void *)&units, (void *)&unit_cap, (void *)&unit_end,
+                    (void *)&counters, (void *)&table, (void *)&num_classes, (void *)&hist_base,
+                    (void *)&c};
+    MK_HIP(hipLaunchKernel(fn, dim3(grid), dim3(kWave), args, (size_t)lds_bytes, stream));
     MK_HIP(hipGetLastError());
     return MK_OK;
 }

@@ -696,6 +696,18 @@ __global__ __launch_bounds__(kWave) void enum_kernel(const DevGraph *graphs, con
     enum_body<K, 0>(graphs, units, unit_cap, unit_end, counters, table, num_classes, hist_base, cfg);
 }
 
+// the test-hook builds of the variants above (V includes kVarDebug)
+template <int K, int V>
+__global__ __launch_bounds__(kWave) void enum_debug_kernel(const DevGraph *graphs, const int4 *units,
+                                                           uint32_t unit_cap, uint32_t unit_end,
+                                                           uint32_t *counters,
+                                                           const uint32_t *table, uint32_t num_classes,
+                                                           unsigned long long *hist_base,
+                                                           EnumConfig cfg)
+{
+    enum_body<K, V>(graphs, units, unit_cap, unit_end, counters, table, num_classes, hist_base, cfg);
+}
+
 // arc tests by list search (V = kVarSearch, optionally | kVarGlobal)
 template <int K, int V>
 __global__ __launch_bounds__(kWave) void enum_lists_kernel(const DevGraph *graphs, const int4 *units,
@@ -716,7 +728,7 @@ int enum_lds_bytes(int k, int max_n, int seg_cap, int variant)
 }
 
 // the instantiated variants: bit matrices, list search, list search with
-// global marks
+// global marks; each also with the test hooks
 template <int K>
 static const void *enum_fn(int variant)
 {
@@ -725,6 +737,12 @@ static const void *enum_fn(int variant)
     case kVarSearch: return reinterpret_cast<const void *>(&enum_lists_kernel<K, kVarSearch>);
     case kVarSearch | kVarGlobal:
         return reinterpret_cast<const void *>(&enum_lists_kernel<K, kVarSearch | kVarGlobal>);
+    case kVarDebug: return reinterpret_cast<const void *>(&enum_debug_kernel<K, kVarDebug>);
+    case kVarDebug | kVarSearch:
+        return reinterpret_cast<const void *>(&enum_debug_kernel<K, kVarDebug | kVarSearch>);
+    case kVarDebug | kVarSearch | kVarGlobal:
+        return reinterpret_cast<const void *>(
+            &enum_debug_kernel<K, kVarDebug | kVarSearch | kVarGlobal>);
     default: return nullptr;
     }
 }

@@ -299,9 +299,11 @@ template <int K, int V>
 __device__ __forceinline__ void hash_insert(EnumState<K, V> &s, bool mine, uint32_t code, uint32_t n)
 {
     bool fresh = false;
-    if (s.flags & kDebugNoHash) {
-        if (mine) add_global<K>(s, code, n);
-        return;
+    if constexpr ((V & kVarDebug) != 0) {
+        if (s.flags & kDebugNoHash) {
+            if (mine) add_global<K>(s, code, n);
+            return;
+        }
     }
     if (mine) {
         // one compare-and-swap either claims an empty slot or finds the code
@@ -323,7 +325,7 @@ __device__ __forceinline__ void hash_insert(EnumState<K, V> &s, bool mine, uint3
     }
     s.hused += __popcll(__ballot(fresh));
     if (s.hused > s.hlimit || s.hpending >= kPendingMax ||
-        (s.flags & kDebugFlushAlways))
+        ((V & kVarDebug) != 0 && (s.flags & kDebugFlushAlways)))
         flush_hash<K>(s);
 }
 

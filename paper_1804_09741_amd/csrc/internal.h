@@ -206,8 +206,12 @@ constexpr uint32_t kAllUnits = 0xFFFFFFFFu;
 //   kVarGlobal  every wave's marks live in a private n-entry array in global
 //               memory instead of LDS, and extension segments hold u32 ids:
 //               graphs with more vertices than LDS marks can hold.
+//   kVarDebug   the kernel honours the kDebug* test hooks of EnumConfig
+//               (the production kernels leave their checks out: about 2%
+//               of the k = 6 kernel's time per hash insert).
 constexpr int kVarSearch = 1;
 constexpr int kVarGlobal = 2;
+constexpr int kVarDebug = 4;
 
 struct EnumConfig {
     int max_n;       // largest n of the batch (LDS marks)
