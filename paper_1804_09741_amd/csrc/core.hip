@@ -602,14 +602,11 @@ __device__ void run_core_unit(EnumState<K, V> &s, const CoreLds &c, int v, int i
     }
 }
 
-// V = 0, or kVarDebug for the build that honours the test hooks
 template <int K, int V>
-__global__ __launch_bounds__(kWave) void core_kernel(const DevGraph *graphs, const int4 *units,
-                                                     uint32_t unit_cap, uint32_t unit_end,
-                                                     uint32_t *counters,
-                                                     const uint32_t *table, uint32_t num_classes,
-                                                     unsigned long long *hist_base,
-                                                     EnumConfig cfg)
+__device__ __forceinline__ void core_body(const DevGraph *graphs, const int4 *units,
+                                          uint32_t unit_cap, uint32_t unit_end, uint32_t *counters,
+                                          const uint32_t *table, uint32_t num_classes,
+                                          unsigned long long *hist_base, const EnumConfig &cfg)
 {
     extern __shared__ uint32_t lds[];
     EnumState<K, V> s;
@@ -635,6 +632,30 @@ __global__ __launch_bounds__(kWave) void core_kernel(const DevGraph *graphs, con
     s.hunit = INT_MAX;
     for_each_unit<K>(s, graphs, units, unit_cap, unit_end, counters, hist_base, cfg,
                      [&](int v, int i, uint32_t range) { run_core_unit<K>(s, c, v, i, range); });
+}
+
+template <int K>
+__global__ __launch_bounds__(kWave) void core_kernel(const DevGraph *graphs, const int4 *units,
+                                                     uint32_t unit_cap, uint32_t unit_end,
+                                                     uint32_t *counters,
+                                                     const uint32_t *table, uint32_t num_classes,
+                                                     unsigned long long *hist_base,
+                                                     EnumConfig cfg)
+{
+    core_body<K, 0>(graphs, units, unit_cap, unit_end, counters, table, num_classes, hist_base, cfg);
+}
+
+// the build that honours the test hooks of the hash
+template <int K>
+__global__ __launch_bounds__(kWave) void core_debug_kernel(const DevGraph *graphs, const int4 *units,
+                                                           uint32_t unit_cap, uint32_t unit_end,
+                                                           uint32_t *counters,
+                                                           const uint32_t *table, uint32_t num_classes,
+                                                           unsigned long long *hist_base,
+                                                           EnumConfig cfg)
+{
+    core_body<K, kVarDebug>(graphs, units, unit_cap, unit_end, counters, table, num_classes,
+                            hist_base, cfg);
 }
 
 // hist[g][c] := raw / core_mult[c]; a raw count that is not a multiple (or
@@ -677,8 +698,8 @@ int core_lds_bytes(int k, int max_n, int seg_cap)
 template <int K>
 static const void *core_fn(bool debug)
 {
-    return debug ? reinterpret_cast<const void *>(&core_kernel<K, kVarDebug>)
-                 : reinterpret_cast<const void *>(&core_kernel<K, 0>);
+    return debug ? reinterpret_cast<const void *>(&core_debug_kernel<K>)
+                 : reinterpret_cast<const void *>(&core_kernel<K>);
 }
 
 int core_max_blocks_per_cu(int k, int lds_bytes, int *blocks)
