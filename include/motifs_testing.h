@@ -20,7 +20,9 @@ extern "C" {
    2 = flush the per-wave count hash after every insert,
    4 = MK_METHOD_CORES rescans every list instead of sharing a parent's arc
        pairs.
-   The histograms are the same on every path. */
+   Flags 1 and 2 switch the batch to builds of its counting kernel that
+   carry these checks (the production builds leave them out).  The
+   histograms are the same on every path. */
 int mk_batch_debug(mk_batch *b, int32_t flags);
 
 #ifdef __cplusplus
