@@ -43,16 +43,29 @@ template <int K>
 constexpr int kCoreR = K - 2;                     // members of a core
 template <int K>
 constexpr int kCells = 1 << (2 * (K - 2));        // 4^(k-2) relation vectors
-// top bit of a mark: "member of the current core" while a core is processed
+// The top four bits of a mark (above every relation bit) are all set on
+// the members of the core being processed (and of a parent while its arc
+// pairs are listed).  Otherwise, on the vertices of adj(X), they hold the
+// list position of the vertex's cell (0..14) from the core's cell phase on,
+// the arc-pair table's index; they are left as they are until the next
+// core overwrites them, or cleared with the vertex's last relation bit.
 template <int K>
-constexpr uint32_t kMemberFlag = 1u << (8 * sizeof(MarkT<K>) - 1);
+constexpr int kPosShift = 8 * (int)sizeof(MarkT<K>) - 4;
+template <int K>
+constexpr uint32_t kMemberFlag = 0xFu << kPosShift<K>;
+
+template <int K>
+__device__ __forceinline__ bool is_member(uint32_t m)
+{
+    return (m & kMemberFlag<K>) == kMemberFlag<K>;
+}
 
 // Cores with at most kAggCells cells count their arc pairs in a small LDS
 // table per (cell pair, arc type) first; the pair phase then takes them off
 // the pair weights and adds them to the true classes, one insert per
 // non-empty entry.  Cores with more cells insert +1/-1 per arc pair.
 template <int K>
-constexpr int kAggCells = K == 6 ? 12 : 16;
+constexpr int kAggCells = K == 6 ? 12 : 15;
 template <int K>
 constexpr int kAggWords = 3 * kAggCells<K> * (kAggCells<K> + 1) / 2;
 
@@ -82,7 +95,7 @@ struct CoreLds {
 __host__ __device__ inline int core_extra_bytes(int k)
 {
     const int cells = 1 << (2 * (k - 2));
-    const int agg_cells = k == 6 ? 12 : 16;
+    const int agg_cells = k == 6 ? 12 : 15;
     return 4 * cells + 2 * ((cells + 3) & ~3) + (k >= 6 ? 4 * kWave : 0) +
            4 * 3 * agg_cells * (agg_cells + 1) / 2;
 }
@@ -165,6 +178,32 @@ __device__ __forceinline__ Held push_marks_held(EnumState<K, V> &s, int x)
     return h;
 }
 
+// pop_held<D>(x) for the core walk: a long list's pop also clears the
+// position bits of the vertices it leaves without any relation bit (a short
+// list's pop restores the marks from before the push, which had none)
+template <int K, int D, int V>
+__device__ __forceinline__ void core_pop(EnumState<K, V> &s, int x, const Held &h)
+{
+    if (h.n <= kWave) {
+        pop_held<K, D>(s, x, h);
+        return;
+    }
+    const int lane = lane_id();
+    const int r0 = uniform(s.urow[x]);
+    const int r1 = uniform(s.urow[x + 1]);
+    const uint32_t keep = ~mark_bits<K>(D, 3u);
+    for (int base = r0; base < r1; base += kWave) {
+        const int e = base + lane;
+        if (e < r1) {
+            const int y = (int)(s.uadj[e] >> 2);
+            uint32_t m = s.mark[y] & keep;
+            if (!(m & ~kMemberFlag<K>)) m = 0u;
+            s.mark[y] = (MarkT<K, V>)m;
+        }
+    }
+    __syncthreads();
+}
+
 // Class id of a code for the class-keyed hash of the core kernel (cores
 // stand for many differently labelled k-sets, so their codes rarely repeat
 // while their classes do).  A code outside the connected classes is a
@@ -222,7 +261,7 @@ __device__ __forceinline__ void scan_taken(EnumState<K, V> &s, const CoreLds &c,
             const int e = member_entry<NM>(pre, r0, a, &d);
             u = (int)(s.uadj[e] >> 2);
             const uint32_t m = s.mark[u];
-            if (!(m & FLAG) && !(m & lower_members<K>(d))) {
+            if (!is_member<K>(m) && !(m & lower_members<K>(d))) {
                 row = s.urow[u];
                 deg = s.urow[u + 1] - row;
                 mu = m;
@@ -267,7 +306,7 @@ __device__ __forceinline__ void scan_taken(EnumState<K, V> &s, const CoreLds &c,
                     m_u = w;
                 }
                 t = ent & 3u;
-                edge = mv != 0u && !(mv & FLAG) && keep(v, uu, mv);
+                edge = mv != 0u && !is_member<K>(mv) && keep(v, uu, mv);
             }
             arc(edge, uu, v, m_u, mv, t);
         }
@@ -344,13 +383,14 @@ __device__ void core_node(EnumState<K, V> &s, const CoreLds &c, const int (&mem)
     for (int base = 0; base < total; base += kWave) {
         const int a = base + lane;
         bool mine = false;
-        uint32_t cell = 0;
+        uint32_t cell = 0, vid = 0, mk = 0;
         if (a < total) {
             int d;
             const int e = member_entry<R>(pre, r0, a, &d);
-            const uint32_t m = s.mark[s.uadj[e] >> 2];
-            mine = !(m & FLAG) && !(m & lower_members<K>(d));
-            cell = cell_of<K>(m);
+            vid = s.uadj[e] >> 2;
+            mk = s.mark[vid];
+            mine = !is_member<K>(mk) && !(mk & lower_members<K>(d));
+            cell = cell_of<K>(mk);
         }
         bool fresh = false;
         if (mine) fresh = atomicAdd(&c.cnt[cell], 1u) == 0u;
@@ -359,6 +399,11 @@ __device__ void core_node(EnumState<K, V> &s, const CoreLds &c, const int (&mem)
             const int at = ncell + (int)lanes_below(bal);
             c.list[at] = (uint8_t)cell;
             c.pos[cell] = (uint8_t)at;
+        }
+        if (mine) {
+            // the cell's position into the mark's top bits (15 and up: none)
+            const uint32_t p = c.pos[cell];
+            s.mark[vid] = (MarkT<K>)((mk & ~kMemberFlag<K>) | ((p < 15u ? p : 0u) << kPosShift<K>));
         }
         ncell += __popcll(bal);
         nadj += __popcll(__ballot(mine));
@@ -374,7 +419,7 @@ __device__ void core_node(EnumState<K, V> &s, const CoreLds &c, const int (&mem)
     auto arc = [&](bool edge, int, int, uint32_t mu, uint32_t mv, uint32_t t) {
         if (agg) {
             if (edge) {
-                uint32_t ia = c.pos[cell_of<K>(mu)], ib = c.pos[cell_of<K>(mv)];
+                uint32_t ia = (mu >> kPosShift<K>) & 15u, ib = (mv >> kPosShift<K>) & 15u;
                 if (ia > ib) {
                     const uint32_t x = ia;
                     ia = ib;
@@ -384,7 +429,8 @@ __device__ void core_node(EnumState<K, V> &s, const CoreLds &c, const int (&mem)
                 atomicAdd(&c.agg[3u * (ib * (ib + 1u) / 2u + ia) + t - 1u], 1u);
             }
         } else {
-            const uint32_t cm = cx | code_bits<K>(mu, K - 2) | code_bits<K>(mv, K - 1);
+            const uint32_t cm = cx | code_bits<K>(mu & ~kMemberFlag<K>, K - 2) |
+                                code_bits<K>(mv & ~kMemberFlag<K>, K - 1);
             const uint32_t ct = cm | ((t & 1u) << B_YZ) | ((t >> 1) << B_ZY);
             bool et = edge, em = edge;
             const uint32_t it = class_of<K>(s, et, ct), im = class_of<K>(s, em, cm);
@@ -542,12 +588,13 @@ __device__ void visit_core(EnumState<K, V> &s, const CoreLds &c, const int (&st)
             }
         }
         const int x = uniform((int)s.seg[L * s.seg_cap + o]);
-        const uint32_t ccode = code | code_bits<K>((uint32_t)uniform((int)s.mark[x]), D + 1);
+        const uint32_t ccode =
+            code | code_bits<K>((uint32_t)uniform((int)s.mark[x]) & ~kMemberFlag<K>, D + 1);
         mem[D + 1] = x;
         if constexpr (D + 1 == K - 3) {
             const Held held = push_marks_held<K, D + 1>(s, x);
             core_node<K>(s, c, mem, ccode, nap);
-            pop_held<K, D + 1>(s, x, held);
+            core_pop<K, D + 1>(s, x, held);
         } else {
             const Held held = push_held<K, D + 1>(s, x);
             int cst[K - 1];
@@ -555,7 +602,7 @@ __device__ void visit_core(EnumState<K, V> &s, const CoreLds &c, const int (&st)
             for (int q = 0; q < K - 1; ++q)
                 cst[q] = q < L ? s.len[q] : (q == L ? o + 1 : (q <= D ? st[q] : 0));
             visit_core<K, D + 1>(s, c, cst, ccode, 0, INT_MAX, mem);
-            pop_held<K, D + 1>(s, x, held);
+            core_pop<K, D + 1>(s, x, held);
         }
     }
 }
@@ -573,17 +620,17 @@ __device__ void run_core_unit(EnumState<K, V> &s, const CoreLds &c, int v, int i
     if constexpr (K == 3) {
         const Held held0 = push_marks_held<K, 0>(s, v);
         core_node<K>(s, c, mem, 0u, -1);
-        pop_held<K, 0>(s, v, held0);
+        core_pop<K, 0>(s, v, held0);
     } else {
         const Held held0 = push_held<K, 0>(s, v);
         if (i < s.len[0]) {
             const int x = uniform((int)s.seg[i]);
-            const uint32_t code = code_bits<K>((uint32_t)uniform((int)s.mark[x]), 1);
+            const uint32_t code = code_bits<K>((uint32_t)uniform((int)s.mark[x]) & ~kMemberFlag<K>, 1);
             mem[1] = x;
             if constexpr (K == 4) {
                 const Held held1 = push_marks_held<K, 1>(s, x);
                 core_node<K>(s, c, mem, code, -1);
-                pop_held<K, 1>(s, x, held1);
+                core_pop<K, 1>(s, x, held1);
             } else {
                 const Held held1 = push_held<K, 1>(s, x);
                 int st[K - 1];
@@ -593,12 +640,12 @@ __device__ void run_core_unit(EnumState<K, V> &s, const CoreLds &c, int v, int i
                 const bool full = range == kFullChild;
                 visit_core<K, 1>(s, c, st, code, full ? 0 : (int)(range & 0xFFFFu),
                                  full ? INT_MAX : (int)(range >> 16), mem);
-                pop_held<K, 1>(s, x, held1);
+                core_pop<K, 1>(s, x, held1);
             }
         } else if (lane_id() == 0) {
             atomicAdd(s.errors, 1u);
         }
-        pop_held<K, 0>(s, v, held0);
+        core_pop<K, 0>(s, v, held0);
     }
 }
 
