@@ -180,7 +180,8 @@ __device__ __forceinline__ Held push_marks_held(EnumState<K, V> &s, int x)
 
 // pop_held<D>(x) for the core walk: a long list's pop also clears the
 // position bits of the vertices it leaves without any relation bit (a short
-// list's pop restores the marks from before the push, which had none)
+// list's pop restores the marks from before the push, where a vertex
+// without relation bits had no position bits either)
 template <int K, int D, int V>
 __device__ __forceinline__ void core_pop(EnumState<K, V> &s, int x, const Held &h)
 {
