@@ -269,12 +269,8 @@ __device__ __forceinline__ void scan_taken(EnumState<K, V> &s, const CoreLds &c,
             }
         }
         int incl = deg;
-#pragma unroll
-        for (int d = 1; d < kWave; d <<= 1) {
-            const int o = __shfl_up(incl, d, kWave);
-            if (lane >= d) incl += o;
-        }
-        const int tot = uniform(__shfl(incl, kWave - 1, kWave));
+        incl = wave_incl_sum(incl);
+        const int tot = __builtin_amdgcn_readlane(incl, kWave - 1);
         pre_deg[lane] = (uint32_t)incl;
         start[lane] = (uint32_t)(row - (incl - deg));  // flat entry f at start + f
         if constexpr (kPackedUid<K>) {
@@ -504,12 +500,8 @@ __device__ void core_node(EnumState<K, V> &s, const CoreLds &c, const int (&mem)
         // one insert when they fit a wave
         const uint32_t nl = (valid ? 1u : 0u) + (e1 ? 1u : 0u) + (e2 ? 1u : 0u) + (e3 ? 1u : 0u);
         uint32_t incl = nl;
-#pragma unroll
-        for (int d = 1; d < kWave; d <<= 1) {
-            const uint32_t o = __shfl_up(incl, d, kWave);
-            if (lane >= d) incl += o;
-        }
-        const int items = uniform((int)__shfl(incl, kWave - 1, kWave));
+        incl = (uint32_t)wave_incl_sum((int)incl);
+        const int items = __builtin_amdgcn_readlane((int)incl, kWave - 1);
         if (items <= kWave) {
             uint32_t *qk = s.scratch, *qn = s.scratch + kWave;
             uint32_t at = incl - nl;

@@ -185,12 +185,8 @@ __device__ void last_two_small(EnumState<K, V> &s, const int (&st)[K - 1],
     }
     if (deg >= kRowMin) deg = 0;
     int incl = deg;
-#pragma unroll
-    for (int d = 1; d < kWave; d <<= 1) {
-        const int o = __shfl_up(incl, d, kWave);
-        if (lane >= d) incl += o;
-    }
-    const int totB = uniform(__shfl(incl, kWave - 1, kWave));
+    incl = wave_incl_sum(incl);
+    const int totB = __builtin_amdgcn_readlane(incl, kWave - 1);
     uint32_t *pre = s.scratch;
     pre[lane] = (uint32_t)incl;
     // flat entry f of this lane's list sits at rowb + f
@@ -322,12 +318,8 @@ __device__ void last_two_cells(EnumState<K, V> &s, const int (&st)[K - 1],
     }
     if (deg >= kRowMin) deg = 0;
     int incl = deg;
-#pragma unroll
-    for (int d = 1; d < kWave; d <<= 1) {
-        const int o = __shfl_up(incl, d, kWave);
-        if (lane >= d) incl += o;
-    }
-    const int totB = uniform(__shfl(incl, kWave - 1, kWave));
+    incl = wave_incl_sum(incl);
+    const int totB = __builtin_amdgcn_readlane(incl, kWave - 1);
     uint32_t *pre = s.scratch;
     pre[lane] = (uint32_t)incl;
     // flat entry f of this lane's list sits at rowb + f
@@ -569,12 +561,8 @@ __device__ void last_two(EnumState<K, V> &s, const int (&st)[K - 1], uint32_t co
         }
         if (deg >= kRowMin) deg = 0;
         int incl = deg;
-#pragma unroll
-        for (int d = 1; d < kWave; d <<= 1) {
-            const int o = __shfl_up(incl, d, kWave);
-            if (lane >= d) incl += o;
-        }
-        const int tot = uniform(__shfl(incl, kWave - 1, kWave));
+        incl = wave_incl_sum(incl);
+        const int tot = __builtin_amdgcn_readlane(incl, kWave - 1);
         pre[lane] = (uint32_t)incl;
         start[lane] = (uint32_t)(row - (incl - deg));  // flat entry f at start + f
         cw[lane] = wcode;

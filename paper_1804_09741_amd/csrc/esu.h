@@ -148,6 +148,21 @@ __device__ __forceinline__ int lane_id() { return (int)threadIdx.x; }
 
 __device__ __forceinline__ int uniform(int x) { return __builtin_amdgcn_readfirstlane(x); }
 
+// Inclusive prefix sum across the wave by DPP moves (rows of 16 lanes
+// shifted by 1, 2, 4 and 8, then each row's last lane broadcast into the
+// next rows): six VALU operations, where the lane-shuffle loop waits on six
+// dependent LDS-crossbar permutes.  Every lane must be active.
+__device__ __forceinline__ int wave_incl_sum(int x)
+{
+    x += __builtin_amdgcn_update_dpp(0, x, 0x111, 0xF, 0xF, false);  // row_shr:1
+    x += __builtin_amdgcn_update_dpp(0, x, 0x112, 0xF, 0xF, false);  // row_shr:2
+    x += __builtin_amdgcn_update_dpp(0, x, 0x114, 0xF, 0xF, false);  // row_shr:4
+    x += __builtin_amdgcn_update_dpp(0, x, 0x118, 0xF, 0xF, false);  // row_shr:8
+    x += __builtin_amdgcn_update_dpp(0, x, 0x142, 0xA, 0xF, false);  // row_bcast:15
+    x += __builtin_amdgcn_update_dpp(0, x, 0x143, 0xC, 0xF, false);  // row_bcast:31
+    return x;
+}
+
 __device__ __forceinline__ uint32_t lanes_below(unsigned long long mask)
 {
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),

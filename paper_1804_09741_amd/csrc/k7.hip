@@ -456,12 +456,8 @@ __device__ __forceinline__ void last_two7_cells(EnumState<7, V> &s, K7Wave &w7, 
     }
     if (deg >= kRowMin) deg = 0;
     int incl = deg;
-#pragma unroll
-    for (int d = 1; d < kWave; d <<= 1) {
-        const int o = __shfl_up(incl, d, kWave);
-        if (lane >= d) incl += o;
-    }
-    const int totB = uniform(__shfl(incl, kWave - 1, kWave));
+    incl = wave_incl_sum(incl);
+    const int totB = __builtin_amdgcn_readlane(incl, kWave - 1);
     uint32_t *pre = s.scratch;
     pre[lane] = (uint32_t)incl;
     // flat entry f of this lane's list sits at rowb + f
@@ -636,12 +632,8 @@ __device__ __forceinline__ void last_two7(EnumState<7, V> &s, K7Wave &w7, const 
             wcode = code_bits7(s.mark[w], 5);
         }
         int incl = deg;
-#pragma unroll
-        for (int d = 1; d < kWave; d <<= 1) {
-            const int o = __shfl_up(incl, d, kWave);
-            if (lane >= d) incl += o;
-        }
-        const int tot = uniform(__shfl(incl, kWave - 1, kWave));
+        incl = wave_incl_sum(incl);
+        const int tot = __builtin_amdgcn_readlane(incl, kWave - 1);
         pre[lane] = (uint32_t)incl;
         start[lane] = (uint32_t)(row - (incl - deg));  // flat entry f at start + f
         __syncthreads();
