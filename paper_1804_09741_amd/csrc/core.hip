@@ -252,7 +252,7 @@ __device__ __forceinline__ void scan_taken(EnumState<K, V> &s, const CoreLds &c,
 {
     constexpr uint32_t FLAG = kMemberFlag<K>;
     const int lane = lane_id();
-    uint32_t *pre_deg = s.scratch, *start = s.scratch + kWave, *cw = s.scratch + 2 * kWave;
+    uint32_t *srcb = s.scratch, *start = s.scratch + kWave, *cw = s.scratch + 2 * kWave;
     for (int base = pre[from]; base < pre[NM]; base += kWave) {
         const int a = base + lane;
         int deg = 0, row = 0, u = 0;
@@ -271,7 +271,6 @@ __device__ __forceinline__ void scan_taken(EnumState<K, V> &s, const CoreLds &c,
         int incl = deg;
         incl = wave_incl_sum(incl);
         const int tot = __builtin_amdgcn_readlane(incl, kWave - 1);
-        pre_deg[lane] = (uint32_t)incl;
         start[lane] = (uint32_t)(row - (incl - deg));  // flat entry f at start + f
         if constexpr (kPackedUid<K>) {
             cw[lane] = mu | ((uint32_t)u << 16);
@@ -285,12 +284,8 @@ __device__ __forceinline__ void scan_taken(EnumState<K, V> &s, const CoreLds &c,
             bool edge = false;
             int uu = 0, v = 0;
             uint32_t m_u = 0, mv = 0, t = 0;
+            const int lo = flat_source(srcb, incl, deg, fb);
             if (f < tot) {
-                // first lane whose inclusive degree prefix exceeds f
-                int lo = 0;
-#pragma unroll
-                for (int step = kWave / 2; step > 0; step >>= 1)
-                    lo += ((int)pre_deg[lo + step - 1] <= f) ? step : 0;
                 const uint32_t ent = s.uadj[start[lo] + (uint32_t)f];
                 v = (int)(ent >> 2);
                 mv = s.mark[v];

@@ -320,24 +320,15 @@ __device__ void last_two_cells(EnumState<K, V> &s, const int (&st)[K - 1],
     int incl = deg;
     incl = wave_incl_sum(incl);
     const int totB = __builtin_amdgcn_readlane(incl, kWave - 1);
-    uint32_t *pre = s.scratch;
-    pre[lane] = (uint32_t)incl;
+    uint32_t *pre = s.scratch;  // flat_source's buffer
     // flat entry f of this lane's list sits at rowb + f
     const int rowb = row - (incl - deg);
-    __syncthreads();
     // the short lists, flat: Part B entries and arcs inside E
     for (int base = 0; base < totB; base += kWave) {
         const int f = base + lane;
         const bool valid = f < totB;
-        int src1 = 0, off = 0;
-        if (valid) {
-            int lo = 0;
-#pragma unroll
-            for (int step = kWave / 2; step > 0; step >>= 1)
-                lo += ((int)pre[lo + step - 1] <= f) ? step : 0;
-            src1 = lo;
-            off = f;
-        }
+        const int src1 = flat_source(pre, incl, deg, base);
+        const int off = f;
         // the permutes run with every lane active
         const int r1 = (int)from_lane((uint32_t)rowb, src1);
         const uint32_t c1 = from_lane(cb1, src1);
@@ -563,7 +554,6 @@ __device__ void last_two(EnumState<K, V> &s, const int (&st)[K - 1], uint32_t co
         int incl = deg;
         incl = wave_incl_sum(incl);
         const int tot = __builtin_amdgcn_readlane(incl, kWave - 1);
-        pre[lane] = (uint32_t)incl;
         start[lane] = (uint32_t)(row - (incl - deg));  // flat entry f at start + f
         cw[lane] = wcode;
         __syncthreads();
@@ -571,12 +561,8 @@ __device__ void last_two(EnumState<K, V> &s, const int (&st)[K - 1], uint32_t co
             const int f = fb + lane;
             bool valid = f < tot;
             uint32_t c = 0;
+            const int lo = flat_source(pre, incl, deg, fb);
             if (valid) {
-                // first child lane whose inclusive degree prefix exceeds f
-                int lo = 0;
-#pragma unroll
-                for (int step = kWave / 2; step > 0; step >>= 1)
-                    lo += ((int)pre[lo + step - 1] <= f) ? step : 0;
                 const uint32_t ent = s.uadj[start[lo] + (uint32_t)f];
                 const int u = (int)(ent >> 2);
                 const uint32_t t = ent & 3u;

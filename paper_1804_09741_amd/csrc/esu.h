@@ -163,6 +163,37 @@ __device__ __forceinline__ int wave_incl_sum(int x)
     return x;
 }
 
+// Inclusive prefix maximum across the wave (the same DPP pattern; values
+// must be >= 0).
+__device__ __forceinline__ int wave_incl_max(int x)
+{
+    x = max(x, __builtin_amdgcn_update_dpp(0, x, 0x111, 0xF, 0xF, false));
+    x = max(x, __builtin_amdgcn_update_dpp(0, x, 0x112, 0xF, 0xF, false));
+    x = max(x, __builtin_amdgcn_update_dpp(0, x, 0x114, 0xF, 0xF, false));
+    x = max(x, __builtin_amdgcn_update_dpp(0, x, 0x118, 0xF, 0xF, false));
+    x = max(x, __builtin_amdgcn_update_dpp(0, x, 0x142, 0xA, 0xF, false));
+    x = max(x, __builtin_amdgcn_update_dpp(0, x, 0x143, 0xC, 0xF, false));
+    return x;
+}
+
+// Flat scan over the lists of the wave's lanes: lane j owns the entries
+// [incl_j - deg_j, incl_j) (incl the inclusive prefix of the degrees).  The
+// source lane of entry fb + lane: every lane whose range meets [fb, fb + 64)
+// writes its id at its first entry there into buf (64 words of LDS), and a
+// prefix maximum carries each id over the entries after it -- in place of a
+// six-step binary search of dependent LDS reads per entry.  Every lane must
+// be active.
+__device__ __forceinline__ int flat_source(uint32_t *buf, int incl, int deg, int fb)
+{
+    const int lane = (int)threadIdx.x;
+    const int excl = incl - deg;
+    buf[lane] = 0u;
+    __syncthreads();
+    if (deg > 0 && excl < fb + kWave && incl > fb) buf[excl > fb ? excl - fb : 0] = (uint32_t)lane;
+    __syncthreads();
+    return wave_incl_max((int)buf[lane]);
+}
+
 __device__ __forceinline__ uint32_t lanes_below(unsigned long long mask)
 {
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
