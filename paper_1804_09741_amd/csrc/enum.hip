@@ -187,11 +187,9 @@ __device__ void last_two_small(EnumState<K, V> &s, const int (&st)[K - 1],
     int incl = deg;
     incl = wave_incl_sum(incl);
     const int totB = __builtin_amdgcn_readlane(incl, kWave - 1);
-    uint32_t *pre = s.scratch;
-    pre[lane] = (uint32_t)incl;
+    uint32_t *pre = s.scratch;  // flat_source's buffer
     // flat entry f of this lane's list sits at rowb + f
     const int rowb = row - (incl - deg);
-    __syncthreads();
     const int mm = e - jlo;
     const int npairs = mm * (mm - 1) / 2;
     const int total = npairs + totB;
@@ -201,6 +199,7 @@ __device__ void last_two_small(EnumState<K, V> &s, const int (&st)[K - 1],
         const bool pair = f < npairs;
         // source lanes first; the permutes run with every lane active (a
         // permute from an inactive lane reads 0)
+        const int srcB = base + kWave > npairs ? flat_source(pre, incl, deg, base - npairs) : 0;
         int src1 = 0, src2 = 0, off = 0;
         if (pair) {
             int b = (int)((1.0f + __builtin_amdgcn_sqrtf(1.0f + 8.0f * (float)f)) * 0.5f);
@@ -209,13 +208,8 @@ __device__ void last_two_small(EnumState<K, V> &s, const int (&st)[K - 1],
             src1 = jlo + (f - b * (b - 1) / 2);
             src2 = jlo + b;
         } else if (valid) {
-            const int fb = f - npairs;
-            int lo = 0;
-#pragma unroll
-            for (int step = kWave / 2; step > 0; step >>= 1)
-                lo += ((int)pre[lo + step - 1] <= fb) ? step : 0;
-            src1 = lo;
-            off = fb;
+            src1 = srcB;
+            off = f - npairs;
         }
         const uint32_t w = from_lane(vtx, src1);
         const uint32_t u2 = from_lane(vtx, src2);

@@ -458,24 +458,15 @@ __device__ __forceinline__ void last_two7_cells(EnumState<7, V> &s, K7Wave &w7, 
     int incl = deg;
     incl = wave_incl_sum(incl);
     const int totB = __builtin_amdgcn_readlane(incl, kWave - 1);
-    uint32_t *pre = s.scratch;
-    pre[lane] = (uint32_t)incl;
+    uint32_t *pre = s.scratch;  // flat_source's buffer
     // flat entry f of this lane's list sits at rowb + f
     const int rowb = row - (incl - deg);
-    __syncthreads();
     // the short lists, flat: exclusive neighbours and arcs inside E
     for (int base = 0; base < totB; base += kWave) {
         const int f = base + lane;
         const bool valid = f < totB;
-        int src1 = 0, off = 0;
-        if (valid) {
-            int lo = 0;
-#pragma unroll
-            for (int step = kWave / 2; step > 0; step >>= 1)
-                lo += ((int)pre[lo + step - 1] <= f) ? step : 0;
-            src1 = lo;
-            off = f;
-        }
+        const int src1 = flat_source(pre, incl, deg, base);
+        const int off = f;
         // the permutes run with every lane active
         const int r1 = (int)from_lane7((uint32_t)rowb, src1);
         const Code7 c1 = from_lane64(cb1, src1);
@@ -634,18 +625,12 @@ __device__ __forceinline__ void last_two7(EnumState<7, V> &s, K7Wave &w7, const 
         int incl = deg;
         incl = wave_incl_sum(incl);
         const int tot = __builtin_amdgcn_readlane(incl, kWave - 1);
-        pre[lane] = (uint32_t)incl;
         start[lane] = (uint32_t)(row - (incl - deg));  // flat entry f at start + f
         __syncthreads();
         for (int fb = 0; fb < tot; fb += kWave) {
             const int f = fb + lane;
             bool valid = f < tot;
-            int lo = 0;
-            if (valid) {
-#pragma unroll
-                for (int step = kWave / 2; step > 0; step >>= 1)
-                    lo += ((int)pre[lo + step - 1] <= f) ? step : 0;
-            }
+            const int lo = flat_source(pre, incl, deg, fb);
             // the child's code bits from its lane (every lane active here)
             const Code7 cw = ((Code7)(uint32_t)__builtin_amdgcn_ds_bpermute(
                                   lo << 2, (int)(uint32_t)(wcode >> 32)) << 32) |
