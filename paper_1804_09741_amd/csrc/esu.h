@@ -121,10 +121,10 @@ struct EnumState {
     SegT<V> *seg;               // vertex ids
     int seg_cap;
     int root;
-    const int32_t *urow;
-    const uint32_t *uadj;
-    const uint32_t *bits_out;   // row w bit u: arc w -> u
-    const uint32_t *bits_in;    // row w bit u: arc u -> w
+    GPtr<const int32_t> urow;
+    GPtr<const uint32_t> uadj;
+    GPtr<const uint32_t> bits_out;  // row w bit u: arc w -> u
+    GPtr<const uint32_t> bits_in;   // row w bit u: arc u -> w
     int words;
     uint32_t *scratch;          // 3 x 64 words of LDS per wave
     uint32_t *hkey;             // per-wave LDS hash: code (kEmpty = free)
@@ -497,10 +497,10 @@ __device__ __forceinline__ void unit_loop(EnumState<K, V> &s, const DevGraph *gr
                 const int gi = uniform(u.x);
                 if (gi != cur) {
                     on_switch(gi);
-                    s.urow = graphs[gi].urow;
-                    s.uadj = graphs[gi].uadj;
-                    s.bits_out = graphs[gi].bits_out;
-                    s.bits_in = graphs[gi].bits_in;
+                    s.urow = (GPtr<const int32_t>)graphs[gi].urow;
+                    s.uadj = (GPtr<const uint32_t>)graphs[gi].uadj;
+                    s.bits_out = (GPtr<const uint32_t>)graphs[gi].bits_out;
+                    s.bits_in = (GPtr<const uint32_t>)graphs[gi].bits_in;
                     s.words = graphs[gi].words;
                     cur = gi;
                 }

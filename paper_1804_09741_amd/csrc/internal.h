@@ -55,6 +55,15 @@ struct Graph {
     int32_t *d_col = nullptr; // m
 };
 
+// A pointer into device memory in the global address space.  Kernels read
+// the graph arrays' addresses from the descriptors below, and the compiler
+// cannot tell that such a pointer is global: loads through it would be flat
+// loads, which also count against the LDS wait counter, so that every wait
+// for an LDS result would wait for them too.  Kernels cast the descriptors'
+// pointers to this type once.
+template <class T>
+using GPtr = __attribute__((address_space(1))) T *;
+
 // Descriptor of one graph inside a batch, read by every kernel of the path.
 struct DevGraph {
     int32_t n;
@@ -74,8 +83,8 @@ struct DevGraph {
 // Two-bit relation of w to u read from the sorted typed lists (bit0: arc
 // w -> u, bit1: arc u -> w; 0 when not adjacent): a binary search for u in
 // w's list or for w in u's, whichever list is shorter.
-__device__ __forceinline__ uint32_t list_relation(const int32_t *urow, const uint32_t *uadj,
-                                                  uint32_t w, uint32_t u)
+template <class RowPtr, class AdjPtr>
+__device__ __forceinline__ uint32_t list_relation(RowPtr urow, AdjPtr uadj, uint32_t w, uint32_t u)
 {
     const int a0 = urow[w], a1 = urow[w + 1], b0 = urow[u], b1 = urow[u + 1];
     const bool sw = b1 - b0 < a1 - a0;

@@ -38,8 +38,35 @@ __device__ __forceinline__ uint64_t choose_small(int64_t n, int r)
     }
 }
 
+// A graph's descriptor as the planner reads it, with its arrays in the
+// global address space.
+struct PlanGraph {
+    int32_t n;
+    int32_t words;
+    GPtr<const uint32_t> bits_out;
+    GPtr<const uint32_t> bits_in;
+    GPtr<const int32_t> urow;
+    GPtr<const uint32_t> uadj;
+    uint32_t slot_base;
+    uint32_t nnz_cap;
+};
+
+__device__ __forceinline__ PlanGraph plan_graph(const DevGraph &d)
+{
+    PlanGraph g;
+    g.n = d.n;
+    g.words = d.words;
+    g.bits_out = (GPtr<const uint32_t>)d.bits_out;
+    g.bits_in = (GPtr<const uint32_t>)d.bits_in;
+    g.urow = (GPtr<const int32_t>)d.urow;
+    g.uadj = (GPtr<const uint32_t>)d.uadj;
+    g.slot_base = d.slot_base;
+    g.nnz_cap = d.nnz_cap;
+    return g;
+}
+
 // vertex v with urow[v] <= e < urow[v+1]
-__device__ __forceinline__ int owner_of(const int32_t *urow, int n, int e)
+__device__ __forceinline__ int owner_of(GPtr<const int32_t> urow, int n, int e)
 {
     int lo = 0, hi = n;  // answer in [lo, hi)
     while (hi - lo > 1) {
@@ -51,7 +78,7 @@ __device__ __forceinline__ int owner_of(const int32_t *urow, int n, int e)
 }
 
 // first position in [r0, r1) whose vertex exceeds v (lists are sorted)
-__device__ __forceinline__ int first_above(const uint32_t *uadj, int r0, int r1, int v)
+__device__ __forceinline__ int first_above(GPtr<const uint32_t> uadj, int r0, int r1, int v)
 {
     int lo = r0, hi = r1;
     while (lo < hi) {
@@ -62,12 +89,15 @@ __device__ __forceinline__ int first_above(const uint32_t *uadj, int r0, int r1,
     return lo;
 }
 
-// bit matrices when the batch has them, else a search of the sorted lists
-__device__ __forceinline__ bool adjacent(const DevGraph &g, int v, int x)
+// x above v and not adjacent to v (so that it enters a node's extension
+// list through another vertex): bit matrices when the batch has them, read
+// without a branch so that unrolled iterations have their loads in flight
+// together, else a search of the sorted lists (only for x above v)
+__device__ __forceinline__ bool exclusive_above(const PlanGraph &g, int v, int x)
 {
-    if (!g.bits_out) return list_relation(g.urow, g.uadj, (uint32_t)v, (uint32_t)x) != 0u;
+    if (!g.bits_out) return x > v && list_relation(g.urow, g.uadj, (uint32_t)v, (uint32_t)x) == 0u;
     const size_t w = (size_t)v * g.words + (x >> 5);
-    return ((g.bits_out[w] | g.bits_in[w]) >> (x & 31)) & 1u;
+    return (x > v) & !(((g.bits_out[w] | g.bits_in[w]) >> (x & 31)) & 1u);
 }
 
 // Pass kinds of the planner kernel.
@@ -87,13 +117,13 @@ enum PlanPass : int { kEstimate = 0, kCount = 1, kEmit = 2 };
 // memory (64 cost 4% there).  A caller can set it per batch
 // (mk_batch_opts.units_per_wave).
 template <int K>
-__device__ __forceinline__ uint64_t units_per_wave(const DevGraph &g)
+__device__ __forceinline__ uint64_t units_per_wave(const PlanGraph &g)
 {
     return K >= 7 ? 16u : (!g.bits_out ? 128u : 32u);
 }
 
 template <int K>
-__device__ __forceinline__ uint64_t effective_threshold(const DevGraph &g,
+__device__ __forceinline__ uint64_t effective_threshold(const PlanGraph &g,
                                                         const uint32_t *counters, uint64_t floor_t,
                                                         uint32_t waves, uint32_t upw)
 {
@@ -114,15 +144,14 @@ constexpr uint32_t kNoNode = 0xFFFFFFFFu;
 // greedy ranges over the children of (v, w_i): calls put(r, j0 | j1 << 16)
 // for every range when EMIT, returns the number of ranges
 template <int K, bool EMIT, typename Put>
-__device__ __forceinline__ uint32_t split_children(const DevGraph &g, int v, int first, int r1,
+__device__ __forceinline__ uint32_t split_children(const PlanGraph &g, int v, int first, int r1,
                                                    int i, int y, int L2, uint64_t threshold,
                                                    uint64_t *est, Put put)
 {
     uint32_t cnt = 0;
     int j = 0, j0 = 0;
     uint64_t acc = 0;
-    auto child = [&](int x) {
-        const int dx = g.urow[x + 1] - g.urow[x];
+    auto child = [&](int dx) {
         const uint64_t cj = choose_small(L2 - j - 1 + dx - 1, K - 3) + 1;
         *est += cj;
         if (j > j0 && acc + cj > threshold) {
@@ -134,10 +163,18 @@ __device__ __forceinline__ uint32_t split_children(const DevGraph &g, int v, int
         acc += cj;
         ++j;
     };
-    for (int t = first + i + 1; t < r1; ++t) child((int)(g.uadj[t] >> 2));
-    for (int t = g.urow[y]; t < g.urow[y + 1]; ++t) {
+    // unrolled: the iterations' loads do not depend on one another
+#pragma unroll 4
+    for (int t = first + i + 1; t < r1; ++t) {
         const int x = (int)(g.uadj[t] >> 2);
-        if (x > v && !adjacent(g, v, x)) child(x);
+        child(g.urow[x + 1] - g.urow[x]);
+    }
+    const int y0 = g.urow[y], y1 = g.urow[y + 1];
+#pragma unroll 4
+    for (int t = y0; t < y1; ++t) {
+        const int x = (int)(g.uadj[t] >> 2);
+        const int dx = g.urow[x + 1] - g.urow[x];
+        if (exclusive_above(g, v, x)) child(dx);
     }
     if (L2 > j0) {
         if (EMIT) put(cnt, (uint32_t)j0 | ((uint32_t)L2 << 16));
@@ -147,12 +184,14 @@ __device__ __forceinline__ uint32_t split_children(const DevGraph &g, int v, int
 }
 
 // extension length L2 of the node (v, w_i = y)
-__device__ __forceinline__ int ext_len(const DevGraph &g, int v, int ext_v, int i, int y)
+__device__ __forceinline__ int ext_len(const PlanGraph &g, int v, int ext_v, int i, int y)
 {
     int fresh = 0;
-    for (int t = g.urow[y]; t < g.urow[y + 1]; ++t) {
+    const int y0 = g.urow[y], y1 = g.urow[y + 1];
+#pragma unroll 8
+    for (int t = y0; t < y1; ++t) {
         const int x = (int)(g.uadj[t] >> 2);
-        if (x > v && !adjacent(g, v, x)) ++fresh;
+        fresh += (int)exclusive_above(g, v, x);
     }
     return ext_v - i - 1 + fresh;
 }
@@ -169,7 +208,7 @@ __global__ __launch_bounds__(kPlanThreads) void plan_kernel(const DevGraph *grap
                                                             uint32_t upw, uint32_t *counters)
 {
     const int gi = blockIdx.y;
-    const DevGraph &g = graphs[gi];
+    const PlanGraph g = plan_graph(graphs[gi]);
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
     uint64_t est = 0;  // kEstimate: this slot's estimated cost
     const bool live = g.n > 0 && e < min(g.urow[g.n], (int)g.nnz_cap);
