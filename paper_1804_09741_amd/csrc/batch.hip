@@ -655,7 +655,8 @@ int batch_prepare(mk_batch *b, hipStream_t stream)
 int batch_enum_slice(mk_batch *b, uint32_t begin, uint32_t end, hipStream_t stream)
 {
     if (b->ng == 0 || end <= begin) return MK_OK;
-    int rc = fill_u32(b->d_counters + kQueueHeads, 0, kQueues * kHeadStride, stream);
+    // both sweeps' heads
+    int rc = fill_u32(b->d_counters + kQueueHeads, 0, 2 * kQueues * kHeadStride, stream);
     if (rc) return rc;
     rc = fill_u32(b->d_counters + kSliceBegin, begin, 1, stream);
     if (rc) return rc;

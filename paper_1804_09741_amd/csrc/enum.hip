@@ -648,7 +648,7 @@ __device__ __forceinline__ void enum_body(const DevGraph *graphs, const int4 *un
     EnumState<K, V> s;
     const LdsLayout lay = lds_layout(K, cfg.max_n, cfg.seg_cap, cfg.hash_bits, (V & kVarGlobal) != 0);
     init_state(s, reinterpret_cast<char *>(lds), lay, cfg, counters, table, num_classes);
-    for_each_unit<K>(s, graphs, units, unit_cap, unit_end, counters, hist_base, cfg,
+    for_each_unit<false, K>(s, graphs, units, unit_cap, unit_end, counters, hist_base, cfg,
                      [&](int v, int i, uint32_t range) { run_unit<K>(s, v, i, range); });
 }
 

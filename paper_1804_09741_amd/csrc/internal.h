@@ -106,7 +106,11 @@ __device__ __forceinline__ uint32_t list_relation(RowPtr urow, AdjPtr uadj, uint
 //   z: index i of the first extension vertex in v's extension list,
 //   w: kFullChild -> the whole subtree below (v, w_i);
 //      else j0 | j1 << 16 -> children j0..j1-1 of the node (v, w_i).
+// kHeavyBit in x marks a unit whose estimated cost is high (the core
+// kernel takes such units in a first sweep of each range; every kernel
+// masks the bit off the graph index).
 constexpr uint32_t kFullChild = 0xFFFFFFFFu;
+constexpr uint32_t kHeavyBit = 1u << 31;
 
 // counters[] slots shared by planner and enumeration kernels
 enum Counter : int {
@@ -117,7 +121,8 @@ enum Counter : int {
     kAdjOverflow = 4, // typed adjacency larger than reserved (must stay 0)
     kEstTotal = 6,    // words 6-7: u64 estimated total cost (planner)
     kQueueHeads = 16, // kQueues heads, one per XCD, kHeadStride words apart
-    kNumCounters = 16 + 8 * 16,
+    kHeavyHeads = 16 + 8 * 16,  // the first sweep's kQueues heads, likewise
+    kNumCounters = 16 + 2 * 8 * 16,
 };
 constexpr int kQueues = 8;       // one queue per XCD of the MI355X
 constexpr int kHeadStride = 16;  // 64 bytes: one cache line per head

@@ -773,7 +773,7 @@ __global__ __launch_bounds__(kWave) void k7_kernel(const DevGraph *graphs, const
     }
     __syncthreads();
 
-    unit_loop(
+    unit_loop<false>(
         s, graphs, units, unit_cap, unit_end, counters, cfg,
         [&](int v, int i, uint32_t range) { run_unit7(s, w7, t, v, i, range); },
         [&](int gi) {

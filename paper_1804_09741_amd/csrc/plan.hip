@@ -141,8 +141,8 @@ constexpr int kViShift = 20;
 constexpr uint32_t kViMask = (1u << kViShift) - 1u;
 constexpr uint32_t kNoNode = 0xFFFFFFFFu;
 
-// greedy ranges over the children of (v, w_i): calls put(r, j0 | j1 << 16)
-// for every range when EMIT, returns the number of ranges
+// greedy ranges over the children of (v, w_i): calls put(r, j0 | j1 << 16,
+// estimated cost) for every range when EMIT, returns the number of ranges
 template <int K, bool EMIT, typename Put>
 __device__ __forceinline__ uint32_t split_children(const PlanGraph &g, int v, int first, int r1,
                                                    int i, int y, int L2, uint64_t threshold,
@@ -155,7 +155,7 @@ __device__ __forceinline__ uint32_t split_children(const PlanGraph &g, int v, in
         const uint64_t cj = choose_small(L2 - j - 1 + dx - 1, K - 3) + 1;
         *est += cj;
         if (j > j0 && acc + cj > threshold) {
-            if (EMIT) put(cnt, (uint32_t)j0 | ((uint32_t)j << 16));
+            if (EMIT) put(cnt, (uint32_t)j0 | ((uint32_t)j << 16), acc);
             ++cnt;
             j0 = j;
             acc = 0;
@@ -177,7 +177,7 @@ __device__ __forceinline__ uint32_t split_children(const PlanGraph &g, int v, in
         if (exclusive_above(g, v, x)) child(dx);
     }
     if (L2 > j0) {
-        if (EMIT) put(cnt, (uint32_t)j0 | ((uint32_t)L2 << 16));
+        if (EMIT) put(cnt, (uint32_t)j0 | ((uint32_t)L2 << 16), acc);
         ++cnt;
     }
     return cnt;
@@ -194,6 +194,17 @@ __device__ __forceinline__ int ext_len(const PlanGraph &g, int v, int ext_v, int
         fresh += (int)exclusive_above(g, v, x);
     }
     return ext_v - i - 1 + fresh;
+}
+
+#ifndef MK_HEAVY_SHIFT
+#define MK_HEAVY_SHIFT 1  // k = 5 core kernel 17.5 ms with 1, 17.8 with 2, 18.8 with 0
+#endif
+
+// x of a unit of graph gi with estimated cost est: kHeavyBit when est
+// exceeds the split threshold >> MK_HEAVY_SHIFT (half of it)
+__device__ __forceinline__ int unit_x(int gi, uint64_t est, uint64_t threshold)
+{
+    return (int)((uint32_t)gi | (est > (threshold >> MK_HEAVY_SHIFT) ? kHeavyBit : 0u));
 }
 
 // One workgroup per (graph, 256 slots): blockIdx.y is the graph.
@@ -234,7 +245,7 @@ __global__ __launch_bounds__(kPlanThreads) void plan_kernel(const DevGraph *grap
                 slot_l2[slot] = (uint32_t)L2;
                 if constexpr (K == 3) est = (uint64_t)L2 + 1;
                 else split_children<K, false>(g, v, first, r1, i, y, L2, ~0ull, &est,
-                                              [](uint32_t, uint32_t) {});
+                                              [](uint32_t, uint32_t, uint64_t) {});
                 vi = (uint32_t)v | ((uint32_t)i << kViShift);
             }
             slot_vi[slot] = vi;
@@ -260,9 +271,9 @@ __global__ __launch_bounds__(kPlanThreads) void plan_kernel(const DevGraph *grap
                     const int L2 = (int)slot_l2[slot];  // from the estimate pass
                     uint32_t base = 0;
                     if (PASS == kEmit) base = slot_off[slot];
-                    auto put = [&](uint32_t r, uint32_t w) {
+                    auto put = [&](uint32_t r, uint32_t w, uint64_t c) {
                         const uint32_t idx = base + r;
-                        if (idx < unit_cap) units[idx] = make_int4(gi, v, i, (int)w);
+                        if (idx < unit_cap) units[idx] = make_int4(unit_x(gi, c, threshold), v, i, (int)w);
                         else atomicOr(&counters[kErrors], 1u);
                     };
                     uint64_t dummy = 0;
@@ -273,7 +284,8 @@ __global__ __launch_bounds__(kPlanThreads) void plan_kernel(const DevGraph *grap
                 }
                 if (PASS == kEmit && cnt == 1 && !(K > 3 && split)) {
                     const uint32_t idx = slot_off[slot];
-                    if (idx < unit_cap) units[idx] = make_int4(gi, v, i, (int)kFullChild);
+                    if (idx < unit_cap)
+                        units[idx] = make_int4(unit_x(gi, sest, threshold), v, i, (int)kFullChild);
                     else atomicOr(&counters[kErrors], 1u);
                 }
             }
