@@ -119,6 +119,7 @@ enum Counter : int {
     kErrors = 2,      // device-side consistency failures (must stay 0)
     kSplitPairs = 3,  // (root, first neighbour) pairs split at the second level
     kAdjOverflow = 4, // typed adjacency larger than reserved (must stay 0)
+    kSpecSplitPairs = 5,  // kSplitPairs at the floor threshold (estimate pass)
     kEstTotal = 6,    // words 6-7: u64 estimated total cost (planner)
     kQueueHeads = 16, // kQueues heads, one per XCD, kHeadStride words apart
     kHeavyHeads = 16 + 8 * 16,  // the first sweep's kQueues heads, likewise

@@ -207,7 +207,18 @@ __device__ __forceinline__ int unit_x(int gi, uint64_t est, uint64_t threshold)
     return (int)((uint32_t)gi | (est > (threshold >> MK_HEAVY_SHIFT) ? kHeavyBit : 0u));
 }
 
-// One workgroup per (graph, 256 slots): blockIdx.y is the graph.
+// whether a first-level node of saturated estimate sest is cut into ranges
+template <int K>
+__device__ __forceinline__ bool node_split(uint32_t sest, uint64_t threshold)
+{
+    return K > 3 && (sest == 0xFFFFFFFFu || sest > threshold);
+}
+
+// One workgroup per (graph, 256 slots): blockIdx.y is the graph.  The
+// estimate pass also counts each slot's units at the floor threshold (its
+// walk over the children is the one the count pass would repeat); when the
+// estimated total leaves the threshold at the floor, as it does for the
+// benchmark batches, the count pass keeps those counts and returns at once.
 template <int K, int PASS>
 __global__ __launch_bounds__(kPlanThreads) void plan_kernel(const DevGraph *graphs,
                                                             uint32_t *slot_cnt,
@@ -224,13 +235,17 @@ __global__ __launch_bounds__(kPlanThreads) void plan_kernel(const DevGraph *grap
     uint64_t est = 0;  // kEstimate: this slot's estimated cost
     const bool live = g.n > 0 && e < min(g.urow[g.n], (int)g.nnz_cap);
     const uint64_t threshold = PASS == kEstimate ? ~0ull : effective_threshold<K>(g, counters, floor_t, waves, upw);
+    if (PASS == kCount && threshold == floor_t) {
+        if (gi == 0 && e == 0) counters[kSplitPairs] = counters[kSpecSplitPairs];
+        return;
+    }
     if (live) {
         const uint32_t slot = g.slot_base + (uint32_t)e;
         const int y = (int)(g.uadj[e] >> 2);
         if (PASS == kEstimate) {
             // the full walk: owner, position, extension length, child costs
             const int v = owner_of(g.urow, g.n, e);
-            uint32_t vi = kNoNode;
+            uint32_t vi = kNoNode, ranges = 0;
             if constexpr (K == 2) {
                 // one unit per vertex, on its first list entry
                 if (e == g.urow[v]) {
@@ -244,20 +259,26 @@ __global__ __launch_bounds__(kPlanThreads) void plan_kernel(const DevGraph *grap
                 const int L2 = ext_len(g, v, r1 - first, i, y);
                 slot_l2[slot] = (uint32_t)L2;
                 if constexpr (K == 3) est = (uint64_t)L2 + 1;
-                else split_children<K, false>(g, v, first, r1, i, y, L2, ~0ull, &est,
-                                              [](uint32_t, uint32_t, uint64_t) {});
+                else ranges = split_children<K, false>(g, v, first, r1, i, y, L2, floor_t, &est,
+                                                       [](uint32_t, uint32_t, uint64_t) {});
                 vi = (uint32_t)v | ((uint32_t)i << kViShift);
             }
             slot_vi[slot] = vi;
-            slot_est[slot] = est > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)est;
+            const uint32_t sest = est > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)est;
+            slot_est[slot] = sest;
+            uint32_t cnt = 0;  // units at the floor threshold
+            if (vi != kNoNode) {
+                cnt = node_split<K>(sest, floor_t) ? ranges : ((K > 3 && sest == 0u) ? 0u : 1u);
+                if (cnt > 1) atomicAdd(&counters[kSpecSplitPairs], 1u);
+            }
+            slot_cnt[slot] = cnt;
         } else {
             const uint32_t vi = slot_vi[slot];
             const uint32_t sest = slot_est[slot];
             uint32_t cnt = 0;
             if (vi != kNoNode) {
                 const int v = (int)(vi & kViMask), i = (int)(vi >> kViShift);
-                const bool split = K > 3 && sest != 0xFFFFFFFFu && sest > threshold
-                                       ? true : (K > 3 && sest == 0xFFFFFFFFu);
+                const bool split = node_split<K>(sest, threshold);
                 if (K <= 3) {
                     cnt = 1;
                 } else if (sest <= 1 && !split) {
