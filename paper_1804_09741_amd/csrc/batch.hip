@@ -39,6 +39,7 @@ struct mk_batch {
     uint32_t total_slots = 0;
     int4 *d_units = nullptr;
     uint32_t unit_cap = 0;
+    uint64_t spec_threshold = 0;  // split threshold of the sizing plan (0: the floor)
     uint32_t *d_counters = nullptr;
     uint32_t *d_unit_begin = nullptr;    // first unit of every graph, plus the total
     unsigned long long *d_hist_own = nullptr;
@@ -225,8 +226,9 @@ static int batch_enqueue_prep(mk_batch *b, unsigned long long *hist, hipStream_t
     if (rc) return rc;
     return launch_plan(b->plan_k, b->d_graphs, b->ng, b->max_nnz, b->total_slots, b->d_slot_cnt,
                        b->d_slot_off, b->d_slot_est, b->d_slot_vi, b->d_slot_l2, b->d_scan_tmp,
-                       b->d_units, b->unit_cap, b->opts.split_threshold, (uint32_t)b->max_grid,
-                       (uint32_t)std::max(b->opts.units_per_wave, 0), b->d_counters, stream);
+                       b->d_units, b->unit_cap, b->opts.split_threshold, b->spec_threshold,
+                       (uint32_t)b->max_grid, (uint32_t)std::max(b->opts.units_per_wave, 0),
+                       b->d_counters, stream);
 }
 
 // the counting kernel over units [counters[kSliceBegin], unit_end)
@@ -458,7 +460,7 @@ static int batch_create(mk_ctx *ctx, const mk_graph *const *gs, int32_t ng, int 
     if (!rc)
         rc = launch_plan(b->plan_k, b->d_graphs, ng, b->max_nnz, b->total_slots, b->d_slot_cnt,
                          b->d_slot_off, b->d_slot_est, b->d_slot_vi, b->d_slot_l2, b->d_scan_tmp,
-                         nullptr, 0, b->opts.split_threshold, (uint32_t)b->max_grid,
+                         nullptr, 0, b->opts.split_threshold, 0, (uint32_t)b->max_grid,
                          (uint32_t)std::max(b->opts.units_per_wave, 0), b->d_counters,
                          ctx->stream);
     if (rc) return bail(rc);
@@ -469,6 +471,8 @@ static int batch_create(mk_ctx *ctx, const mk_graph *const *gs, int32_t ng, int 
         return bail(fail(MK_EDEVICE, "typed adjacency exceeds its reserved size"));
     b->units = cnt[kNumUnits];
     b->split_pairs = cnt[kSplitPairs];
+    // the same graphs plan to the same threshold at every pass
+    std::memcpy(&b->spec_threshold, &cnt[kPlanThreshold], sizeof(b->spec_threshold));
     b->unit_cap = std::max<uint32_t>(cnt[kNumUnits], 1);
     BAIL_HIP(hipMalloc(&b->d_units, sizeof(int4) * b->unit_cap));
 

@@ -121,6 +121,7 @@ enum Counter : int {
     kAdjOverflow = 4, // typed adjacency larger than reserved (must stay 0)
     kSpecSplitPairs = 5,  // kSplitPairs at the floor threshold (estimate pass)
     kEstTotal = 6,    // words 6-7: u64 estimated total cost (planner)
+    kPlanThreshold = 8,  // words 8-9: u64 split threshold of the last count pass
     kQueueHeads = 16, // kQueues heads, one per XCD, kHeadStride words apart
     kHeavyHeads = 16 + 8 * 16,  // the first sweep's kQueues heads, likewise
     kNumCounters = 16 + 2 * 8 * 16,
@@ -182,11 +183,15 @@ int launch_typed_csr(const DevGraph *d_graphs, int ng, int max_n, int64_t max_m,
 // planner's rule (16, or 64 on sorted-list adjacency below k = 7).
 // slot_l2: per slot, the extension length of its first-level node (written
 // by the estimate pass, read by the count and emit passes).
+// spec_threshold (0: the floor): the threshold at which the estimate pass
+// also counts each slot's units; the count pass keeps those counts when the
+// threshold comes out equal to it (a batch passes the one its sizing plan
+// found, read from counters[kPlanThreshold]).
 int launch_plan(int k, const DevGraph *d_graphs, int ng, int64_t max_nnz, uint32_t total_slots,
                 uint32_t *slot_cnt, uint32_t *slot_off, uint32_t *slot_est, uint32_t *slot_vi,
                 uint32_t *slot_l2, uint32_t *scan_tmp, int4 *units, uint32_t unit_cap,
-                uint64_t split_threshold, uint32_t waves, uint32_t units_per_wave,
-                uint32_t *counters, hipStream_t stream);
+                uint64_t split_threshold, uint64_t spec_threshold, uint32_t waves,
+                uint32_t units_per_wave, uint32_t *counters, hipStream_t stream);
 
 // Enumeration + code + lookup + histogram over the queued units.
 // k = 7 (k7.hip): device tables of one count

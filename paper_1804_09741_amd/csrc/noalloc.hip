@@ -158,7 +158,7 @@ extern "C" int mk_count_static(mk_ctx *ctx, const mk_graph *g, const mk_table *t
         rc = launch_plan(k, dg, 1, (int64_t)nnz, (uint32_t)nnz, slots, slots + nnz, slots + 2 * nnz,
                          slots + 3 * nnz, slots + 4 * nnz, reinterpret_cast<uint32_t *>(base + o_scan),
                          units, (uint32_t)std::min<uint64_t>(unit_cap, 0xFFFFFFFFull),
-                         default_split_floor(k), (uint32_t)grid, 0u, counters, s);
+                         default_split_floor(k), 0, (uint32_t)grid, 0u, counters, s);
     EnumConfig cfg{};
     cfg.max_n = g->n;
     cfg.seg_cap = seg_cap;

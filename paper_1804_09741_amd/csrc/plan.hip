@@ -215,10 +215,11 @@ __device__ __forceinline__ bool node_split(uint32_t sest, uint64_t threshold)
 }
 
 // One workgroup per (graph, 256 slots): blockIdx.y is the graph.  The
-// estimate pass also counts each slot's units at the floor threshold (its
+// estimate pass also counts each slot's units at the threshold spec_t (its
 // walk over the children is the one the count pass would repeat); when the
-// estimated total leaves the threshold at the floor, as it does for the
-// benchmark batches, the count pass keeps those counts and returns at once.
+// threshold comes out equal to spec_t -- the floor, or for a batch the
+// threshold its sizing plan found, since a batch plans the same graphs
+// every pass -- the count pass keeps those counts and returns at once.
 template <int K, int PASS>
 __global__ __launch_bounds__(kPlanThreads) void plan_kernel(const DevGraph *graphs,
                                                             uint32_t *slot_cnt,
@@ -226,7 +227,8 @@ __global__ __launch_bounds__(kPlanThreads) void plan_kernel(const DevGraph *grap
                                                             uint32_t *slot_est, uint32_t *slot_vi,
                                                             uint32_t *slot_l2,
                                                             int4 *units, uint32_t unit_cap,
-                                                            uint64_t floor_t, uint32_t waves,
+                                                            uint64_t floor_t, uint64_t spec_t,
+                                                            uint32_t waves,
                                                             uint32_t upw, uint32_t *counters)
 {
     const int gi = blockIdx.y;
@@ -235,9 +237,13 @@ __global__ __launch_bounds__(kPlanThreads) void plan_kernel(const DevGraph *grap
     uint64_t est = 0;  // kEstimate: this slot's estimated cost
     const bool live = g.n > 0 && e < min(g.urow[g.n], (int)g.nnz_cap);
     const uint64_t threshold = PASS == kEstimate ? ~0ull : effective_threshold<K>(g, counters, floor_t, waves, upw);
-    if (PASS == kCount && threshold == floor_t) {
-        if (gi == 0 && e == 0) counters[kSplitPairs] = counters[kSpecSplitPairs];
-        return;
+    if (PASS == kCount) {
+        if (gi == 0 && e == 0)
+            *reinterpret_cast<unsigned long long *>(counters + kPlanThreshold) = threshold;
+        if (threshold == spec_t) {
+            if (gi == 0 && e == 0) counters[kSplitPairs] = counters[kSpecSplitPairs];
+            return;
+        }
     }
     if (live) {
         const uint32_t slot = g.slot_base + (uint32_t)e;
@@ -259,16 +265,16 @@ __global__ __launch_bounds__(kPlanThreads) void plan_kernel(const DevGraph *grap
                 const int L2 = ext_len(g, v, r1 - first, i, y);
                 slot_l2[slot] = (uint32_t)L2;
                 if constexpr (K == 3) est = (uint64_t)L2 + 1;
-                else ranges = split_children<K, false>(g, v, first, r1, i, y, L2, floor_t, &est,
+                else ranges = split_children<K, false>(g, v, first, r1, i, y, L2, spec_t, &est,
                                                        [](uint32_t, uint32_t, uint64_t) {});
                 vi = (uint32_t)v | ((uint32_t)i << kViShift);
             }
             slot_vi[slot] = vi;
             const uint32_t sest = est > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)est;
             slot_est[slot] = sest;
-            uint32_t cnt = 0;  // units at the floor threshold
+            uint32_t cnt = 0;  // units at the threshold spec_t
             if (vi != kNoNode) {
-                cnt = node_split<K>(sest, floor_t) ? ranges : ((K > 3 && sest == 0u) ? 0u : 1u);
+                cnt = node_split<K>(sest, spec_t) ? ranges : ((K > 3 && sest == 0u) ? 0u : 1u);
                 if (cnt > 1) atomicAdd(&counters[kSpecSplitPairs], 1u);
             }
             slot_cnt[slot] = cnt;
@@ -333,8 +339,8 @@ template <int K>
 static int plan_k(const DevGraph *d_graphs, int ng, int64_t max_nnz, uint32_t total_slots,
                   uint32_t *slot_cnt, uint32_t *slot_off, uint32_t *slot_est, uint32_t *slot_vi,
                   uint32_t *slot_l2, uint32_t *scan_tmp, int4 *units, uint32_t unit_cap,
-                  uint64_t threshold, uint32_t waves, uint32_t upw, uint32_t *counters,
-                  hipStream_t stream)
+                  uint64_t threshold, uint64_t spec, uint32_t waves, uint32_t upw,
+                  uint32_t *counters, hipStream_t stream)
 {
     const dim3 grid((unsigned)std::max<int64_t>((max_nnz + kPlanThreads - 1) / kPlanThreads, 1),
                     (unsigned)ng);
@@ -342,18 +348,18 @@ static int plan_k(const DevGraph *d_graphs, int ng, int64_t max_nnz, uint32_t to
     // clear all counters before every plan
     hipLaunchKernelGGL((plan_kernel<K, kEstimate>), grid, dim3(kPlanThreads), 0, stream, d_graphs,
                        slot_cnt, slot_off, slot_est, slot_vi, slot_l2, units, unit_cap, threshold,
-                       waves, upw, counters);
+                       spec ? spec : threshold, waves, upw, counters);
     MK_HIP(hipGetLastError());
     hipLaunchKernelGGL((plan_kernel<K, kCount>), grid, dim3(kPlanThreads), 0, stream, d_graphs,
                        slot_cnt, slot_off, slot_est, slot_vi, slot_l2, units, unit_cap, threshold,
-                       waves, upw, counters);
+                       spec ? spec : threshold, waves, upw, counters);
     MK_HIP(hipGetLastError());
     int rc = scan_u32(slot_cnt, slot_off, total_slots, 0, &counters[kNumUnits], scan_tmp, stream);
     if (rc != MK_OK) return rc;
     if (!units) return MK_OK;  // sizing pass
     hipLaunchKernelGGL((plan_kernel<K, kEmit>), grid, dim3(kPlanThreads), 0, stream, d_graphs,
                        slot_cnt, slot_off, slot_est, slot_vi, slot_l2, units, unit_cap, threshold,
-                       waves, upw, counters);
+                       spec ? spec : threshold, waves, upw, counters);
     MK_HIP(hipGetLastError());
     return MK_OK;
 }
@@ -389,14 +395,14 @@ int launch_unit_begins(const DevGraph *d_graphs, int ng, const uint32_t *slot_of
 int launch_plan(int k, const DevGraph *d_graphs, int ng, int64_t max_nnz, uint32_t total_slots,
                 uint32_t *slot_cnt, uint32_t *slot_off, uint32_t *slot_est, uint32_t *slot_vi,
                 uint32_t *slot_l2, uint32_t *scan_tmp, int4 *units, uint32_t unit_cap,
-                uint64_t split_threshold, uint32_t waves, uint32_t units_per_wave,
-                uint32_t *counters, hipStream_t stream)
+                uint64_t split_threshold, uint64_t spec_threshold, uint32_t waves,
+                uint32_t units_per_wave, uint32_t *counters, hipStream_t stream)
 {
     if (ng <= 0) return MK_OK;
 #define MK_PLAN(KK)                                                                         \
     plan_k<KK>(d_graphs, ng, max_nnz, total_slots, slot_cnt, slot_off, slot_est, slot_vi,  \
-               slot_l2, scan_tmp, units, unit_cap, split_threshold, waves, units_per_wave, \
-               counters, stream)
+               slot_l2, scan_tmp, units, unit_cap, split_threshold, spec_threshold, waves, \
+               units_per_wave, counters, stream)
     switch (k) {
     case 2: return MK_PLAN(2);
     case 3: return MK_PLAN(3);
